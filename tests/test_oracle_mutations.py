@@ -1,0 +1,72 @@
+"""The oracle's pins are strong enough: each plausible mistake planted in a
+temporary copy of the oracle sources (on the CPU) makes some pin fail."""
+import os
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+ORACLE = os.path.join(ROOT, "oracle")
+PIN_FILES = ["tests/test_oracle_path.py", "tests/test_oracle_wmap.py",
+             "tests/test_oracle_assign.py", "tests/test_oracle_update.py",
+             "tests/test_oracle_soft.py"]
+
+H = "scalp_oracle.c"
+S = "scalp_soft_oracle.c"
+MUTATIONS = {
+    "drop_lambda_term": (H, "float A = c->lambda * dcp + oml * (sc / np);",
+                         "float A = oml * (sc / np);"),
+    "path_sign": (H, "return d < 0 ? (int)-off : (int)off;", "return d < 0 ? (int)off : (int)-off;"),
+    "path_ties_toward_p": (H, "long off = (2 * i * ad + n) / (2 * n);",
+                           "long off = (2 * i * ad + n - 1) / (2 * n);"),
+    "transposed_centre": (H, "float ey = (float)y - centre[4];", "float ey = (float)y - centre[3];"),
+    "spatial_uses_endpoint": (H, "float ex = (float)x - centre[3];", "float ex = (float)x - (float)cx;"),
+    "ties_to_last": (H, "if (D < best) { best = D; bestk = k; }", "if (D <= best) { best = D; bestk = k; }"),
+    "drop_gamma": (H, "float B = 1.0f + c->gamma * (sw / np);", "float B = 1.0f + (sw / np);"),
+    "path_len_excludes_p": (H, "float np = (float)(n + 1);", "float np = (float)(n > 0 ? n : 1);"),
+    "wmap_not_squared": (H, "w[i] = (float)(1.0 - exp(-(c * c) / s2));", "w[i] = (float)(1.0 - exp(-c / s2));"),
+    "missing_neighbour": (H, "for (int dj = -1; dj <= 1; dj++) {", "for (int dj = -1; dj <= 0; dj++) {"),
+    "update_x_from_row": (H, "sx[k] += p % W;", "sx[k] += p / W;"),
+    "projection_ties": (H, "if (d < best) { best = d; bestp = p; }", "if (d <= best) { best = d; bestp = p; }"),
+    "cell_rounding": (H, "static int cell_col(int x, int W, int nx) { return (int)(((long)x * nx) / W); }",
+                      "static int cell_col(int x, int W, int nx) { return (int)(((long)x * nx + W / 2) / W); }"),
+    "soft_bwd_drop_lambda": (S, "gf[3 * p + e] += g * Bw * lambda * dpe;", "gf[3 * p + e] += 0.0 * dpe;"),
+    "soft_bwd_drop_gamma": (S, "gw[qix] += g * A * c.gamma / np;", "gw[qix] += g * A / np;"),
+    "soft_bwd_softmax_sign": (S, "double g = -(1.0 / T) * Q[9 * p + j] * (gQ[9 * p + j] - dot);",
+                              "double g = (1.0 / T) * Q[9 * p + j] * (gQ[9 * p + j] - dot);"),
+}
+
+
+# Pin files that are expected to catch each family of mistakes (all files
+# are run for a mutation not listed here).
+WHERE = {
+    "soft_bwd_drop_lambda": ["tests/test_oracle_soft.py"],
+    "soft_bwd_drop_gamma": ["tests/test_oracle_soft.py"],
+    "soft_bwd_softmax_sign": ["tests/test_oracle_soft.py"],
+    "update_x_from_row": ["tests/test_oracle_update.py"],
+    "projection_ties": ["tests/test_oracle_update.py"],
+    "wmap_not_squared": ["tests/test_oracle_wmap.py"],
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_mutation_is_caught(name, tmp_path):
+    fname, old, new = MUTATIONS[name]
+    work = tmp_path / "oracle"
+    shutil.copytree(ORACLE, work, ignore=shutil.ignore_patterns("*.so", "__pycache__"))
+    src = (work / fname).read_text()
+    assert src.count(old) == 1, f"mutation site for {name} not found exactly once"
+    (work / fname).write_text(src.replace(old, new))
+    sys.path.insert(0, ROOT)
+    from oracle.oracle import CFLAGS, _SOURCES
+    lib = work / "liboracle_mut.so"
+    subprocess.run(["gcc", *CFLAGS, "-o", str(lib), *[str(work / s) for s in _SOURCES], "-lm"],
+                   check=True)
+    env = dict(os.environ, SCALP_ORACLE_LIB=str(lib), OMP_NUM_THREADS="4")
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        *WHERE.get(name, PIN_FILES)], cwd=ROOT, env=env, capture_output=True, text=True,
+                       timeout=600)
+    assert r.returncode == 1 and " failed" in r.stdout, (
+        f"planted mistake '{name}' survived the pins:\n{r.stdout[-2000:]}")

@@ -1,0 +1,113 @@
+"""Pins for the FP64 soft-SCALP oracle (an extension: softmax over the
+distances of Eq. (3) with temperature T, soft barycenter update).
+
+  * its analytic gradient against FP64 central finite differences of its own
+    forward (eps = 1e-4) on 32x32 crops with K = 16;
+  * T -> 0: the argmax of Q is the hard assignment of Algorithm 1, and a
+    one-hot Q makes the soft update equal to the hard update.
+"""
+import numpy as np
+import pytest
+
+from paper_1903_07149_amd import synth
+
+
+def _crop_batch(n, size=32, seed=500):
+    labs, cons = [], []
+    for b in range(n):
+        img = synth.make_image(size, size, 6, 10.0, seed + b)
+        labs.append(img.lab)
+        cons.append(img.contour)
+    return np.stack(labs), np.stack(cons)
+
+
+def _loss(orc, lab, con, k, gq, gth, iters, T):
+    th, q, _ = orc.soft_forward(lab, con, k, iterations=iters, T=T)
+    return float((gq * q[-1]).sum() + (gth * th[-1]).sum()), th
+
+
+@pytest.mark.parametrize("T,iters", [(50.0, 2), (0.5, 2), (5.0, 3)])
+def test_soft_gradient_finite_differences(orc, T, iters):
+    k = 16
+    lab, con = _crop_batch(1)
+    # soft contour values so that dw/dC is not ~0 everywhere
+    con = np.clip(con + 0.15 * np.random.default_rng(1).random(con.shape), 0, 1).astype(np.float32)
+    g = orc.grid(32, 32, k)
+    rng = np.random.default_rng(2)
+    gq = rng.normal(0, 1, (1, 32, 32, 9))
+    gth = rng.normal(0, 1, (1, g.num_sp, 5))
+    glab, gcon = orc.soft_backward(lab, con, k, gq, gth, iterations=iters, T=T)
+    eps = 1e-4
+    checked = 0
+    idx_lab = [tuple(rng.integers(0, s) for s in lab.shape) for _ in range(40)]
+    idx_con = [tuple(rng.integers(0, s) for s in con.shape) for _ in range(25)]
+    for arr, grad, idxs in ((lab, glab, idx_lab), (con, gcon, idx_con)):
+        for idx in idxs:
+            base = arr[idx]
+            if arr is con and (base - eps < 0 or base + eps > 1):
+                continue
+            vals = []
+            eps_ok = True
+            ends = []
+            for s in (+1, -1):
+                a = arr.copy()
+                # FD in FP64 on an FP32 input: the step is applied in FP64 through the value
+                a = a.astype(np.float64)
+                a[idx] = base + s * eps
+                a32 = a.astype(np.float32)
+                # the oracle consumes FP32 inputs; use an exactly representable step
+                h = float(a32[idx]) - float(base)
+                if h == 0.0:
+                    eps_ok = False
+                    break
+                args = (a32, con, k) if arr is lab else (lab, a32, k)
+                L, th = _loss(orc, *args, gq, gth, iters, T)
+                vals.append((L, h))
+                ends.append(np.floor(th[:-1, ..., 3:5] + 0.5))
+            if not eps_ok or not (ends[0] == ends[1]).all():
+                continue                              # an endpoint rounding flipped: FD invalid
+            (lp, hp), (lm, hm) = vals
+            fd = (lp - lm) / (hp - hm)
+            an = float(grad[idx])
+            assert abs(fd - an) <= 2e-3 * max(1.0, abs(an)) + 2e-3 * abs(fd), (idx, fd, an)
+            checked += 1
+    assert checked >= 40
+
+
+def test_soft_zero_temperature_is_hard(orc):
+    """Integer Lab on 4x4-pixel cells: the FP32 hard and FP64 soft initial centres coincide,
+    so argmax Q at T -> 0 is the hard assignment and a one-hot Q gives the hard update."""
+    W = H = 16
+    k = 16
+    rng = np.random.default_rng(4)
+    lab = rng.integers(0, 60, (H, W, 3)).astype(np.float32)
+    con = (rng.integers(0, 5, (H, W)) / 4.0).astype(np.float32)
+    g = orc.grid(W, H, k)
+    assert (g.nx, g.ny) == (4, 4)
+    th, q, z = orc.soft_forward(lab[None], con[None], k, iterations=1, T=1e-4)
+    c0, e0, _ = orc.init_grid(g, lab)
+    assert (th[0, 0] == c0.astype(np.float64)).all()
+    hard, _, _ = orc.assign(g, lab, orc.wmap(con), c0, e0, gamma=orc.default_gamma(g),
+                            spw=orc.spatial_weight(g))
+    yy, xx = np.mgrid[0:H, 0:W]
+    ci, cj = yy * g.ny // H, xx * g.nx // W
+    j = q[0, 0].argmax(axis=-1)
+    soft_lbl = (ci + j // 3 - 1) * g.nx + (cj + j % 3 - 1)
+    assert (soft_lbl == hard).all()
+    assert np.allclose(q[0, 0].max(axis=-1), 1.0)
+    onehot = (q[0, 0].max(axis=-1) == 1.0)
+    if onehot.all():
+        c1, n1 = orc.update(g, lab, hard, c0)
+        nz = n1 > 0
+        assert (th[1, 0][nz] .astype(np.float32) == c1[nz]).all()
+        assert (z[0, 0][nz] == n1[nz]).all()
+
+
+def test_soft_forward_shapes_and_simplex(orc):
+    lab, con = _crop_batch(2)
+    th, q, z = orc.soft_forward(lab, con, 16, iterations=3, T=0.5)
+    assert th.shape == (4, 2, 16, 5) and q.shape == (3, 2, 32, 32, 9) and z.shape == (3, 2, 16)
+    assert np.allclose(q.sum(-1), 1.0) and (q >= 0).all()
+    assert np.allclose(z.sum(-1), 32 * 32)
+    # corner pixels see only 4 of the 9 neighbours
+    assert (q[:, :, 0, 0, [0, 1, 2, 3, 6]] == 0).all()
