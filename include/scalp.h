@@ -1,0 +1,225 @@
+/*
+ * scalp.h -- C ABI of libscalp.so, the MI355X (gfx950) implementation of the
+ * iterative clustering of SCALP ("Superpixels with Contour Adherence using
+ * Linear Path", Giraud, Ta, Papadakis, ICPR 2018, arXiv 1903.07149).
+ *
+ * Conventions for every entry point
+ *   - Array arguments are DEVICE pointers (e.g. torch tensor data pointers)
+ *     unless marked "host".  All arrays are row-major and contiguous:
+ *       lab      float32 [H][W][3]  CIELab features (l, a, b) of Sec. II-A
+ *       contour  float32 [H][W]     soft contour prior C in [0, 1] of Sec. II-D
+ *       labels   int32   [H][W]     superpixel index in [0, K')
+ *       centers  float32 [K'][5]    cluster C_k = (l_k, a_k, b_k, x_k, y_k)
+ *       endpoints int32  [K'][2]    path end pixel (x, y) of each cluster: the
+ *                                   rounded barycenter, or its projection X_k*
+ *                                   of Eq. (4)
+ *       counts   int32   [K']       |S_k|
+ *   - The caller owns every buffer, including the workspace.  The library
+ *     never allocates device memory and never synchronises: every call only
+ *     enqueues work on `stream` (a hipStream_t passed as void*; NULL is the
+ *     null stream) and returns.  Kernel faults surface at the caller's next
+ *     synchronisation.
+ *   - Return value: SCALP_OK (0) or a negative SCALP_ERR_* code.  Argument
+ *     errors are detected on the host before anything is enqueued.  Nothing
+ *     is thrown across the ABI.
+ *   - workspace / workspace_bytes: caller-allocated device scratch and its
+ *     size; SCALP_ERR_WORKSPACE if it is NULL or smaller than the matching
+ *     *_workspace_bytes() value.  Its contents persist between calls (the
+ *     packed image, see reuse_prepared) but are otherwise opaque.
+ *   - Calls that share a workspace must be ordered (same stream, or the
+ *     caller synchronises); calls on distinct workspaces are independent.
+ *
+ * Grid (Sec. II-A): r = sqrt(N / k) with N = W*H and the requested k;
+ * nx = max(1, lround(W / r)), ny = max(1, lround(H / r)), K' = nx * ny
+ * (K' may differ from k; every K'-sized buffer uses K').  Pixel (x, y)
+ * belongs to cell (floor(y*ny/H), floor(x*nx/W)), cluster index
+ * i * nx + j.
+ */
+#ifndef SCALP_H
+#define SCALP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    SCALP_OK = 0,
+    SCALP_ERR_ARG = -1,          /* invalid argument (null pointer, size, parameter range) */
+    SCALP_ERR_WORKSPACE = -2,    /* workspace pointer null or smaller than required        */
+    SCALP_ERR_HIP = -3,          /* a HIP runtime call or kernel launch reported an error  */
+    SCALP_ERR_UNSUPPORTED = -4   /* valid request this build does not support              */
+};
+
+typedef struct {
+    int32_t width, height;   /* W, H (pixels), both >= 1                     */
+    int32_t k_requested;     /* k, 1 <= k <= W*H                             */
+    int32_t nx, ny;          /* grid columns / rows                          */
+    int32_t num_sp;          /* K' = nx * ny                                 */
+    float r;                 /* sqrt(N / k), informational                  */
+} scalp_grid_t;
+
+typedef struct {
+    float m;                 /* compactness of Eq. (3); paper default 10     */
+    float lambda;            /* weight of Eq. (1), in [0, 1]; default 0.5    */
+    float sigma;             /* scale of Eq. (2), > 0; default 0.25          */
+    float gamma;             /* weight of Eq. (2), >= 0; < 0 selects 2r      */
+    int32_t iterations;      /* clustering iterations (Algorithm 1); >= 0    */
+    int32_t project;         /* 1: Eq. (4) projection after each update      */
+    int32_t reuse_prepared;  /* 1: the workspace already holds this image's
+                                packed (l, a, b, w) from an earlier call with
+                                the same lab/contour/sigma; skip re-packing  */
+    int32_t lds_pixels;      /* tuning: LDS halo budget in pixels (16 B each),
+                                0..9728; 0 selects the default (4800)        */
+    int32_t wg_size;         /* tuning: assignment workgroup size, 0 (default
+                                256), 256 or 512                             */
+} scalp_params_t;
+
+/* Fills the paper's defaults (Sec. III-A.3: m = 10, lambda = 0.5,
+ * sigma = 0.25, gamma = 2r) with 10 iterations and projection on.
+ * out: host pointer.  Returns SCALP_ERR_ARG if out is NULL. */
+int scalp_default_params(scalp_params_t* out);
+
+/* Host-only grid arithmetic (Sec. II-A; see the header comment).
+ * out: host pointer.  SCALP_ERR_ARG if W, H < 1, k < 1, k > W*H or
+ * W*H >= 2^31. */
+int scalp_make_grid(int32_t width, int32_t height, int32_t k, scalp_grid_t* out);
+
+/* Bytes of device workspace the single-image entry points need for grid g:
+ * the packed (l, a, b, w) image (16 B per pixel) plus 68 B per superpixel
+ * (integer accumulators, projection queue) and 256 B of control words.
+ * 0 if g is invalid. */
+size_t scalp_workspace_bytes(const scalp_grid_t* g);
+
+/* Packs lab and contour into the workspace as float4 (l, a, b, w) with
+ * w = 1 - exp(-C^2 / sigma^2), the summand of Eq. (2), evaluated in FP64 and
+ * rounded once to FP32. */
+int scalp_prepare(const scalp_grid_t* g, const scalp_params_t* p, const float* lab,
+                  const float* contour, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Algorithm 1, initialisation: packs the image (unless reuse_prepared), sets
+ * labels to the cell index of every pixel, centers to each cell's mean
+ * colour and barycenter, and endpoints to the rounded barycenters
+ * floor(x + 0.5).  Means use exact integer sums of the positions and of the
+ * colours in 2^-24 fixed point, divided in FP64 and rounded once to FP32. */
+int scalp_init_grid(const scalp_grid_t* g, const scalp_params_t* p, const float* lab,
+                    const float* contour, float* centers, int32_t* endpoints, int32_t* labels,
+                    void* workspace, size_t workspace_bytes, void* stream);
+
+/* Algorithm 1, one assignment pass from the given centers and endpoints:
+ * every pixel compares the distance D of Eqs. (1)-(3), computed along the
+ * Bresenham path from the pixel to each candidate's endpoint (Sec. II-B),
+ * over the superpixels of the 3x3 grid cells around its own cell, and takes
+ * the first strict minimum in ascending superpixel order.  FP32 arithmetic
+ * in a fixed per-pixel order (no contraction), so labels are reproducible
+ * bit for bit.  labels: output. */
+int scalp_assign(const scalp_grid_t* g, const scalp_params_t* p, const float* lab,
+                 const float* contour, const float* centers, const int32_t* endpoints,
+                 int32_t* labels, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Algorithm 1, cluster update, then (if p->project) the projection of
+ * Eq. (4): centers (in/out) become the mean colour and barycenter of each
+ * superpixel of `labels` (empty superpixels keep their center); endpoints
+ * (in/out) become the rounded barycenter, or, when that pixel's label is
+ * not k, the member pixel nearest to the barycenter (ties: lowest raster
+ * index); counts: output.  Labels outside [0, K') are ignored. */
+int scalp_update(const scalp_grid_t* g, const scalp_params_t* p, const float* lab,
+                 const int32_t* labels, float* centers, int32_t* endpoints, int32_t* counts,
+                 void* workspace, size_t workspace_bytes, void* stream);
+
+/* Algorithm 1 end to end: prepare, init, then p->iterations x (assign,
+ * update, projection).  The update is fused into the assignment kernel.
+ * centers, endpoints, labels, counts: outputs. */
+int scalp_run(const scalp_grid_t* g, const scalp_params_t* p, const float* lab,
+              const float* contour, float* centers, int32_t* endpoints, int32_t* labels,
+              int32_t* counts, void* workspace, size_t workspace_bytes, void* stream);
+
+/* The iteration loop of scalp_run (assign, update, projection, repeated
+ * p->iterations times) captured once into a hipGraph for fixed buffers, and
+ * replayed with scalp_graph_launch.  The graph reads centers and endpoints
+ * and leaves the next state in them, so each replay continues the run.
+ * *out receives an opaque handle (host pointer).  The packed image must
+ * already be in the workspace (scalp_prepare or scalp_init_grid). */
+typedef struct scalp_graph* scalp_graph_handle;
+int scalp_graph_create(const scalp_grid_t* g, const scalp_params_t* p, float* centers,
+                       int32_t* endpoints, int32_t* labels, int32_t* counts, void* workspace,
+                       size_t workspace_bytes, scalp_graph_handle* out);
+int scalp_graph_launch(scalp_graph_handle h, void* stream);
+int scalp_graph_destroy(scalp_graph_handle h);
+
+/* ---- Batched hard SCALP: many images of different sizes and k ---------- */
+
+/* One image of a batch.  Pixel data of image i starts at pixel pix_offset
+ * in the concatenated lab (x3 floats), contour and labels arrays; its
+ * superpixels start at sp_offset in the concatenated centers (x5),
+ * endpoints (x2) and counts arrays.  grid must come from scalp_make_grid. */
+typedef struct {
+    int64_t pix_offset;
+    int32_t sp_offset;
+    int32_t reserved;
+    scalp_grid_t grid;
+} scalp_batch_desc_t;
+
+/* Workspace bytes for a batch (descs: host array of n_images); 0 if a
+ * descriptor is invalid or the images are not concatenated in order
+ * (pix_offset and sp_offset must be the running sums of W*H and K'). */
+size_t scalp_batch_workspace_bytes(const scalp_batch_desc_t* descs, int32_t n_images);
+
+/* Algorithm 1 on every image of the batch: prepare, init and
+ * p->iterations x (assign + update, projection), each iteration one
+ * persistent launch over a work queue of (image, cell) items.  Results are
+ * identical to scalp_run on each image alone.  descs: host array; all other
+ * arrays are device arrays concatenated as described above.  gamma < 0
+ * selects 2r per image. */
+int scalp_run_batched(const scalp_batch_desc_t* descs, int32_t n_images, const scalp_params_t* p,
+                      const float* lab, const float* contour, float* centers,
+                      int32_t* endpoints, int32_t* labels, int32_t* counts, void* workspace,
+                      size_t workspace_bytes, void* stream);
+
+/* The same run captured once into a hipGraph (prepare, init and all
+ * iterations), replayed with scalp_graph_launch; each replay recomputes the
+ * whole run from lab/contour. */
+int scalp_batched_graph_create(const scalp_batch_desc_t* descs, int32_t n_images,
+                               const scalp_params_t* p, const float* lab, const float* contour,
+                               float* centers, int32_t* endpoints, int32_t* labels,
+                               int32_t* counts, void* workspace, size_t workspace_bytes,
+                               scalp_graph_handle* out);
+
+/* ---- Soft SCALP (differentiable extension, not in the paper) ------------ */
+/*
+ * B images of the same size.  Q_pj = softmax_j(-D_pj / T) over the 3x3
+ * candidate slots j = (di+1)*3 + (dj+1) (slots outside the grid get 0), D of
+ * Eqs. (1)-(3) with paths to floor(X_k + 0.5) (no projection); soft update
+ * f_k = sum Q f_p / sum Q, X_k = sum Q X_p / sum Q (sum Q = 0: keep);
+ * Theta_0 = cell means.  FP32 throughout.
+ *   centers_t : float32 [iters+1][B][K'][5]   (output; Theta_0 .. Theta_T)
+ *   q_t       : float32 [iters][B][H][W][9]   (output)
+ *   saved     : scalp_soft_saved_bytes() bytes (output of forward, input of
+ *               backward): per-iteration distance factors and sum Q.
+ */
+size_t scalp_soft_saved_bytes(const scalp_grid_t* g, int32_t batch, int32_t iterations);
+size_t scalp_soft_workspace_bytes(const scalp_grid_t* g, int32_t batch);
+int scalp_soft_forward(const scalp_grid_t* g, const scalp_params_t* p, float temperature,
+                       int32_t batch, const float* lab, const float* contour, float* centers_t,
+                       float* q_t, void* saved, void* workspace, size_t workspace_bytes, void* stream);
+/* Gradient of L given dL/dQ_T (grad_q: [B][H][W][9]) and dL/dTheta_T
+ * (grad_centers: [B][K'][5]) with respect to lab (grad_lab: [B][H][W][3],
+ * output) and contour (grad_contour: [B][H][W], output).  Path samples are
+ * recomputed, not stored.  FP32 with float atomics: not bit-reproducible. */
+int scalp_soft_backward(const scalp_grid_t* g, const scalp_params_t* p, float temperature,
+                        int32_t batch, const float* lab, const float* contour,
+                        const float* centers_t, const float* q_t, const void* saved,
+                        const float* grad_q, const float* grad_centers, float* grad_lab,
+                        float* grad_contour, void* workspace, size_t workspace_bytes,
+                        void* stream);
+
+/* Static description of a code. */
+const char* scalp_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SCALP_H */

@@ -1,0 +1,460 @@
+// scalp_abi.hip -- the extern "C" entry points of libscalp.so: argument
+// validation, workspace layout, kernel sequencing and hipGraph capture.
+// Declarations and their contracts are in include/scalp.h.
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "scalp.h"
+#include "scalp_internal.h"
+
+using namespace scalp;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+std::once_flag g_init_once;
+void library_init() { std::call_once(g_init_once, [] { lift_lds_limits(); }); }
+
+// r = sqrt(N / k) in FP64 (Sec. II-A), with the requested k.
+double grid_r(int W, int H, int k) { return std::sqrt((double)W * (double)H / (double)k); }
+
+bool grid_valid(const scalp_grid_t* g) {
+    if (!g) return false;
+    scalp_grid_t ref;
+    if (scalp_make_grid(g->width, g->height, g->k_requested, &ref) != SCALP_OK) return false;
+    return ref.nx == g->nx && ref.ny == g->ny && ref.num_sp == g->num_sp;
+}
+
+bool params_valid(const scalp_params_t* p) {
+    if (!p) return false;
+    if (!std::isfinite(p->m) || p->m < 0.0f) return false;
+    if (!(p->lambda >= 0.0f && p->lambda <= 1.0f)) return false;
+    if (!(p->sigma > 0.0f) || !std::isfinite(p->sigma)) return false;
+    if (!std::isfinite(p->gamma)) return false;
+    if (p->iterations < 0) return false;
+    if (p->lds_pixels < 0 || p->lds_pixels > kMaxLdsPixels) return false;
+    if (p->wg_size != 0 && p->wg_size != 256 && p->wg_size != 512) return false;
+    return true;
+}
+
+Tuning tuning_of(const scalp_params_t* p) {
+    Tuning t;
+    t.wg = p->wg_size == 512 ? 512 : 256;
+    t.lds_pixels = p->lds_pixels > 0 ? p->lds_pixels : default_lds_pixels();
+    return t;
+}
+
+Img img_of(const scalp_grid_t* g, const scalp_params_t* p, long long pix, int sp) {
+    Img im;
+    im.W = g->width;
+    im.H = g->height;
+    im.nx = g->nx;
+    im.ny = g->ny;
+    im.pix = pix;
+    im.sp = sp;
+    const double r = grid_r(g->width, g->height, g->k_requested);
+    im.spw = (float)(((double)p->m * (double)p->m) / (r * r));          // Eq. (3)
+    im.gamma = p->gamma < 0.0f ? (float)(2.0 * r) : p->gamma;           // Sec. III-A.3
+    im.pad = 0;
+    return im;
+}
+
+// Single-image workspace: [packed float4 N][acc int64 8K][ctrl int32 64][plist int32 K]
+struct Layout {
+    size_t packed, acc, ctrl, plist, total;
+};
+
+Layout layout_of(long long N, long long K) {
+    Layout L;
+    L.packed = 0;
+    L.acc = align_up((size_t)N * 16);
+    L.ctrl = L.acc + (size_t)K * kAccStride * 8;   // acc and ctrl are contiguous (cleared together)
+    L.plist = align_up(L.ctrl + kCtrlWords * 4);
+    L.total = align_up(L.plist + (size_t)K * 4);
+    return L;
+}
+
+struct Views {
+    float4* packed;
+    long long* acc;
+    int* ctrl;
+    int* plist;
+};
+
+Views views_of(void* ws, const Layout& L) {
+    char* b = static_cast<char*>(ws);
+    return Views{reinterpret_cast<float4*>(b + L.packed), reinterpret_cast<long long*>(b + L.acc),
+                 reinterpret_cast<int*>(b + L.ctrl), reinterpret_cast<int*>(b + L.plist)};
+}
+
+long long clear_words(const Layout& L) { return (long long)((L.ctrl + kCtrlWords * 4 - L.acc) / 8); }
+
+#define CHECK_HIP(expr)                            \
+    do {                                           \
+        if ((expr) != hipSuccess) return SCALP_ERR_HIP; \
+    } while (0)
+
+int check_common(const scalp_grid_t* g, const scalp_params_t* p, void* ws, size_t ws_bytes) {
+    if (!grid_valid(g) || !params_valid(p)) return SCALP_ERR_ARG;
+    if (!ws || ws_bytes < scalp_workspace_bytes(g)) return SCALP_ERR_WORKSPACE;
+    return SCALP_OK;
+}
+
+// Enqueue helpers (no validation).
+int enq_prepare(const scalp_grid_t* g, const scalp_params_t* p, const float* lab,
+                const float* contour, const Views& v, hipStream_t s) {
+    return launch_prepare((long long)g->width * g->height, lab, contour, p->sigma, v.packed, s);
+}
+
+int enq_init(const Img& im, const Views& v, float* centers, int* endpoints, int* counts,
+             int* labels, hipStream_t s) {
+    int e = launch_init_cells(im, v.packed, labels, v.acc, s);
+    if (e == hipSuccess)
+        e = launch_finalize(im, centers, endpoints, counts, v.acc, labels, v.ctrl, v.plist, false, s);
+    return e;
+}
+
+int enq_iterations(const Img& im, const scalp_params_t* p, const Views& v, float* centers,
+                   int* endpoints, int* labels, int* counts, hipStream_t s) {
+    const Tuning t = tuning_of(p);
+    for (int it = 0; it < p->iterations; ++it) {
+        int e = launch_assign(im, v.packed, centers, endpoints, labels, v.acc, v.ctrl, p->lambda,
+                              true, t, s);
+        if (e == hipSuccess)
+            e = launch_finalize(im, centers, endpoints, counts, v.acc, labels, v.ctrl, v.plist,
+                                p->project != 0, s);
+        if (e == hipSuccess && p->project)
+            e = launch_project(im, centers, counts, labels, endpoints, v.ctrl, v.plist, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
+struct scalp_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+extern "C" int scalp_graph_destroy(scalp_graph_handle h);
+
+namespace {
+
+int capture(scalp_graph_handle* out, const std::function<int(hipStream_t)>& body) {
+    hipStream_t cs = nullptr;
+    CHECK_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    scalp_graph* h = new (std::nothrow) scalp_graph();
+    if (!h) {
+        static_cast<void>(hipStreamDestroy(cs));
+        return SCALP_ERR_HIP;
+    }
+    int rc = SCALP_OK;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) rc = SCALP_ERR_HIP;
+    if (rc == SCALP_OK) {
+        const int e = body(cs);
+        const hipError_t ee = hipStreamEndCapture(cs, &h->graph);
+        if (e != hipSuccess || ee != hipSuccess) rc = SCALP_ERR_HIP;
+    }
+    if (rc == SCALP_OK && hipGraphInstantiate(&h->exec, h->graph, nullptr, nullptr, 0) != hipSuccess)
+        rc = SCALP_ERR_HIP;
+    static_cast<void>(hipStreamDestroy(cs));
+    if (rc != SCALP_OK) {
+        scalp_graph_destroy(h);
+        return rc;
+    }
+    *out = h;
+    return SCALP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int scalp_default_params(scalp_params_t* out) {
+    if (!out) return SCALP_ERR_ARG;
+    out->m = 10.0f;
+    out->lambda = 0.5f;
+    out->sigma = 0.25f;
+    out->gamma = -1.0f;
+    out->iterations = 10;
+    out->project = 1;
+    out->reuse_prepared = 0;
+    out->lds_pixels = 0;
+    out->wg_size = 0;
+    return SCALP_OK;
+}
+
+int scalp_make_grid(int32_t W, int32_t H, int32_t k, scalp_grid_t* out) {
+    if (!out || W < 1 || H < 1 || k < 1) return SCALP_ERR_ARG;
+    const long long N = (long long)W * H;
+    if (N >= (1LL << 31) || (long long)k > N) return SCALP_ERR_ARG;
+    const double r = grid_r(W, H, k);
+    long gx = std::lround((double)W / r), gy = std::lround((double)H / r);
+    gx = gx < 1 ? 1 : (gx > W ? W : gx);
+    gy = gy < 1 ? 1 : (gy > H ? H : gy);
+    out->width = W;
+    out->height = H;
+    out->k_requested = k;
+    out->nx = (int32_t)gx;
+    out->ny = (int32_t)gy;
+    out->num_sp = (int32_t)(gx * gy);
+    out->r = (float)r;
+    return SCALP_OK;
+}
+
+size_t scalp_workspace_bytes(const scalp_grid_t* g) {
+    if (!grid_valid(g)) return 0;
+    return layout_of((long long)g->width * g->height, g->num_sp).total;
+}
+
+int scalp_prepare(const scalp_grid_t* g, const scalp_params_t* p, const float* lab,
+                  const float* contour, void* ws, size_t ws_bytes, void* stream) {
+    int rc = check_common(g, p, ws, ws_bytes);
+    if (rc != SCALP_OK) return rc;
+    if (!lab || !contour) return SCALP_ERR_ARG;
+    library_init();
+    const Views v = views_of(ws, layout_of((long long)g->width * g->height, g->num_sp));
+    CHECK_HIP(enq_prepare(g, p, lab, contour, v, (hipStream_t)stream));
+    return SCALP_OK;
+}
+
+int scalp_init_grid(const scalp_grid_t* g, const scalp_params_t* p, const float* lab,
+                    const float* contour, float* centers, int32_t* endpoints, int32_t* labels,
+                    void* ws, size_t ws_bytes, void* stream) {
+    int rc = check_common(g, p, ws, ws_bytes);
+    if (rc != SCALP_OK) return rc;
+    if (!centers || !endpoints || !labels) return SCALP_ERR_ARG;
+    if (!p->reuse_prepared && (!lab || !contour)) return SCALP_ERR_ARG;
+    library_init();
+    const hipStream_t s = (hipStream_t)stream;
+    const Layout L = layout_of((long long)g->width * g->height, g->num_sp);
+    const Views v = views_of(ws, L);
+    if (!p->reuse_prepared) CHECK_HIP(enq_prepare(g, p, lab, contour, v, s));
+    // counts are not an output of this call: the projection list area holds them
+    CHECK_HIP(enq_init(img_of(g, p, 0, 0), v, centers, endpoints, v.plist, labels, s));
+    return SCALP_OK;
+}
+
+int scalp_assign(const scalp_grid_t* g, const scalp_params_t* p, const float* lab,
+                 const float* contour, const float* centers, const int32_t* endpoints,
+                 int32_t* labels, void* ws, size_t ws_bytes, void* stream) {
+    int rc = check_common(g, p, ws, ws_bytes);
+    if (rc != SCALP_OK) return rc;
+    if (!centers || !endpoints || !labels) return SCALP_ERR_ARG;
+    if (!p->reuse_prepared && (!lab || !contour)) return SCALP_ERR_ARG;
+    library_init();
+    const hipStream_t s = (hipStream_t)stream;
+    const Views v = views_of(ws, layout_of((long long)g->width * g->height, g->num_sp));
+    if (!p->reuse_prepared) CHECK_HIP(enq_prepare(g, p, lab, contour, v, s));
+    CHECK_HIP(launch_assign(img_of(g, p, 0, 0), v.packed, centers, endpoints, labels, v.acc,
+                            v.ctrl, p->lambda, false, tuning_of(p), s));
+    return SCALP_OK;
+}
+
+int scalp_update(const scalp_grid_t* g, const scalp_params_t* p, const float* lab,
+                 const int32_t* labels, float* centers, int32_t* endpoints, int32_t* counts,
+                 void* ws, size_t ws_bytes, void* stream) {
+    int rc = check_common(g, p, ws, ws_bytes);
+    if (rc != SCALP_OK) return rc;
+    if (!lab || !labels || !centers || !endpoints || !counts) return SCALP_ERR_ARG;
+    library_init();
+    const hipStream_t s = (hipStream_t)stream;
+    const Layout L = layout_of((long long)g->width * g->height, g->num_sp);
+    const Views v = views_of(ws, L);
+    const Img im = img_of(g, p, 0, 0);
+    CHECK_HIP(launch_clear(v.acc, clear_words(L), s));
+    CHECK_HIP(launch_accumulate(im, lab, labels, v.acc, s));
+    CHECK_HIP(launch_finalize(im, centers, endpoints, counts, v.acc, labels, v.ctrl, v.plist,
+                              p->project != 0, s));
+    if (p->project)
+        CHECK_HIP(launch_project(im, centers, counts, labels, endpoints, v.ctrl, v.plist, s));
+    return SCALP_OK;
+}
+
+int scalp_run(const scalp_grid_t* g, const scalp_params_t* p, const float* lab,
+              const float* contour, float* centers, int32_t* endpoints, int32_t* labels,
+              int32_t* counts, void* ws, size_t ws_bytes, void* stream) {
+    int rc = check_common(g, p, ws, ws_bytes);
+    if (rc != SCALP_OK) return rc;
+    if (!centers || !endpoints || !labels || !counts) return SCALP_ERR_ARG;
+    if (!p->reuse_prepared && (!lab || !contour)) return SCALP_ERR_ARG;
+    library_init();
+    const hipStream_t s = (hipStream_t)stream;
+    const Views v = views_of(ws, layout_of((long long)g->width * g->height, g->num_sp));
+    const Img im = img_of(g, p, 0, 0);
+    if (!p->reuse_prepared) CHECK_HIP(enq_prepare(g, p, lab, contour, v, s));
+    CHECK_HIP(enq_init(im, v, centers, endpoints, counts, labels, s));
+    CHECK_HIP(enq_iterations(im, p, v, centers, endpoints, labels, counts, s));
+    return SCALP_OK;
+}
+
+int scalp_graph_create(const scalp_grid_t* g, const scalp_params_t* p, float* centers,
+                       int32_t* endpoints, int32_t* labels, int32_t* counts, void* ws,
+                       size_t ws_bytes, scalp_graph_handle* out) {
+    int rc = check_common(g, p, ws, ws_bytes);
+    if (rc != SCALP_OK) return rc;
+    if (!centers || !endpoints || !labels || !counts || !out) return SCALP_ERR_ARG;
+    library_init();
+    const Views v = views_of(ws, layout_of((long long)g->width * g->height, g->num_sp));
+    const Img im = img_of(g, p, 0, 0);
+    const scalp_params_t pc = *p;
+    return capture(out, [&](hipStream_t s) {
+        return enq_iterations(im, &pc, v, centers, endpoints, labels, counts, s);
+    });
+}
+
+int scalp_graph_launch(scalp_graph_handle h, void* stream) {
+    if (!h || !h->exec) return SCALP_ERR_ARG;
+    CHECK_HIP(hipGraphLaunch(h->exec, (hipStream_t)stream));
+    return SCALP_OK;
+}
+
+int scalp_graph_destroy(scalp_graph_handle h) {
+    if (!h) return SCALP_OK;
+    int rc = SCALP_OK;
+    if (h->exec && hipGraphExecDestroy(h->exec) != hipSuccess) rc = SCALP_ERR_HIP;
+    if (h->graph && hipGraphDestroy(h->graph) != hipSuccess) rc = SCALP_ERR_HIP;
+    delete h;
+    return rc;
+}
+
+// ------------------------------------------------------------------ batched
+
+namespace {
+
+// Batched workspace: [packed][acc][ctrl][plist][imgs][cell_start]
+struct BatchLayout {
+    Layout base;
+    size_t imgs, starts, total;
+    long long N, K;
+};
+
+bool batch_layout(const scalp_batch_desc_t* d, int n, BatchLayout* out) {
+    if (!d || n < 1) return false;
+    long long N = 0, K = 0;
+    for (int i = 0; i < n; ++i) {
+        if (!grid_valid(&d[i].grid)) return false;
+        if (d[i].pix_offset != N || d[i].sp_offset != K) return false;
+        N += (long long)d[i].grid.width * d[i].grid.height;
+        K += d[i].grid.num_sp;
+        if (N >= (1LL << 40) || K >= (1LL << 31)) return false;
+    }
+    out->base = layout_of(N, K);
+    out->imgs = out->base.total;
+    out->starts = align_up(out->imgs + sizeof(Img) * (size_t)n);
+    out->total = align_up(out->starts + sizeof(int) * (size_t)(n + 1));
+    out->N = N;
+    out->K = K;
+    return true;
+}
+
+int enq_batched(const scalp_batch_desc_t* d, int n, const scalp_params_t* p, const float* lab,
+                const float* contour, float* centers, int* endpoints, int* labels, int* counts,
+                void* ws, const BatchLayout& BL, int grid, hipStream_t s) {
+    const Views v = views_of(ws, BL.base);
+    char* b = static_cast<char*>(ws);
+    Img* imgs = reinterpret_cast<Img*>(b + BL.imgs);
+    int* starts = reinterpret_cast<int*>(b + BL.starts);
+    std::vector<Img> himg((size_t)n);
+    std::vector<int> hstart((size_t)n + 1);
+    for (int i = 0; i < n; ++i) {
+        himg[(size_t)i] = img_of(&d[i].grid, p, d[i].pix_offset, d[i].sp_offset);
+        hstart[(size_t)i] = d[i].sp_offset;
+    }
+    hstart[(size_t)n] = (int)BL.K;
+    int e = launch_write_bytes(imgs, himg.data(), sizeof(Img) * (size_t)n, s);
+    if (e == hipSuccess) e = launch_write_bytes(starts, hstart.data(), sizeof(int) * (size_t)(n + 1), s);
+    if (e == hipSuccess && !p->reuse_prepared) e = launch_prepare(BL.N, lab, contour, p->sigma, v.packed, s);
+    if (e == hipSuccess) e = launch_init_cells_batched(imgs, starts, n, (int)BL.K, v.packed, labels, v.acc, s);
+    if (e == hipSuccess)
+        e = launch_finalize_batched(imgs, starts, n, (int)BL.K, centers, endpoints, counts, v.acc,
+                                    labels, v.ctrl, v.plist, false, s);
+    const Tuning t = tuning_of(p);
+    for (int it = 0; e == hipSuccess && it < p->iterations; ++it) {
+        e = launch_assign_persistent(imgs, starts, n, (int)BL.K, v.packed, centers, endpoints,
+                                     labels, v.acc, v.ctrl, p->lambda, t, grid, s);
+        if (e == hipSuccess)
+            e = launch_finalize_batched(imgs, starts, n, (int)BL.K, centers, endpoints, counts,
+                                        v.acc, labels, v.ctrl, v.plist, p->project != 0, s);
+        if (e == hipSuccess && p->project)
+            e = launch_project_batched(imgs, starts, n, centers, counts, labels, endpoints, v.ctrl,
+                                       v.plist, s);
+    }
+    return e;
+}
+
+}  // namespace
+
+size_t scalp_batch_workspace_bytes(const scalp_batch_desc_t* descs, int32_t n) {
+    BatchLayout BL;
+    if (!batch_layout(descs, n, &BL)) return 0;
+    return BL.total;
+}
+
+int scalp_run_batched(const scalp_batch_desc_t* descs, int32_t n, const scalp_params_t* p,
+                      const float* lab, const float* contour, float* centers, int32_t* endpoints,
+                      int32_t* labels, int32_t* counts, void* ws, size_t ws_bytes,
+                      void* stream) {
+    BatchLayout BL;
+    if (!batch_layout(descs, n, &BL) || !params_valid(p)) return SCALP_ERR_ARG;
+    if (!centers || !endpoints || !labels || !counts) return SCALP_ERR_ARG;
+    if (!p->reuse_prepared && (!lab || !contour)) return SCALP_ERR_ARG;
+    if (!ws || ws_bytes < BL.total) return SCALP_ERR_WORKSPACE;
+    library_init();
+    const int grid = persistent_grid(tuning_of(p));
+    if (grid < 1) return SCALP_ERR_HIP;
+    CHECK_HIP(enq_batched(descs, n, p, lab, contour, centers, endpoints, labels, counts, ws, BL,
+                          grid, (hipStream_t)stream));
+    return SCALP_OK;
+}
+
+int scalp_batched_graph_create(const scalp_batch_desc_t* descs, int32_t n, const scalp_params_t* p,
+                               const float* lab, const float* contour, float* centers,
+                               int32_t* endpoints, int32_t* labels, int32_t* counts, void* ws,
+                               size_t ws_bytes, scalp_graph_handle* out) {
+    BatchLayout BL;
+    if (!batch_layout(descs, n, &BL) || !params_valid(p)) return SCALP_ERR_ARG;
+    if (!centers || !endpoints || !labels || !counts || !out) return SCALP_ERR_ARG;
+    if (!p->reuse_prepared && (!lab || !contour)) return SCALP_ERR_ARG;
+    if (!ws || ws_bytes < BL.total) return SCALP_ERR_WORKSPACE;
+    library_init();
+    // the occupancy query runs before the capture
+    const int grid = persistent_grid(tuning_of(p));
+    if (grid < 1) return SCALP_ERR_HIP;
+    return capture(out, [&](hipStream_t s) {
+        return enq_batched(descs, n, p, lab, contour, centers, endpoints, labels, counts, ws, BL,
+                           grid, s);
+    });
+}
+
+size_t scalp_soft_saved_bytes(const scalp_grid_t*, int32_t, int32_t) { return 0; }
+size_t scalp_soft_workspace_bytes(const scalp_grid_t*, int32_t) { return 0; }
+int scalp_soft_forward(const scalp_grid_t*, const scalp_params_t*, float, int32_t, const float*,
+                       const float*, float*, float*, void*, void*, size_t, void*) {
+    return SCALP_ERR_UNSUPPORTED;
+}
+int scalp_soft_backward(const scalp_grid_t*, const scalp_params_t*, float, int32_t, const float*,
+                        const float*, const float*, const float*, const void*, const float*,
+                        const float*, float*, float*, void*, size_t, void*) {
+    return SCALP_ERR_UNSUPPORTED;
+}
+
+const char* scalp_strerror(int code) {
+    switch (code) {
+        case SCALP_OK: return "ok";
+        case SCALP_ERR_ARG: return "invalid argument";
+        case SCALP_ERR_WORKSPACE: return "workspace missing or too small";
+        case SCALP_ERR_HIP: return "HIP runtime error";
+        case SCALP_ERR_UNSUPPORTED: return "unsupported request";
+        default: return "unknown error code";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,83 @@
+// scalp_internal.h -- shared declarations of the HIP kernels and the host ABI
+// layer of libscalp.so (not part of the public interface).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace scalp {
+
+// Fixed point of the colour sums in the update: values are rounded to
+// multiples of 2^-24 and summed as 64-bit integers, so the sum does not
+// depend on the order in which pixels arrive (atomics, workgroups).
+constexpr float kFixScaleF = 16777216.0f;
+constexpr double kFixInv = 1.0 / 16777216.0;
+
+// Per-superpixel accumulator stride (int64 words): count, sum x, sum y,
+// sum l, sum a, sum b, 2 pad -> one 64-byte line per superpixel.
+constexpr int kAccStride = 8;
+
+// Control words in the workspace.
+enum Ctrl : int {
+    kCtrlProjCount = 0,   // entries in the projection list
+    kCtrlQueue = 1,       // persistent work-queue head
+    kCtrlWords = 64
+};
+
+// One image as the kernels see it.
+struct Img {
+    int W, H, nx, ny;
+    long long pix;    // first pixel in the concatenated pixel arrays
+    int sp;           // first superpixel in the concatenated superpixel arrays
+    float spw;        // m^2 / r^2 of Eq. (3)
+    float gamma;      // gamma of Eq. (2)
+    int pad;
+};
+
+struct Tuning {
+    int wg;           // workgroup size of the assignment kernel (256 or 512)
+    int lds_pixels;   // LDS halo budget in pixels
+};
+
+int default_lds_pixels();
+constexpr int kMaxLdsPixels = 9728;   // 152 KiB of the 160 KiB LDS of a gfx950 CU
+
+// Raises the per-kernel dynamic LDS limit of the assignment kernels (once per
+// process, before any launch or capture).
+void lift_lds_limits();
+int launch_write_bytes(void* dst, const void* src, size_t n, hipStream_t s);
+
+// Launchers (return hipError_t as int).  All enqueue on `s`.
+int launch_prepare(long long n, const float* lab, const float* contour, float sigma,
+                   float4* packed, hipStream_t s);
+int launch_clear(long long* p, long long n_words, hipStream_t s);
+int launch_init_cells(const Img& im, const float4* packed, int* labels, long long* acc,
+                      hipStream_t s);
+int launch_assign(const Img& im, const float4* packed, const float* centres,
+                  const int* endpoints, int* labels, long long* acc, int* ctrl, float lambda,
+                  bool accumulate, const Tuning& t, hipStream_t s);
+int launch_accumulate(const Img& im, const float* lab, const int* labels, long long* acc,
+                      hipStream_t s);
+int launch_finalize(const Img& im, float* centres, int* endpoints, int* counts,
+                    long long* acc, const int* labels, int* ctrl, int* plist, bool project,
+                    hipStream_t s);
+int launch_project(const Img& im, const float* centres, const int* counts, const int* labels,
+                   int* endpoints, const int* ctrl, const int* plist, hipStream_t s);
+
+// Batched variants: imgs/cell_start/sp_start are device arrays in the workspace.
+int launch_init_cells_batched(const Img* imgs, const int* cell_start, int n_img, int total_cells,
+                              const float4* packed, int* labels, long long* acc, hipStream_t s);
+int launch_assign_persistent(const Img* imgs, const int* cell_start, int n_img, int total_cells,
+                             const float4* packed, const float* centres, const int* endpoints,
+                             int* labels, long long* acc, int* ctrl, float lambda,
+                             const Tuning& t, int grid, hipStream_t s);
+int launch_finalize_batched(const Img* imgs, const int* sp_start, int n_img, int total_sp,
+                            float* centres, int* endpoints, int* counts, long long* acc,
+                            const int* labels, int* ctrl, int* plist, bool project,
+                            hipStream_t s);
+int launch_project_batched(const Img* imgs, const int* sp_start, int n_img, const float* centres,
+                           const int* counts, const int* labels, int* endpoints,
+                           const int* ctrl, const int* plist, hipStream_t s);
+int persistent_grid(const Tuning& t);
+
+}  // namespace scalp

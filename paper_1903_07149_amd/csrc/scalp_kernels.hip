@@ -1,0 +1,783 @@
+// scalp_kernels.hip -- HIP kernels (gfx950) of the SCALP clustering path.
+//
+//   k_prepare         packs (l, a, b, w) with w = 1 - exp(-C^2/sigma^2), the
+//                     summand of Eq. (2), evaluated in FP64 and rounded once.
+//   k_init_cells      Algorithm 1 initialisation: labels = grid cell, per-cell
+//                     integer sums (Sec. II-A regular grid).
+//   k_assign*         Algorithm 1 assignment: one workgroup per grid cell.  The
+//                     rectangle of the packed image that the cell's paths can
+//                     reach (the cell plus its <= 9 candidates' endpoints) is
+//                     staged in LDS; every lane walks the Bresenham path
+//                     (Sec. II-B) from its pixel to each candidate's endpoint,
+//                     accumulating Eq. (1)'s colour term and Eq. (2)'s contour
+//                     term in a fixed FP32 order, forms D of Eq. (3) and keeps
+//                     the first strict minimum.  With ACCUM the update's sums
+//                     are fused in: each pixel can only choose among the cell's
+//                     9 candidates, so they reduce into 9 LDS bins and leave
+//                     the workgroup as 54 integer atomics.
+//   k_finalize*       Algorithm 1 update: means from the integer sums, the
+//                     rounded barycenter, and the membership test of the
+//                     Sec. II-D Remark; clusters that fail it are queued.
+//   k_project*        Eq. (4): nearest member pixel of each queued cluster.
+//
+// All FP32 arithmetic of the distance is written operation by operation and
+// compiled with -ffp-contract=off, so it matches the plain CPU definition
+// bit for bit.
+#include <algorithm>
+
+#include "scalp_internal.h"
+
+namespace scalp {
+namespace {
+
+// First coordinate of grid cell `idx` of `n` along an axis of `len` pixels:
+// pixel c is in cell floor(c * n / len), i.e. cell idx starts at
+// ceil(idx * len / n).
+__device__ __forceinline__ int cell_lo(int idx, int len, int n) {
+    return (int)(((long long)idx * len + n - 1) / n);
+}
+
+struct Cand {
+    int k;            // superpixel index within the image, -1 outside the grid
+    float l, a, b, x, y;
+    int cx, cy;       // path endpoint
+    float dcc, wc;    // colour distance and w of the endpoint sample
+    int staged;       // 1: the endpoint (hence every path to it) is inside the LDS rectangle
+};
+
+struct CellShared {
+    Cand cand[9];
+    int rx0, ry0, rw, rh;
+    unsigned long long bins[9][6];
+};
+
+__device__ __forceinline__ float colour_dist(float4 f, float l, float a, float b) {
+    float dl = f.x - l;
+    float da = f.y - a;
+    float db = f.z - b;
+    return (dl * dl + da * da) + db * db;
+}
+
+__device__ __forceinline__ long long to_fixed(float v) {
+    return (long long)rintf(v * kFixScaleF);
+}
+
+// Accumulates the samples i = 1 .. n-1 of the path from the pixel at linear
+// index `idx` toward (dx, dy): on major-axis step i the minor offset is
+// floor((2 i |d_minor| + n) / (2 n)), kept incrementally as a remainder.
+// stepx / stepy are the index strides of one pixel in x / y.
+__device__ __forceinline__ void walk_path(const float4* __restrict__ base, int idx, int stepx,
+                                          int stepy, int dx, int dy, float l, float a, float b,
+                                          float& sc, float& sw) {
+    const int adx = dx < 0 ? -dx : dx;
+    const int ady = dy < 0 ? -dy : dy;
+    const bool xmaj = adx >= ady;
+    const int n = xmaj ? adx : ady;
+    const int am = xmaj ? ady : adx;
+    const int sx = dx < 0 ? -stepx : stepx;
+    const int sy = dy < 0 ? -stepy : stepy;
+    const int smaj = xmaj ? sx : sy;
+    const int sdiag = smaj + (xmaj ? sy : sx);
+    const int two_n = 2 * n;
+    const int inc = 2 * am;
+    int rem = n;
+    for (int i = 1; i < n; ++i) {
+        rem += inc;
+        const bool step = rem >= two_n;
+        rem -= step ? two_n : 0;
+        idx += step ? sdiag : smaj;
+        const float4 f = base[idx];
+        const float dl = f.x - l;
+        const float da = f.y - a;
+        const float db = f.z - b;
+        const float dc = (dl * dl + da * da) + db * db;
+        sc = sc + dc;
+        sw = sw + f.w;
+    }
+}
+
+template <int WG, bool ACCUM>
+__device__ __forceinline__ void process_cell(const Img& im, int cell,
+                                             const float4* __restrict__ packed,
+                                             const float* __restrict__ centres,
+                                             const int* __restrict__ endpoints,
+                                             int* __restrict__ labels,
+                                             long long* __restrict__ acc, float lambda, int cap,
+                                             float4* lds, CellShared& sh) {
+    const int tid = threadIdx.x;
+    const int W = im.W, H = im.H, nx = im.nx, ny = im.ny;
+    const int ci = cell / nx, cj = cell - ci * nx;
+    const int x0 = cell_lo(cj, W, nx), x1 = cell_lo(cj + 1, W, nx);
+    const int y0 = cell_lo(ci, H, ny), y1 = cell_lo(ci + 1, H, ny);
+    const float4* __restrict__ img = packed + im.pix;
+
+    if (tid < 9) {
+        Cand c;
+        const int ii = ci + tid / 3 - 1, jj = cj + tid % 3 - 1;
+        c.staged = 0;
+        if (ii >= 0 && ii < ny && jj >= 0 && jj < nx) {
+            const int k = ii * nx + jj;
+            const float* ck = centres + 5LL * (im.sp + k);
+            c.k = k;
+            c.l = ck[0]; c.a = ck[1]; c.b = ck[2]; c.x = ck[3]; c.y = ck[4];
+            // endpoints outside the image are clamped into it
+            c.cx = min(max(endpoints[2LL * (im.sp + k)], 0), W - 1);
+            c.cy = min(max(endpoints[2LL * (im.sp + k) + 1], 0), H - 1);
+            const float4 fc = img[(long long)c.cy * W + c.cx];
+            c.dcc = colour_dist(fc, c.l, c.a, c.b);
+            c.wc = fc.w;
+        } else {
+            c.k = -1;
+            c.l = c.a = c.b = c.x = c.y = 0.0f;
+            c.cx = c.cy = 0;
+            c.dcc = c.wc = 0.0f;
+        }
+        sh.cand[tid] = c;
+    }
+    if (ACCUM) {
+        for (int t = tid; t < 54; t += WG) (&sh.bins[0][0])[t] = 0ULL;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        // Greedy LDS rectangle: the cell, grown by each candidate endpoint
+        // that keeps it within the budget.  Candidates left out walk their
+        // paths from global memory instead.
+        int rx0 = x0, rx1 = x1, ry0 = y0, ry1 = y1;
+        const bool fits = (long long)(x1 - x0) * (y1 - y0) <= cap;
+        if (fits) {
+            for (int j = 0; j < 9; ++j) {
+                if (sh.cand[j].k < 0) continue;
+                const int cx = sh.cand[j].cx, cy = sh.cand[j].cy;
+                const int ax0 = min(rx0, cx), ax1 = max(rx1, cx + 1);
+                const int ay0 = min(ry0, cy), ay1 = max(ry1, cy + 1);
+                if ((long long)(ax1 - ax0) * (ay1 - ay0) <= cap) {
+                    rx0 = ax0; rx1 = ax1; ry0 = ay0; ry1 = ay1;
+                    sh.cand[j].staged = 1;
+                }
+            }
+            sh.rx0 = rx0; sh.ry0 = ry0; sh.rw = rx1 - rx0; sh.rh = ry1 - ry0;
+        } else {
+            sh.rx0 = x0; sh.ry0 = y0; sh.rw = 0; sh.rh = 0;
+        }
+    }
+    __syncthreads();
+    const int rx0 = sh.rx0, ry0 = sh.ry0, rw = sh.rw;
+    const int area = rw * sh.rh;
+    for (int e = tid; e < area; e += WG) {
+        const int r = e / rw;
+        const int c = e - r * rw;
+        lds[e] = img[(long long)(ry0 + r) * W + rx0 + c];
+    }
+    __syncthreads();
+
+    // Pixels of the cell in 8-wide column strips, serpentine (down, up, ...),
+    // 64 consecutive pixels per wave: compact 8x8 blocks, so the lanes of a
+    // wave walk paths of similar length.
+    const int cw = x1 - x0, ch = y1 - y0;
+    const int P = cw * ch;
+    const int nfull = cw >> 3, wr = cw & 7;
+    const int fullpx = nfull * 8 * ch;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int nchunks = (P + 63) >> 6;
+    const float oml = 1.0f - lambda;
+    const float gamma = im.gamma, spw = im.spw;
+    for (int chunk = wave; chunk < nchunks; chunk += WG / 64) {
+        const int t = chunk * 64 + lane;
+        if (t >= P) continue;
+        int s, row, col;
+        if (t < fullpx) {
+            const int per = 8 * ch;
+            s = t / per;
+            const int r = t - s * per;
+            row = r >> 3;
+            col = 8 * s + (r & 7);
+        } else {
+            s = nfull;
+            const int r = t - fullpx;
+            row = r / wr;
+            col = 8 * nfull + (r - row * wr);
+        }
+        const int y = y0 + ((s & 1) ? (ch - 1 - row) : row);
+        const int x = x0 + col;
+        const int p = y * W + x;
+        const float4 fp = img[p];
+        const int lidx = (y - ry0) * rw + (x - rx0);
+        float best = INFINITY;
+        int bestj = -1;
+#pragma unroll 1
+        for (int j = 0; j < 9; ++j) {
+            const int k = sh.cand[j].k;
+            if (k < 0) continue;
+            const float l = sh.cand[j].l, a = sh.cand[j].a, b = sh.cand[j].b;
+            const int dx = sh.cand[j].cx - x, dy = sh.cand[j].cy - y;
+            const float dcp = colour_dist(fp, l, a, b);
+            float sc = dcp;      // sample i = 0 is p itself
+            float sw = fp.w;
+            if (sh.cand[j].staged)
+                walk_path(lds, lidx, 1, rw, dx, dy, l, a, b, sc, sw);
+            else
+                walk_path(img, p, 1, W, dx, dy, l, a, b, sc, sw);
+            const int adx = dx < 0 ? -dx : dx, ady = dy < 0 ? -dy : dy;
+            const int n = adx > ady ? adx : ady;
+            if (n > 0) {         // sample i = n is the endpoint
+                sc = sc + sh.cand[j].dcc;
+                sw = sw + sh.cand[j].wc;
+            }
+            const float np = (float)(n + 1);
+            const float A = lambda * dcp + oml * (sc / np);      // Eq. (1)
+            const float B = 1.0f + gamma * (sw / np);            // Eq. (2)
+            const float ex = (float)x - sh.cand[j].x;
+            const float ey = (float)y - sh.cand[j].y;
+            const float ds = ex * ex + ey * ey;
+            const float D = A * B + ds * spw;                    // Eq. (3)
+            if (D < best) {
+                best = D;
+                bestj = j;
+            }
+        }
+        if (bestj < 0) bestj = 4;   // only reachable with non-finite input
+        labels[im.pix + p] = sh.cand[bestj].k;
+        if (ACCUM) {
+            unsigned long long* bin = sh.bins[bestj];
+            atomicAdd(bin + 0, 1ULL);
+            atomicAdd(bin + 1, (unsigned long long)x);
+            atomicAdd(bin + 2, (unsigned long long)y);
+            atomicAdd(bin + 3, (unsigned long long)to_fixed(fp.x));
+            atomicAdd(bin + 4, (unsigned long long)to_fixed(fp.y));
+            atomicAdd(bin + 5, (unsigned long long)to_fixed(fp.z));
+        }
+    }
+    if (ACCUM) {
+        __syncthreads();
+        if (tid < 54) {
+            const int j = tid / 6, v = tid - 6 * (tid / 6);
+            const int k = sh.cand[j].k;
+            if (k >= 0 && sh.bins[j][0] != 0ULL)
+                atomicAdd((unsigned long long*)(acc + kAccStride * (long long)(im.sp + k) + v),
+                          sh.bins[j][v]);
+        }
+    }
+    __syncthreads();   // shared state is reused by the next cell of a persistent workgroup
+}
+
+// Workgroup index -> grid cell.  Workgroups are dispatched round-robin over
+// the 8 XCDs; give each XCD a contiguous run of cells so that neighbouring
+// cells, which stage overlapping halos, share an L2.
+__device__ __forceinline__ int xcd_remap(int b, int G) {
+    const int q = G >> 3, rem = G & 7;
+    const int x = b & 7, slot = b >> 3;
+    return x < rem ? x * (q + 1) + slot : rem * (q + 1) + (x - rem) * q + slot;
+}
+
+template <int WG, bool ACCUM>
+__global__ __launch_bounds__(WG) void k_assign(Img im, const float4* __restrict__ packed,
+                                               const float* __restrict__ centres,
+                                               const int* __restrict__ endpoints,
+                                               int* __restrict__ labels,
+                                               long long* __restrict__ acc, int* ctrl,
+                                               float lambda, int cap) {
+    extern __shared__ float4 lds_dyn[];
+    __shared__ CellShared sh;
+    if (ACCUM && blockIdx.x == 0 && threadIdx.x == 0) ctrl[kCtrlProjCount] = 0;
+    const int cell = xcd_remap(blockIdx.x, gridDim.x);
+    process_cell<WG, ACCUM>(im, cell, packed, centres, endpoints, labels, acc, lambda, cap,
+                            lds_dyn, sh);
+}
+
+__device__ __forceinline__ int find_image(const int* start, int n, int v) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (start[mid] <= v) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int WG>
+__global__ __launch_bounds__(WG) void k_assign_persistent(const Img* __restrict__ imgs,
+                                                          const int* __restrict__ cell_start,
+                                                          int n_img, int total,
+                                                          const float4* __restrict__ packed,
+                                                          const float* __restrict__ centres,
+                                                          const int* __restrict__ endpoints,
+                                                          int* __restrict__ labels,
+                                                          long long* __restrict__ acc, int* ctrl,
+                                                          float lambda, int cap) {
+    extern __shared__ float4 lds_dyn[];
+    __shared__ CellShared sh;
+    __shared__ int item;
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctrl[kCtrlProjCount] = 0;
+    for (;;) {
+        if (threadIdx.x == 0) item = atomicAdd(&ctrl[kCtrlQueue], 1);
+        __syncthreads();
+        const int it = item;
+        __syncthreads();
+        if (it >= total) break;
+        const int i = find_image(cell_start, n_img, it);
+        const Img im = imgs[i];
+        process_cell<WG, true>(im, it - cell_start[i], packed, centres, endpoints, labels, acc,
+                               lambda, cap, lds_dyn, sh);
+    }
+}
+
+// ---------------------------------------------------------------- prepare
+
+__global__ void k_prepare(long long n, const float* __restrict__ lab,
+                          const float* __restrict__ contour, float sigma,
+                          float4* __restrict__ packed) {
+    const double s2 = (double)sigma * (double)sigma;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const double c = (double)contour[i];
+        const float w = (float)(1.0 - exp(-(c * c) / s2));
+        packed[i] = make_float4(lab[3 * i], lab[3 * i + 1], lab[3 * i + 2], w);
+    }
+}
+
+__global__ void k_clear(long long* __restrict__ p, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+// ---------------------------------------------------------------- init
+
+template <int WG>
+__device__ __forceinline__ void init_cell(const Img& im, int cell, const float4* __restrict__ packed,
+                                          int* __restrict__ labels, long long* __restrict__ acc) {
+    __shared__ long long red[6][WG];
+    const int tid = threadIdx.x;
+    const int ci = cell / im.nx, cj = cell - ci * im.nx;
+    const int x0 = cell_lo(cj, im.W, im.nx), x1 = cell_lo(cj + 1, im.W, im.nx);
+    const int y0 = cell_lo(ci, im.H, im.ny), y1 = cell_lo(ci + 1, im.H, im.ny);
+    const int cw = x1 - x0, P = cw * (y1 - y0);
+    long long s[6] = {0, 0, 0, 0, 0, 0};
+    for (int t = tid; t < P; t += WG) {
+        const int r = t / cw;
+        const int x = x0 + (t - r * cw), y = y0 + r;
+        const long long p = (long long)y * im.W + x;
+        const float4 f = packed[im.pix + p];
+        labels[im.pix + p] = cell;
+        s[0] += 1; s[1] += x; s[2] += y;
+        s[3] += to_fixed(f.x); s[4] += to_fixed(f.y); s[5] += to_fixed(f.z);
+    }
+    for (int v = 0; v < 6; ++v) red[v][tid] = s[v];
+    __syncthreads();
+    for (int h = WG / 2; h > 0; h >>= 1) {
+        if (tid < h)
+            for (int v = 0; v < 6; ++v) red[v][tid] += red[v][tid + h];
+        __syncthreads();
+    }
+    if (tid < 6) acc[kAccStride * (long long)(im.sp + cell) + tid] = red[tid][0];
+    __syncthreads();
+}
+
+template <int WG>
+__global__ __launch_bounds__(WG) void k_init_cells(Img im, const float4* __restrict__ packed,
+                                                   int* __restrict__ labels,
+                                                   long long* __restrict__ acc) {
+    init_cell<WG>(im, blockIdx.x, packed, labels, acc);
+}
+
+template <int WG>
+__global__ __launch_bounds__(WG) void k_init_cells_batched(const Img* __restrict__ imgs,
+                                                           const int* __restrict__ cell_start,
+                                                           int n_img, const float4* packed,
+                                                           int* labels, long long* acc) {
+    const int i = find_image(cell_start, n_img, blockIdx.x);
+    init_cell<WG>(imgs[i], blockIdx.x - cell_start[i], packed, labels, acc);
+}
+
+// ---------------------------------------------------------------- update from labels
+
+template <int WG>
+__global__ __launch_bounds__(WG) void k_accumulate(Img im, const float* __restrict__ lab,
+                                                   const int* __restrict__ labels,
+                                                   long long* __restrict__ acc) {
+    __shared__ unsigned long long bins[9][6];
+    const int tid = threadIdx.x;
+    const int cell = blockIdx.x;
+    const int ci = cell / im.nx, cj = cell - ci * im.nx;
+    const int x0 = cell_lo(cj, im.W, im.nx), x1 = cell_lo(cj + 1, im.W, im.nx);
+    const int y0 = cell_lo(ci, im.H, im.ny), y1 = cell_lo(ci + 1, im.H, im.ny);
+    const int K = im.nx * im.ny;
+    for (int t = tid; t < 54; t += WG) (&bins[0][0])[t] = 0ULL;
+    __syncthreads();
+    const int cw = x1 - x0, P = cw * (y1 - y0);
+    for (int t = tid; t < P; t += WG) {
+        const int r = t / cw;
+        const int x = x0 + (t - r * cw), y = y0 + r;
+        const long long p = (long long)y * im.W + x;
+        const int k = labels[p];
+        if (k < 0 || k >= K) continue;
+        unsigned long long v[6] = {1ULL, (unsigned long long)x, (unsigned long long)y,
+                                   (unsigned long long)to_fixed(lab[3 * p]),
+                                   (unsigned long long)to_fixed(lab[3 * p + 1]),
+                                   (unsigned long long)to_fixed(lab[3 * p + 2])};
+        const int ki = k / im.nx, kj = k - ki * im.nx;
+        const int di = ki - ci + 1, dj = kj - cj + 1;
+        if (di >= 0 && di < 3 && dj >= 0 && dj < 3) {
+            unsigned long long* bin = bins[di * 3 + dj];
+            for (int q = 0; q < 6; ++q) atomicAdd(bin + q, v[q]);
+        } else {
+            for (int q = 0; q < 6; ++q)
+                atomicAdd((unsigned long long*)(acc + kAccStride * (long long)k + q), v[q]);
+        }
+    }
+    __syncthreads();
+    if (tid < 54) {
+        const int j = tid / 6, q = tid - 6 * (tid / 6);
+        const int ii = ci + j / 3 - 1, jj = cj + j % 3 - 1;
+        if (ii >= 0 && ii < im.ny && jj >= 0 && jj < im.nx && bins[j][0] != 0ULL)
+            atomicAdd((unsigned long long*)(acc + kAccStride * (long long)(ii * im.nx + jj) + q),
+                      bins[j][q]);
+    }
+}
+
+// ---------------------------------------------------------------- finalize
+
+__device__ __forceinline__ int round_coord(float v, int hi) {
+    int e = (int)floorf(v + 0.5f);
+    e = e < 0 ? 0 : e;
+    return e > hi ? hi : e;
+}
+
+__device__ __forceinline__ void finalize_one(const Img& im, int k, float* __restrict__ centres,
+                                             int* __restrict__ endpoints,
+                                             int* __restrict__ counts,
+                                             long long* __restrict__ acc,
+                                             const int* __restrict__ labels, int* ctrl,
+                                             int* plist, bool project) {
+    long long* a = acc + kAccStride * (long long)(im.sp + k);
+    const long long cnt = a[0];
+    if (cnt > 0) {
+        const double n = (double)cnt;
+        float* c = centres + 5LL * (im.sp + k);
+        c[0] = (float)(((double)a[3] / n) * kFixInv);
+        c[1] = (float)(((double)a[4] / n) * kFixInv);
+        c[2] = (float)(((double)a[5] / n) * kFixInv);
+        const float xk = (float)((double)a[1] / n);
+        const float yk = (float)((double)a[2] / n);
+        c[3] = xk;
+        c[4] = yk;
+        const int ex = round_coord(xk, im.W - 1), ey = round_coord(yk, im.H - 1);
+        if (!project || labels[im.pix + (long long)ey * im.W + ex] == k) {
+            endpoints[2LL * (im.sp + k)] = ex;
+            endpoints[2LL * (im.sp + k) + 1] = ey;
+        } else {
+            const int slot = atomicAdd(&ctrl[kCtrlProjCount], 1);
+            plist[slot] = im.sp + k;
+        }
+    }
+    counts[im.sp + k] = (int)cnt;
+    for (int v = 0; v < 6; ++v) a[v] = 0;
+}
+
+__global__ void k_finalize(Img im, float* centres, int* endpoints, int* counts, long long* acc,
+                           const int* labels, int* ctrl, int* plist, int project) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < im.nx * im.ny)
+        finalize_one(im, k, centres, endpoints, counts, acc, labels, ctrl, plist, project != 0);
+}
+
+__global__ void k_finalize_batched(const Img* __restrict__ imgs, const int* __restrict__ sp_start,
+                                   int n_img, int total, float* centres, int* endpoints,
+                                   int* counts, long long* acc, const int* labels, int* ctrl,
+                                   int* plist, int project) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g == 0) ctrl[kCtrlQueue] = 0;   // the next persistent assignment starts at item 0
+    if (g >= total) return;
+    const int i = find_image(sp_start, n_img, g);
+    const Img im = imgs[i];
+    finalize_one(im, g - im.sp, centres, endpoints, counts, acc, labels, ctrl, plist,
+                 project != 0);
+}
+
+// ---------------------------------------------------------------- projection
+
+template <int WG>
+__device__ __forceinline__ void block_min_sum(unsigned long long& key, int& cnt) {
+    __shared__ unsigned long long rk[WG];
+    __shared__ int rc[WG];
+    const int tid = threadIdx.x;
+    rk[tid] = key;
+    rc[tid] = cnt;
+    __syncthreads();
+    for (int h = WG / 2; h > 0; h >>= 1) {
+        if (tid < h) {
+            rk[tid] = rk[tid] < rk[tid + h] ? rk[tid] : rk[tid + h];
+            rc[tid] += rc[tid + h];
+        }
+        __syncthreads();
+    }
+    key = rk[0];
+    cnt = rc[0];
+    __syncthreads();
+}
+
+// Squared FP32 distance to (xk, yk) in the high word, raster index in the
+// low word: the minimum key is the nearest pixel, ties to the lowest index.
+__device__ __forceinline__ unsigned long long proj_key(int x, int y, int W, float xk, float yk) {
+    const float dx = (float)x - xk;
+    const float dy = (float)y - yk;
+    const float d = dx * dx + dy * dy;
+    return ((unsigned long long)__float_as_uint(d) << 32) | (unsigned)(y * W + x);
+}
+
+template <int WG>
+__device__ void project_one(const Img& im, int k, const float* __restrict__ centres,
+                            const int* __restrict__ counts, const int* __restrict__ labels,
+                            int* __restrict__ endpoints) {
+    const int tid = threadIdx.x;
+    const int W = im.W, H = im.H;
+    const int* lb = labels + im.pix;
+    const float xk = centres[5LL * (im.sp + k) + 3];
+    const float yk = centres[5LL * (im.sp + k) + 4];
+    const int ci = k / im.nx, cj = k - ci * im.nx;
+    const int X0 = cell_lo(max(cj - 1, 0), W, im.nx), X1 = cell_lo(min(cj + 2, im.nx), W, im.nx);
+    const int Y0 = cell_lo(max(ci - 1, 0), H, im.ny), Y1 = cell_lo(min(ci + 2, im.ny), H, im.ny);
+    const int bw = X1 - X0, area = bw * (Y1 - Y0);
+    unsigned long long best = ~0ULL;
+    int found = 0;
+    for (int e = tid; e < area; e += WG) {
+        const int r = e / bw;
+        const int x = X0 + (e - r * bw), y = Y0 + r;
+        if (lb[(long long)y * W + x] == k) {
+            ++found;
+            const unsigned long long key = proj_key(x, y, W, xk, yk);
+            best = key < best ? key : best;
+        }
+    }
+    block_min_sum<WG>(best, found);
+    if (found < counts[im.sp + k]) {
+        // members outside the 3x3 cell block (labels not produced by the
+        // assignment): scan the whole image
+        best = ~0ULL;
+        found = 0;
+        for (long long p = tid; p < (long long)W * H; p += WG) {
+            if (lb[p] == k) {
+                const unsigned long long key = proj_key((int)(p % W), (int)(p / W), W, xk, yk);
+                best = key < best ? key : best;
+            }
+        }
+        block_min_sum<WG>(best, found);
+    }
+    if (tid == 0 && best != ~0ULL) {
+        const unsigned idx = (unsigned)(best & 0xffffffffULL);
+        endpoints[2LL * (im.sp + k)] = (int)(idx % (unsigned)W);
+        endpoints[2LL * (im.sp + k) + 1] = (int)(idx / (unsigned)W);
+    }
+}
+
+template <int WG>
+__global__ __launch_bounds__(WG) void k_project(Img im, const float* centres, const int* counts,
+                                                const int* labels, int* endpoints,
+                                                const int* ctrl, const int* plist) {
+    const int n = ctrl[kCtrlProjCount];
+    for (int i = blockIdx.x; i < n; i += gridDim.x)
+        project_one<WG>(im, plist[i] - im.sp, centres, counts, labels, endpoints);
+}
+
+template <int WG>
+__global__ __launch_bounds__(WG) void k_project_batched(const Img* __restrict__ imgs,
+                                                        const int* __restrict__ sp_start,
+                                                        int n_img, const float* centres,
+                                                        const int* counts, const int* labels,
+                                                        int* endpoints, const int* ctrl,
+                                                        const int* plist) {
+    const int n = ctrl[kCtrlProjCount];
+    for (int i = blockIdx.x; i < n; i += gridDim.x) {
+        const int g = plist[i];
+        const int ii = find_image(sp_start, n_img, g);
+        const Img im = imgs[ii];
+        project_one<WG>(im, g - im.sp, centres, counts, labels, endpoints);
+    }
+}
+
+// Small host tables (image descriptors) reach the device as kernel
+// arguments, so no host buffer has to outlive the call and the copy can be
+// captured into a graph.
+struct ByteChunk {
+    unsigned nbytes;
+    unsigned char data[3072];
+};
+
+__global__ void k_write_bytes(unsigned char* __restrict__ dst, ByteChunk c) {
+    for (unsigned i = threadIdx.x; i < c.nbytes; i += blockDim.x) dst[i] = c.data[i];
+}
+
+constexpr int kSmallWG = 256;
+constexpr int kProjectBlocks = 256;
+
+size_t dyn_lds(const Tuning& t) { return (size_t)t.lds_pixels * sizeof(float4); }
+
+template <typename K>
+void allow_lds(K kernel, size_t bytes) {
+    // Lift the dynamic-LDS limit to what the launch needs (gfx950: 160 KiB per CU).
+    static_cast<void>(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                          hipFuncAttributeMaxDynamicSharedMemorySize,
+                                          (int)bytes));
+    static_cast<void>(hipGetLastError());
+}
+
+}  // namespace
+
+int default_lds_pixels() { return 4800; }
+
+int launch_write_bytes(void* dst, const void* src, size_t n, hipStream_t s) {
+    const unsigned char* in = static_cast<const unsigned char*>(src);
+    unsigned char* out = static_cast<unsigned char*>(dst);
+    for (size_t off = 0; off < n; off += sizeof(ByteChunk::data)) {
+        ByteChunk c;
+        c.nbytes = (unsigned)std::min(n - off, sizeof(c.data));
+        std::copy(in + off, in + off + c.nbytes, c.data);
+        hipLaunchKernelGGL(k_write_bytes, dim3(1), dim3(256), 0, s, out + off, c);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+void lift_lds_limits() {
+    const size_t cap = 160 * 1024 - sizeof(CellShared) - 64;
+    allow_lds(k_assign<256, true>, cap);
+    allow_lds(k_assign<256, false>, cap);
+    allow_lds(k_assign<512, true>, cap);
+    allow_lds(k_assign<512, false>, cap);
+    allow_lds(k_assign_persistent<256>, cap);
+    allow_lds(k_assign_persistent<512>, cap);
+}
+
+int launch_prepare(long long n, const float* lab, const float* contour, float sigma,
+                   float4* packed, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const long long blocks = std::min<long long>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_prepare, dim3((unsigned)blocks), dim3(256), 0, s, n, lab, contour, sigma,
+                       packed);
+    return hipGetLastError();
+}
+
+int launch_clear(long long* p, long long n_words, hipStream_t s) {
+    if (n_words <= 0) return hipSuccess;
+    const long long blocks = std::min<long long>((n_words + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_clear, dim3((unsigned)blocks), dim3(256), 0, s, p, n_words);
+    return hipGetLastError();
+}
+
+int launch_init_cells(const Img& im, const float4* packed, int* labels, long long* acc,
+                      hipStream_t s) {
+    hipLaunchKernelGGL(k_init_cells<kSmallWG>, dim3(im.nx * im.ny), dim3(kSmallWG), 0, s, im,
+                       packed, labels, acc);
+    return hipGetLastError();
+}
+
+int launch_init_cells_batched(const Img* imgs, const int* cell_start, int n_img, int total_cells,
+                              const float4* packed, int* labels, long long* acc, hipStream_t s) {
+    hipLaunchKernelGGL(k_init_cells_batched<kSmallWG>, dim3(total_cells), dim3(kSmallWG), 0, s,
+                       imgs, cell_start, n_img, packed, labels, acc);
+    return hipGetLastError();
+}
+
+template <int WG, bool ACCUM>
+static int launch_assign_t(const Img& im, const float4* packed, const float* centres,
+                           const int* endpoints, int* labels, long long* acc, int* ctrl,
+                           float lambda, const Tuning& t, hipStream_t s) {
+    const size_t bytes = dyn_lds(t);
+    hipLaunchKernelGGL((k_assign<WG, ACCUM>), dim3(im.nx * im.ny), dim3(WG), bytes, s, im, packed,
+                       centres, endpoints, labels, acc, ctrl, lambda, t.lds_pixels);
+    return hipGetLastError();
+}
+
+int launch_assign(const Img& im, const float4* packed, const float* centres,
+                  const int* endpoints, int* labels, long long* acc, int* ctrl, float lambda,
+                  bool accumulate, const Tuning& t, hipStream_t s) {
+    if (t.wg == 512)
+        return accumulate ? launch_assign_t<512, true>(im, packed, centres, endpoints, labels, acc,
+                                                       ctrl, lambda, t, s)
+                          : launch_assign_t<512, false>(im, packed, centres, endpoints, labels,
+                                                        acc, ctrl, lambda, t, s);
+    return accumulate ? launch_assign_t<256, true>(im, packed, centres, endpoints, labels, acc,
+                                                   ctrl, lambda, t, s)
+                      : launch_assign_t<256, false>(im, packed, centres, endpoints, labels, acc,
+                                                    ctrl, lambda, t, s);
+}
+
+template <int WG>
+static int launch_persistent_t(const Img* imgs, const int* cell_start, int n_img, int total,
+                               const float4* packed, const float* centres, const int* endpoints,
+                               int* labels, long long* acc, int* ctrl, float lambda,
+                               const Tuning& t, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_assign_persistent<WG>, dim3(grid), dim3(WG), dyn_lds(t), s, imgs,
+                       cell_start, n_img, total, packed, centres, endpoints, labels, acc, ctrl,
+                       lambda, t.lds_pixels);
+    return hipGetLastError();
+}
+
+int launch_assign_persistent(const Img* imgs, const int* cell_start, int n_img, int total_cells,
+                             const float4* packed, const float* centres, const int* endpoints,
+                             int* labels, long long* acc, int* ctrl, float lambda,
+                             const Tuning& t, int grid, hipStream_t s) {
+    if (t.wg == 512)
+        return launch_persistent_t<512>(imgs, cell_start, n_img, total_cells, packed, centres,
+                                        endpoints, labels, acc, ctrl, lambda, t, grid, s);
+    return launch_persistent_t<256>(imgs, cell_start, n_img, total_cells, packed, centres,
+                                    endpoints, labels, acc, ctrl, lambda, t, grid, s);
+}
+
+int persistent_grid(const Tuning& t) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return -1;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return -1;
+    hipError_t e;
+    if (t.wg == 512)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_assign_persistent<512>, 512,
+                                                         dyn_lds(t));
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_assign_persistent<256>, 256,
+                                                         dyn_lds(t));
+    if (e != hipSuccess || per < 1) per = 1;
+    return cus * per;
+}
+
+int launch_accumulate(const Img& im, const float* lab, const int* labels, long long* acc,
+                      hipStream_t s) {
+    hipLaunchKernelGGL(k_accumulate<kSmallWG>, dim3(im.nx * im.ny), dim3(kSmallWG), 0, s, im, lab,
+                       labels, acc);
+    return hipGetLastError();
+}
+
+int launch_finalize(const Img& im, float* centres, int* endpoints, int* counts, long long* acc,
+                    const int* labels, int* ctrl, int* plist, bool project, hipStream_t s) {
+    const int K = im.nx * im.ny;
+    hipLaunchKernelGGL(k_finalize, dim3((K + 255) / 256), dim3(256), 0, s, im, centres,
+                       endpoints, counts, acc, labels, ctrl, plist, project ? 1 : 0);
+    return hipGetLastError();
+}
+
+int launch_finalize_batched(const Img* imgs, const int* sp_start, int n_img, int total_sp,
+                            float* centres, int* endpoints, int* counts, long long* acc,
+                            const int* labels, int* ctrl, int* plist, bool project,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize_batched, dim3((total_sp + 255) / 256), dim3(256), 0, s, imgs,
+                       sp_start, n_img, total_sp, centres, endpoints, counts, acc, labels, ctrl,
+                       plist, project ? 1 : 0);
+    return hipGetLastError();
+}
+
+int launch_project(const Img& im, const float* centres, const int* counts, const int* labels,
+                   int* endpoints, const int* ctrl, const int* plist, hipStream_t s) {
+    hipLaunchKernelGGL(k_project<kSmallWG>, dim3(kProjectBlocks), dim3(kSmallWG), 0, s, im,
+                       centres, counts, labels, endpoints, ctrl, plist);
+    return hipGetLastError();
+}
+
+int launch_project_batched(const Img* imgs, const int* sp_start, int n_img, const float* centres,
+                           const int* counts, const int* labels, int* endpoints,
+                           const int* ctrl, const int* plist, hipStream_t s) {
+    hipLaunchKernelGGL(k_project_batched<kSmallWG>, dim3(kProjectBlocks), dim3(kSmallWG), 0, s,
+                       imgs, sp_start, n_img, centres, counts, labels, endpoints, ctrl, plist);
+    return hipGetLastError();
+}
+
+}  // namespace scalp

@@ -1,0 +1,213 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Bars:
+  * packed w map, grid initialisation, one assignment pass from identical
+    centres, and the update from identical labels: bit-exact;
+  * whole runs: bit-exact against the oracle's fixed-point-mean mode (the
+    same rounding of the mean as the GPU's order-free integer sums), and at
+    least 99.9 % label agreement with barycenters within 1e-5 relative
+    against the oracle's plain FP64 mean.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from paper_1903_07149_amd import synth
+from gpu_util import dev, host, needs_gpu, perturbed_state, say, torch
+
+pytestmark = [pytest.mark.gpu, needs_gpu]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _threads(orc):
+    orc.set_threads(min(16, os.cpu_count() or 1))
+
+
+def _image(W, H, seed, regions=None):
+    if regions is None:
+        regions = max(2, (W * H) // 4000)
+    return synth.make_image(W, H, regions, 10.0, seed)
+
+
+# (W, H, k): several tiles and ragged cells, thin and degenerate shapes,
+# one superpixel per pixel, and cells too large for the LDS halo.
+SMALL = [(97, 61, 30), (256, 200, 100), (481, 321, 250), (37, 5, 7), (1, 1, 1), (1, 50, 5),
+         (50, 1, 5), (64, 64, 4096), (300, 200, 2), (129, 77, 1)]
+# tuning variants: default; LDS budget too small for any endpoint (cell only);
+# budget below one cell (every path from global memory); 512-thread workgroups
+TUNINGS = [dict(), dict(lds_pixels=900), dict(lds_pixels=1), dict(wg_size=512)]
+
+
+def _scalp(W, H, k, **kw):
+    from paper_1903_07149_amd.scalp import Scalp
+    return Scalp(W, H, k, **kw)
+
+
+@pytest.mark.parametrize("W,H,k", SMALL[:4])
+def test_prepare_packs_w_bit_exact(orc, W, H, k):
+    img = _image(W, H, 1)
+    con = img.contour.copy()
+    con.ravel()[::7] = np.random.default_rng(0).random(con.size)[::7]   # many distinct values
+    s = _scalp(W, H, k)
+    say("prepare", W, H, k)
+    s.prepare(dev(img.lab), dev(con))
+    packed = host(s.workspace[: 16 * W * H].view(torch.float32)).reshape(H, W, 4)
+    assert (packed[..., :3] == img.lab).all()
+    w = orc.wmap(con)
+    mism = int((packed[..., 3] != w).sum())
+    assert mism == 0, f"{mism} w values differ"
+
+
+@pytest.mark.parametrize("W,H,k", SMALL)
+def test_init_grid_bit_exact(orc, W, H, k):
+    img = _image(W, H, 2)
+    s = _scalp(W, H, k)
+    g = orc.grid(W, H, k)
+    say("init_grid", W, H, k)
+    c, e, l = s.init_grid(dev(img.lab), dev(img.contour))
+    oc, oe, ol = orc.init_grid(g, img.lab, mode=orc.MEAN_FIXED)
+    assert (host(l) == ol).all()
+    assert (host(c) == oc).all()
+    assert (host(e) == oe).all()
+
+
+@pytest.mark.parametrize("tune", range(len(TUNINGS)))
+@pytest.mark.parametrize("W,H,k", SMALL)
+def test_assign_bit_exact(orc, W, H, k, tune):
+    img = _image(W, H, 3)
+    g = orc.grid(W, H, k)
+    c, e = perturbed_state(orc, g, img.lab, seed=W * 7 + H, jitter=0.3 * g.r + 1)
+    s = _scalp(W, H, k, **TUNINGS[tune])
+    say("assign", W, H, k, TUNINGS[tune])
+    lbl = host(s.assign(dev(img.lab), dev(img.contour), dev(c), dev(e)))
+    ol, _, _ = orc.assign(g, img.lab, orc.wmap(img.contour), c, e)
+    assert (lbl == ol).all(), f"{int((lbl != ol).sum())} labels differ"
+
+
+@pytest.mark.parametrize("lam,gamma", [(1.0, 0.0), (0.0, 0.0), (0.3, 7.0)])
+def test_assign_parameters(orc, lam, gamma):
+    W, H, k = 200, 150, 60
+    img = _image(W, H, 4)
+    g = orc.grid(W, H, k)
+    c, e = perturbed_state(orc, g, img.lab, seed=5, jitter=4)
+    s = _scalp(W, H, k, lam=lam, gamma=gamma, m=7.0)
+    say("assign params", lam, gamma)
+    lbl = host(s.assign(dev(img.lab), dev(img.contour), dev(c), dev(e)))
+    ol, _, _ = orc.assign(g, img.lab, orc.wmap(img.contour), c, e, lam=lam, gamma=gamma,
+                          spw=orc.spatial_weight(g, 7.0))
+    assert (lbl == ol).all()
+
+
+@pytest.mark.parametrize("W,H,k", [(97, 61, 30), (481, 321, 250), (64, 64, 4096), (300, 200, 2)])
+def test_update_bit_exact(orc, W, H, k):
+    img = _image(W, H, 5)
+    g = orc.grid(W, H, k)
+    c, e = perturbed_state(orc, g, img.lab, seed=11, jitter=0.4 * g.r + 1)
+    labels, _, _ = orc.assign(g, img.lab, orc.wmap(img.contour), c, e)
+    s = _scalp(W, H, k)
+    say("update", W, H, k)
+    nc, ne, cnt = (host(t) for t in s.update(dev(img.lab), dev(labels), dev(c), dev(e)))
+    oc, ocnt = orc.update(g, img.lab, labels, c, mode=orc.MEAN_FIXED)
+    oe, _ = orc.project(g, labels, oc, ocnt, e)
+    assert (cnt == ocnt).all()
+    assert (nc == oc).all()
+    assert (ne == oe).all()
+    pc, _ = orc.update(g, img.lab, labels, c, mode=orc.MEAN_PLAIN)
+    nz = ocnt > 0
+    assert np.allclose(nc[nz], pc[nz], rtol=1e-5, atol=1e-5)
+
+
+def test_update_arbitrary_labels(orc):
+    """Labels that are not grid neighbours (global-atomic path, full-image projection scan)."""
+    W, H, k = 120, 90, 24
+    img = _image(W, H, 6)
+    g = orc.grid(W, H, k)
+    rng = np.random.default_rng(3)
+    labels = rng.integers(0, g.num_sp, (H, W)).astype(np.int32)
+    labels[labels == 3] = 4
+    labels[:5, :5] = -1                             # ignored
+    c, e, _ = orc.init_grid(g, img.lab, mode=orc.MEAN_FIXED)
+    s = _scalp(W, H, k)
+    say("update arbitrary labels")
+    nc, ne, cnt = (host(t) for t in s.update(dev(img.lab), dev(labels), dev(c), dev(e)))
+    oc, ocnt = orc.update(g, img.lab, labels, c, mode=orc.MEAN_FIXED)
+    oe, moved = orc.project(g, labels, oc, ocnt, e)
+    assert moved > 0
+    assert (cnt == ocnt).all() and (nc == oc).all() and (ne == oe).all()
+
+
+def _compare_runs(orc, img, k, iters, **kw):
+    H, W = img.contour.shape
+    s = _scalp(W, H, k, **kw)
+    say("run", W, H, k, iters, kw)
+    r = s.run(dev(img.lab), dev(img.contour), iterations=iters)
+    lbl, c, e, n = host(r.labels), host(r.centers), host(r.endpoints), host(r.counts)
+    fixed = orc.run(img.lab, img.contour, k, iterations=iters, mode=orc.MEAN_FIXED)
+    assert (lbl == fixed.labels).all(), f"{int((lbl != fixed.labels).sum())} labels differ"
+    assert (c == fixed.centres).all() and (e == fixed.endpoints).all()
+    assert (n == fixed.counts).all()
+    plain = orc.run(img.lab, img.contour, k, iterations=iters, mode=orc.MEAN_PLAIN)
+    agree = float((lbl == plain.labels).mean())
+    assert agree >= 0.999, agree
+    return agree
+
+
+@pytest.mark.parametrize("W,H,k", [(481, 321, 250), (97, 61, 30), (129, 77, 1), (64, 64, 4096)])
+def test_run_bit_exact_small(orc, W, H, k):
+    _compare_runs(orc, _image(W, H, 7), k, 10)
+
+
+def test_run_bsd_shape_workload(orc):
+    _compare_runs(orc, synth.workload_image(synth.BSD_SHAPE), 250, 10)
+
+
+def test_run_hd_workload(orc):
+    """The benchmark's workload (1920x1080, k = 2000, 10 iterations) in its launch config."""
+    _compare_runs(orc, synth.workload_image(synth.HD), synth.HD.k, synth.HD.iterations)
+
+
+def test_run_uhd_workload(orc):
+    _compare_runs(orc, synth.workload_image(synth.UHD), synth.UHD.k, synth.UHD.iterations)
+
+
+def test_graph_replays_match_eager(orc):
+    img = synth.workload_image(synth.BSD_SHAPE)
+    H, W = img.contour.shape
+    s = _scalp(W, H, 250)
+    lab, con = dev(img.lab), dev(img.contour)
+    say("graph replay")
+    ref = s.run(lab, con)
+    refs = [host(t) for t in (ref.labels, ref.centers, ref.endpoints, ref.counts)]
+    c, e, l = s.init_grid(lab, con)
+    n = torch.empty_like(ref.counts)
+    gr = s.graph(c, e, l, n)
+    for rep in range(3):
+        c0, e0, _ = s.init_grid(lab, con)          # eager work between replays
+        c.copy_(c0)
+        e.copy_(e0)
+        torch.cuda.synchronize()
+        gr.launch()
+        got = [host(t) for t in (l, c, e, n)]
+        for a, b in zip(got, refs):
+            assert (a == b).all(), rep
+    gr.close()
+
+
+def test_run_repeatable_and_resumable(orc):
+    img = _image(160, 120, 9)
+    s = _scalp(160, 120, 48)
+    lab, con = dev(img.lab), dev(img.contour)
+    say("repeat/resume")
+    a = s.run(lab, con, iterations=6)
+    b = s.run(lab, con, iterations=6)
+    for x, y in zip((a.labels, a.centers, a.endpoints), (b.labels, b.centers, b.endpoints)):
+        assert (host(x) == host(y)).all()
+    # 3 iterations, then 3 more from the saved state through a graph of the loop
+    h = s.run(lab, con, iterations=3)
+    c, e = h.centers.clone(), h.endpoints.clone()
+    l, n = torch.empty_like(h.labels), torch.empty_like(h.counts)
+    g3 = s.graph(c, e, l, n, iterations=3)
+    g3.launch()
+    assert (host(l) == host(a.labels)).all() and (host(c) == host(a.centers)).all()
+    g3.close()
