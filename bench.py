@@ -1,0 +1,291 @@
+#!/usr/bin/env python3
+"""Throughput of the SCALP clustering path on one MI355X.
+
+Headline: Mpixel-iterations/s of hard SCALP on the 1920x1080 synthetic
+Voronoi workload with k = 2000 and 10 iterations.  One step is one whole job
+from inputs resident in HBM: pack (l, a, b, w), grid initialisation, then
+10 x (fused assignment + update, finalize + Eq. (4) projection).
+
+Also reported on the same JSON line:
+  roofline      the fused assignment kernel (the dominant kernel): algorithmic
+                FP32 operations per launch / its average duration, measured with
+                HIP events around every launch inside the timed region, against
+                the FP32 VALU issue peak for non-fused, non-packed operations;
+  cpu_baseline  the plain C oracle timed on this host's cores on the same
+                workload;
+  extensions    the ragged 64-image batch in one persistent launch per
+                iteration (hipGraph), against the same images run one by one
+                through the single-image path, and soft SCALP forward+backward.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mpixel-iter/s (assign+update) 1080p K=2000; batched and soft fwd+bwd MP/s"
+
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz issue 39.3 T non-fused,
+# non-packed FP32 operations per second (the published 157.3 TFLOP/s counts a
+# packed FMA as 4 operations per lane slot).
+VALU_FP32_PEAK_TFLOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+HBM_PEAK_GBPS = 8000.0
+# LDS: 128 bytes per clock per CU (64 banks x 4 B is not assumed): 78.6 TB/s.
+LDS_PEAK_TBPS = 256 * 128 * 2.4e9 / 1e12
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "assign_hd_traffic.json")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1903_07149_amd", "csrc", "scalp_kernels.hip")
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def source_digest() -> str:
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extensions", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 512 MiB device copy (counter calibration)")
+    return ap.parse_args()
+
+
+def traffic_for(digest: str):
+    """HBM bytes per launch of the assignment kernel from the committed counter
+    summary, if it was taken on the current kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256_16") != digest:
+        return None
+    return t.get("bytes_per_launch")
+
+
+def bench_hard(torch, args):
+    from paper_1903_07149_amd import counts, synth
+    from paper_1903_07149_amd.scalp import Scalp
+
+    wl = synth.HD
+    img = synth.workload_image(wl)
+    H, W = img.contour.shape
+    s = Scalp(W, H, wl.k, iterations=wl.iterations)
+    lab = torch.from_numpy(img.lab).cuda()
+    con = torch.from_numpy(img.contour).cuda()
+    c, e, l, n = s.new_state()
+    iters = wl.iterations
+
+    def step(evs=None):
+        s.init_grid(lab, con, out=(c, e, l))
+        for it in range(iters):
+            if evs is not None:
+                evs[it][0].record()
+            s.assign_accumulate(c, e, l)
+            if evs is not None:
+                evs[it][1].record()
+            s.finalize(l, c, e, n)
+
+    # algorithmic work of every iteration (the run is deterministic)
+    s.init_grid(lab, con, out=(c, e, l))
+    work = []
+    for it in range(iters):
+        torch.cuda.synchronize()
+        work.append(counts.pass_work(W, H, s.grid.nx, s.grid.ny, e.cpu().numpy()))
+        s.assign_accumulate(c, e, l)
+        s.finalize(l, c, e, n)
+    torch.cuda.synchronize()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)]
+            for _ in range(iters)] for _ in range(args.steps)]
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t_start.record()
+    for k in range(args.steps):
+        step(evs[k])
+    t_end.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms_step = t_start.elapsed_time(t_end) / args.steps
+    per_it = [sum(evs[k][it][0].elapsed_time(evs[k][it][1]) for k in range(args.steps)) / args.steps
+              for it in range(iters)]
+
+    # the same loop as one hipGraph replay after an eager init
+    gr = s.graph(c, e, l, n)
+    for _ in range(args.warmup):
+        s.init_grid(lab, con, out=(c, e, l))
+        gr.launch()
+    torch.cuda.synchronize()
+    g0 = torch.cuda.Event(enable_timing=True)
+    g1 = torch.cuda.Event(enable_timing=True)
+    g0.record()
+    for _ in range(args.steps):
+        s.init_grid(lab, con, out=(c, e, l))
+        gr.launch()
+    g1.record()
+    torch.cuda.synchronize()
+    graph_ms = g0.elapsed_time(g1) / args.steps
+    gr.close()
+
+    N = W * H
+    value = N * iters / (ms_step * 1e-3) / 1e6
+    flops = sum(w["flops"] for w in work)
+    samples = sum(w["samples"] for w in work)
+    kern_s = sum(per_it) * 1e-3
+    achieved = flops / kern_s / 1e12
+    digest = source_digest()
+    traffic = traffic_for(digest)
+    roofline = {
+        "bound": "alu",
+        "kernel": "k_assign<256,true> (fused assignment + update sums)",
+        "achieved": round(achieved, 3),
+        "peak": round(VALU_FP32_PEAK_TFLOPS, 2),
+        "unit": "TFLOP/s",
+        "frac": round(achieved / VALU_FP32_PEAK_TFLOPS, 4),
+        "traffic": traffic,
+        "avg_launch_ms": round(kern_s * 1e3 / iters, 4),
+        "flops_per_launch": flops // iters,
+        "samples_per_launch": samples // iters,
+        "samples_per_px_iter": round(samples / (N * iters), 2),
+        "lds_algorithmic_TBps": round(16 * samples / kern_s / 1e12, 3),
+        "lds_peak_TBps": round(LDS_PEAK_TBPS, 1),
+        "kernel_source_sha256_16": digest,
+    }
+    log(f"hard: {ms_step:.3f} ms/step eager, {graph_ms:.3f} ms/step graph, wall {wall:.2f}s")
+    if args.copy_probe:
+        src = torch.empty(512 * 2**20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy probe: 3 x 512 MiB device copies")
+    return img, {
+        "value": value, "ms_per_step": ms_step, "graph_ms_per_step": graph_ms,
+        "graph_value": N * iters / (graph_ms * 1e-3) / 1e6, "roofline": roofline,
+        "config": {"workload": wl.name, "width": W, "height": H, "k": wl.k,
+                   "num_sp": s.grid.num_sp, "iterations": iters,
+                   "step": "pack + grid init + 10 x (fused assign/update, finalize/projection)"},
+    }
+
+
+def cpu_baseline(img, k, iters):
+    from oracle import oracle as orc
+    orc.lib()
+    threads = orc.max_threads()
+    H, W = img.contour.shape
+    reps = 0
+    t0 = time.perf_counter()
+    while True:
+        orc.run(img.lab, img.contour, k, iterations=iters)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= 10.0 or reps >= 3:
+            break
+    return {"value": round(W * H * iters * reps / el / 1e6, 3), "unit": "Mpixel-iter/s",
+            "cores": threads, "kind": "oracle",
+            "sample": f"{reps} full run(s) of {W}x{H} k={k}, {iters} iterations, "
+                      f"{el:.1f} s on {threads} OpenMP threads"}
+
+
+def bench_batched(torch, args):
+    from paper_1903_07149_amd import synth
+    from paper_1903_07149_amd.scalp import Scalp, ScalpBatch
+
+    wls = synth.batch_workloads()
+    imgs = [synth.workload_image(w) for w in wls]
+    b = ScalpBatch([(w.width, w.height, w.k) for w in wls], iterations=10)
+    lab = torch.cat([torch.from_numpy(i.lab.reshape(-1, 3)) for i in imgs]).cuda()
+    con = torch.cat([torch.from_numpy(i.contour.reshape(-1)) for i in imgs]).cuda()
+    st = b.new_state()
+    gr = b.graph(lab, con, *st)
+    for _ in range(2):
+        gr.launch()
+    torch.cuda.synchronize()
+    reps = 5
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        gr.launch()
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / reps
+    gr.close()
+    # the same images, one by one, through the single-image path
+    singles = []
+    for w, i in zip(wls, imgs):
+        s = Scalp(w.width, w.height, w.k, iterations=10)
+        singles.append((s, torch.from_numpy(i.lab).cuda(), torch.from_numpy(i.contour).cuda(),
+                        s.new_state()))
+    for s, la, co, out in singles:
+        s.run(la, co, out=out)
+    torch.cuda.synchronize()
+    t0.record()
+    for _ in range(2):
+        for s, la, co, out in singles:
+            s.run(la, co, out=out)
+    t1.record()
+    torch.cuda.synchronize()
+    ms1 = t0.elapsed_time(t1) / 2
+    px_it = b.total_pixels * 10
+    return {"workload": f"{len(wls)} ragged Voronoi images, H,W in [240,2160], k = HW/1000, 10 it",
+            "pixels": b.total_pixels, "superpixels": b.total_sp,
+            "batched_mpx_iter_s": round(px_it / (ms * 1e-3) / 1e6, 1), "batched_ms": round(ms, 3),
+            "single_path_mpx_iter_s": round(px_it / (ms1 * 1e-3) / 1e6, 1),
+            "single_path_ms": round(ms1, 3)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the batched and "
+              "single-image paths shard by image across GPUs without communication, so "
+              "per-GPU throughput is the figure", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU (torch.cuda.is_available() is False)", file=sys.stderr)
+        sys.exit(1)
+    log("hard SCALP, 1920x1080, k=2000, 10 iterations")
+    img, hard = bench_hard(torch, args)
+    out = {
+        "metric": METRIC, "value": round(hard["value"], 1), "unit": "Mpixel-iter/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(hard["ms_per_step"], 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": hard["config"], "roofline": hard["roofline"],
+        "graph_ms_per_step": round(hard["graph_ms_per_step"], 4),
+        "graph_value": round(hard["graph_value"], 1),
+    }
+    if not args.no_extensions:
+        log("batched")
+        out["extensions"] = {"batched": bench_batched(torch, args)}
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(img, 2000, 10)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -108,8 +108,8 @@ int scalp_init_grid(const scalp_grid_t* g, const scalp_params_t* p, const float*
                     const float* contour, float* centers, int32_t* endpoints, int32_t* labels,
                     void* workspace, size_t workspace_bytes, void* stream);
 
-/* Algorithm 1, one assignment pass from the given centers and endpoints:
- * every pixel compares the distance D of Eqs. (1)-(3), computed along the
+/* Algorithm 1, one assignment pass from the given centers and endpoints
+ * (endpoints outside the image are clamped into it): every pixel compares the distance D of Eqs. (1)-(3), computed along the
  * Bresenham path from the pixel to each candidate's endpoint (Sec. II-B),
  * over the superpixels of the 3x3 grid cells around its own cell, and takes
  * the first strict minimum in ascending superpixel order.  FP32 arithmetic
@@ -128,6 +128,22 @@ int scalp_assign(const scalp_grid_t* g, const scalp_params_t* p, const float* la
 int scalp_update(const scalp_grid_t* g, const scalp_params_t* p, const float* lab,
                  const int32_t* labels, float* centers, int32_t* endpoints, int32_t* counts,
                  void* workspace, size_t workspace_bytes, void* stream);
+
+/* The two halves of one fused iteration of scalp_run, for callers that step
+ * the loop themselves.  scalp_assign_accumulate: one assignment pass exactly
+ * as scalp_assign (on the packed image already in the workspace) that also
+ * adds each pixel's position and 2^-24 fixed-point colour to its
+ * superpixel's integer sums in the workspace.  scalp_finalize: the update of
+ * scalp_update computed from those sums (centers, endpoints with the Eq. (4)
+ * projection if p->project, counts), which then clears the sums.  The sums
+ * are zero after scalp_init_grid, scalp_update, scalp_finalize and
+ * scalp_run. */
+int scalp_assign_accumulate(const scalp_grid_t* g, const scalp_params_t* p, const float* centers,
+                            const int32_t* endpoints, int32_t* labels, void* workspace,
+                            size_t workspace_bytes, void* stream);
+int scalp_finalize(const scalp_grid_t* g, const scalp_params_t* p, const int32_t* labels,
+                   float* centers, int32_t* endpoints, int32_t* counts, void* workspace,
+                   size_t workspace_bytes, void* stream);
 
 /* Algorithm 1 end to end: prepare, init, then p->iterations x (assign,
  * update, projection).  The update is fused into the assignment kernel.

@@ -22,7 +22,8 @@ SCALP_ERR_UNSUPPORTED = -4
 
 EXPORTED = [
     "scalp_default_params", "scalp_make_grid", "scalp_workspace_bytes", "scalp_prepare",
-    "scalp_init_grid", "scalp_assign", "scalp_update", "scalp_run", "scalp_graph_create",
+    "scalp_init_grid", "scalp_assign", "scalp_update", "scalp_assign_accumulate",
+    "scalp_finalize", "scalp_run", "scalp_graph_create",
     "scalp_graph_launch", "scalp_graph_destroy", "scalp_batch_workspace_bytes",
     "scalp_run_batched", "scalp_batched_graph_create", "scalp_soft_saved_bytes",
     "scalp_soft_workspace_bytes", "scalp_soft_forward", "scalp_soft_backward", "scalp_strerror",
@@ -84,6 +85,8 @@ def lib() -> ctypes.CDLL:
             "scalp_init_grid": ([gp, pp, _P, _P, _P, _P, _P, _P, _SZ, _P], ctypes.c_int),
             "scalp_assign": ([gp, pp, _P, _P, _P, _P, _P, _P, _SZ, _P], ctypes.c_int),
             "scalp_update": ([gp, pp, _P, _P, _P, _P, _P, _P, _SZ, _P], ctypes.c_int),
+            "scalp_assign_accumulate": ([gp, pp, _P, _P, _P, _P, _SZ, _P], ctypes.c_int),
+            "scalp_finalize": ([gp, pp, _P, _P, _P, _P, _P, _SZ, _P], ctypes.c_int),
             "scalp_run": ([gp, pp, _P, _P, _P, _P, _P, _P, _P, _SZ, _P], ctypes.c_int),
             "scalp_graph_create": ([gp, pp, _P, _P, _P, _P, _P, _SZ, ctypes.POINTER(_P)],
                                    ctypes.c_int),

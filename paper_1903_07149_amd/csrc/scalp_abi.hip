@@ -278,6 +278,36 @@ int scalp_update(const scalp_grid_t* g, const scalp_params_t* p, const float* la
     return SCALP_OK;
 }
 
+int scalp_assign_accumulate(const scalp_grid_t* g, const scalp_params_t* p, const float* centers,
+                            const int32_t* endpoints, int32_t* labels, void* ws, size_t ws_bytes,
+                            void* stream) {
+    int rc = check_common(g, p, ws, ws_bytes);
+    if (rc != SCALP_OK) return rc;
+    if (!centers || !endpoints || !labels) return SCALP_ERR_ARG;
+    library_init();
+    const Views v = views_of(ws, layout_of((long long)g->width * g->height, g->num_sp));
+    CHECK_HIP(launch_assign(img_of(g, p, 0, 0), v.packed, centers, endpoints, labels, v.acc,
+                            v.ctrl, p->lambda, true, tuning_of(p), (hipStream_t)stream));
+    return SCALP_OK;
+}
+
+int scalp_finalize(const scalp_grid_t* g, const scalp_params_t* p, const int32_t* labels,
+                   float* centers, int32_t* endpoints, int32_t* counts, void* ws,
+                   size_t ws_bytes, void* stream) {
+    int rc = check_common(g, p, ws, ws_bytes);
+    if (rc != SCALP_OK) return rc;
+    if (!labels || !centers || !endpoints || !counts) return SCALP_ERR_ARG;
+    library_init();
+    const hipStream_t s = (hipStream_t)stream;
+    const Views v = views_of(ws, layout_of((long long)g->width * g->height, g->num_sp));
+    const Img im = img_of(g, p, 0, 0);
+    CHECK_HIP(launch_finalize(im, centers, endpoints, counts, v.acc, labels, v.ctrl, v.plist,
+                              p->project != 0, s));
+    if (p->project)
+        CHECK_HIP(launch_project(im, centers, counts, labels, endpoints, v.ctrl, v.plist, s));
+    return SCALP_OK;
+}
+
 int scalp_run(const scalp_grid_t* g, const scalp_params_t* p, const float* lab,
               const float* contour, float* centers, int32_t* endpoints, int32_t* labels,
               int32_t* counts, void* ws, size_t ws_bytes, void* stream) {

@@ -96,10 +96,13 @@ class Scalp:
         check(L.lib().scalp_prepare(ctypes.byref(self.grid), ctypes.byref(p), _p(lab),
                                     _p(contour), *self._ws(), _s(stream)), "scalp_prepare")
 
-    def init_grid(self, lab=None, contour=None, stream=None, reuse_prepared=False):
+    def init_grid(self, lab=None, contour=None, stream=None, reuse_prepared=False, out=None):
         if not reuse_prepared:
             self._img(lab, contour)
-        centers, endpoints, labels, _ = self.new_state()
+        if out is None:
+            centers, endpoints, labels, _ = self.new_state()
+        else:
+            centers, endpoints, labels = out
         p = self._params(reuse_prepared=int(reuse_prepared))
         check(L.lib().scalp_init_grid(ctypes.byref(self.grid), ctypes.byref(p), _p(lab),
                                       _p(contour), _p(centers), _p(endpoints), _p(labels),
@@ -135,6 +138,22 @@ class Scalp:
                                    _p(c), _p(e), _p(counts), *self._ws(), _s(stream)),
               "scalp_update")
         return c, e, counts
+
+    def assign_accumulate(self, centers, endpoints, labels, stream=None, **over) -> None:
+        """One fused assignment pass on the packed image in the workspace; the
+        update's sums stay in the workspace until finalize()."""
+        p = self._params(**over)
+        check(L.lib().scalp_assign_accumulate(ctypes.byref(self.grid), ctypes.byref(p),
+                                              _p(centers), _p(endpoints), _p(labels),
+                                              *self._ws(), _s(stream)),
+              "scalp_assign_accumulate")
+
+    def finalize(self, labels, centers, endpoints, counts, stream=None, **over) -> None:
+        """Update (in place) from the sums left by assign_accumulate()."""
+        p = self._params(**over)
+        check(L.lib().scalp_finalize(ctypes.byref(self.grid), ctypes.byref(p), _p(labels),
+                                     _p(centers), _p(endpoints), _p(counts), *self._ws(),
+                                     _s(stream)), "scalp_finalize")
 
     def run(self, lab, contour, stream=None, out=None, **over) -> RunResult:
         self._img(lab, contour)

@@ -1,0 +1,20 @@
+"""The algorithmic sample count used for throughput/roofline figures equals the
+number of path samples the oracle evaluates."""
+import numpy as np
+
+from paper_1903_07149_amd import counts, synth
+
+
+def test_sample_count_matches_oracle(orc):
+    for (W, H, k, seed) in [(97, 61, 30, 1), (160, 120, 48, 2), (50, 1, 5, 3)]:
+        lab, con = synth.random_lab(W, H, seed)
+        g = orc.grid(W, H, k)
+        c, e, _ = orc.init_grid(g, lab)
+        rng = np.random.default_rng(seed)
+        c[:, 3] = np.clip(c[:, 3] + rng.uniform(-3, 3, g.num_sp), 0, W - 1)
+        c[:, 4] = np.clip(c[:, 4] + rng.uniform(-3, 3, g.num_sp), 0, H - 1)
+        e = orc.round_endpoints(g, c)
+        _, _, samples = orc.assign(g, lab, orc.wmap(con), c, e)
+        w = counts.pass_work(W, H, g.nx, g.ny, e)
+        assert w["samples"] == samples
+        assert w["flops"] == 10 * samples + 16 * w["candidates"]
