@@ -83,10 +83,13 @@ def _declare(L):
     L.orc_run.restype = _l
     L.orc_set_threads.argtypes = [_i]; L.orc_set_threads.restype = None
     L.orc_max_threads.argtypes = []; L.orc_max_threads.restype = _i
-    L.orc_soft_forward.argtypes = [_i, _i, _i, _i, _p, _p, _d, _d, _d, _d, _d, _i, _p, _p, _p]
+    L.orc_distance_ab.argtypes = [_i, _i, _p, _p, _f, _f, _f, _i, _i, _p, _i, _i, _p, _p, _p]
+    L.orc_distance_ab.restype = _f
+    L.orc_soft_forward.argtypes = [_i, _i, _i, _i, _p, _p, _d, _d, _d, _d, _d, _i, _i, _p, _p,
+                                   _p]
     L.orc_soft_forward.restype = _i
-    L.orc_soft_backward.argtypes = [_i, _i, _i, _i, _p, _p, _d, _d, _d, _d, _d, _i, _p, _p,
-                                    _p, _p]
+    L.orc_soft_backward.argtypes = [_i, _i, _i, _i, _p, _p, _d, _d, _d, _d, _d, _i, _i, _p,
+                                    _p, _p, _p]
     L.orc_soft_backward.restype = _i
 
 
@@ -263,9 +266,11 @@ def run(lab, contour, k: int, iterations: int = 10, m: float = 10.0, lam: float 
 
 
 def soft_forward(lab, contour, k: int, iterations: int = 5, m: float = 10.0,
-                 lam: float = 0.5, sigma: float = 0.25, gamma: float = -1.0, T: float = 0.5):
+                 lam: float = 0.5, sigma: float = 0.25, gamma: float = -1.0, T: float = 0.5,
+                 d32: bool = False):
     """lab float32[B][H][W][3], contour float32[B][H][W].
-    Returns (theta f64[iters+1][B][K][5], q f64[iters][B][H][W][9], z f64[iters][B][K])."""
+    Returns (theta f64[iters+1][B][K][5], q f64[iters][B][H][W][9], z f64[iters][B][K]).
+    d32: the FP32-distance precision mode (see scalp_soft_oracle.c)."""
     lab = _f32(lab)
     contour = _f32(contour)
     B, H, W = contour.shape
@@ -275,14 +280,15 @@ def soft_forward(lab, contour, k: int, iterations: int = 5, m: float = 10.0,
     q = np.zeros((iterations, B, H, W, 9))
     z = np.zeros((iterations, B, K))
     rc = lib().orc_soft_forward(B, W, H, k, _ptr(lab), _ptr(contour), m, lam, sigma, gamma, T,
-                                iterations, _ptr(theta), _ptr(q), _ptr(z))
+                                iterations, int(d32), _ptr(theta), _ptr(q), _ptr(z))
     if rc != 0:
         raise ValueError("oracle soft forward rejected its arguments")
     return theta, q, z
 
 
 def soft_backward(lab, contour, k: int, gq, gtheta, iterations: int = 5, m: float = 10.0,
-                  lam: float = 0.5, sigma: float = 0.25, gamma: float = -1.0, T: float = 0.5):
+                  lam: float = 0.5, sigma: float = 0.25, gamma: float = -1.0, T: float = 0.5,
+                  d32: bool = False):
     """Gradient of <gq, Q_T> + <gtheta, Theta_T>.  Returns (glab f64[B][H][W][3],
     gcontour f64[B][H][W])."""
     lab = _f32(lab)
@@ -293,7 +299,8 @@ def soft_backward(lab, contour, k: int, gq, gtheta, iterations: int = 5, m: floa
     glab = np.zeros((B, H, W, 3))
     gc = np.zeros((B, H, W))
     rc = lib().orc_soft_backward(B, W, H, k, _ptr(lab), _ptr(contour), m, lam, sigma, gamma, T,
-                                 iterations, _ptr(gq), _ptr(gtheta), _ptr(glab), _ptr(gc))
+                                 iterations, int(d32), _ptr(gq), _ptr(gtheta), _ptr(glab),
+                                 _ptr(gc))
     if rc != 0:
         raise ValueError("oracle soft backward rejected its arguments")
     return glab, gc

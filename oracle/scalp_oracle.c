@@ -167,6 +167,30 @@ static float hard_distance(const hard_ctx *c, int x, int y, const float *centre,
     return A * B + ds * c->spw;                          /* Eq. (3) */
 }
 
+/* D and its factors A (Eq. (1)) and B (Eq. (2)), FP32; used by the soft
+ * oracle's FP32-distance mode. */
+float orc_distance_ab(int W, int H, const float *lab, const float *w, float lambda, float gamma,
+                      float spw, int x, int y, const float *centre, int cx, int cy,
+                      float *A_out, float *B_out, int *np1) {
+    hard_ctx c = {W, H, lab, w, lambda, gamma, spw};
+    int dx = cx - x, dy = cy - y;
+    int n = abs(dx) > abs(dy) ? abs(dx) : abs(dy);
+    float D = hard_distance(&c, x, y, centre, cx, cy, NULL);
+    /* the factors, recomputed in the same order as in hard_distance */
+    float sc = 0.0f, sw = 0.0f;
+    for (int i = 0; i <= n; i++) {
+        long q = (long)(y + path_offset(i, n, dy)) * W + (x + path_offset(i, n, dx));
+        sc = sc + colour_dist(lab + 3 * q, centre);
+        sw = sw + w[q];
+    }
+    float dcp = colour_dist(lab + 3 * ((long)y * W + x), centre);
+    float np = (float)(n + 1);
+    *A_out = lambda * dcp + (1.0f - lambda) * (sc / np);
+    *B_out = 1.0f + gamma * (sw / np);
+    *np1 = n + 1;
+    return D;
+}
+
 float orc_distance(int W, int H, const float *lab, const float *w,
                    float lambda, float gamma, float spw,
                    int x, int y, const float *centre, int cx, int cy) {

@@ -16,9 +16,20 @@
  * constant in X_k, so they carry no gradient.  Slots j = (di+1)*3 + (dj+1)
  * index the 3x3 neighbourhood; slots outside the grid have Q = 0.
  *
- * Everything here is FP64: the oracle is the exact-arithmetic reference for
- * the FP32 GPU path, and its own gradient is checked against central finite
- * differences of its own forward.
+ * A superpixel whose soft mass Z_k is below 1e-6 (a millionth of a pixel)
+ * counts as empty and keeps its centre, as an empty superpixel does in the
+ * hard update: its soft mean would be decided by weights that FP32 cannot
+ * represent, and dTheta/dQ = (f - Theta)/Z would be unbounded.
+ *
+ * Two precisions:
+ *   d32 = 0  everything in FP64.  This is the mode whose gradient is checked
+ *            against central finite differences of its own forward.
+ *   d32 = 1  the precision contract of the FP32 path: D, A and B are the hard
+ *            oracle's FP32 distance (same operation order), the softmax and
+ *            the update sums are FP64, and Q and Theta are rounded to FP32
+ *            where they are produced (endpoints are floorf(x + 0.5f) of the
+ *            FP32 barycenter); the backward is the FP64 chain rule at those
+ *            values.  The GPU path is compared with this mode.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -26,13 +37,27 @@
 
 int orc_grid(int W, int H, int k, int *nx, int *ny);
 double orc_grid_r(int W, int H, int k);
+float orc_spatial_weight(int W, int H, int k, float m);
+float orc_default_gamma(int W, int H, int k);
+void orc_wmap(const float *contour, long n, float sigma, float *w);
+float orc_distance_ab(int W, int H, const float *lab, const float *w, float lambda, float gamma,
+                      float spw, int x, int y, const float *centre, int cx, int cy,
+                      float *A_out, float *B_out, int *np1);
+
+#define SOFT_Z_MIN 1e-6
 
 typedef struct {
     int W, H, nx, ny, K;
     const float *lab;      /* [H][W][3] */
     const double *w;       /* [H][W]    */
     double lambda, gamma, spw, T;
+    int d32;               /* FP32-distance mode (see header) */
+    const float *w32;      /* [H][W], FP32 w map (d32 mode) */
+    float lambda32, gamma32, spw32;
 } soft_ctx;
+
+/* FP64 value as produced in the active precision (FP32 rounding in d32 mode). */
+static double as_out(const soft_ctx *c, double v) { return c->d32 ? (double)(float)v : v; }
 
 static int s_path_offset(long i, long n, int d) {
     if (n == 0) return 0;
@@ -41,8 +66,8 @@ static int s_path_offset(long i, long n, int d) {
     return d < 0 ? (int)-off : (int)off;
 }
 
-static int s_round(double v, int hi) {
-    int e = (int)floor(v + 0.5);
+static int s_round(double v, int hi, int d32) {
+    int e = d32 ? (int)floorf((float)v + 0.5f) : (int)floor(v + 0.5);
     if (e < 0) e = 0;
     if (e > hi) e = hi;
     return e;
@@ -64,6 +89,15 @@ static double dc64(const float *f, const double *ck) {
  * and B (Eq. (2)) and the path length n+1. */
 static double soft_distance(const soft_ctx *c, int x, int y, const double *th,
                             int cx, int cy, double *A, double *B, int *np1) {
+    if (c->d32) {
+        float centre[5] = {(float)th[0], (float)th[1], (float)th[2], (float)th[3], (float)th[4]};
+        float a32, b32;
+        float D = orc_distance_ab(c->W, c->H, c->lab, c->w32, c->lambda32, c->gamma32, c->spw32,
+                                  x, y, centre, cx, cy, &a32, &b32, np1);
+        *A = a32;
+        *B = b32;
+        return D;
+    }
     int dx = cx - x, dy = cy - y;
     int n = abs(dx) > abs(dy) ? abs(dx) : abs(dy);
     double sc = 0.0, sw = 0.0;
@@ -96,7 +130,7 @@ static void soft_init(const soft_ctx *c, double *th0) {
             cnt[k] += 1.0;
         }
     for (int k = 0; k < c->K; k++)
-        for (int e = 0; e < 5; e++) th0[5 * k + e] /= cnt[k];
+        for (int e = 0; e < 5; e++) th0[5 * k + e] = as_out(c, th0[5 * k + e] / cnt[k]);
     free(cnt);
 }
 
@@ -106,8 +140,8 @@ static void soft_step(const soft_ctx *c, const double *th_prev, double *q, doubl
     int K = c->K;
     int *ex = malloc(sizeof(int) * 2 * (size_t)K);
     for (int k = 0; k < K; k++) {
-        ex[2 * k] = s_round(th_prev[5 * k + 3], c->W - 1);
-        ex[2 * k + 1] = s_round(th_prev[5 * k + 4], c->H - 1);
+        ex[2 * k] = s_round(th_prev[5 * k + 3], c->W - 1, c->d32);
+        ex[2 * k + 1] = s_round(th_prev[5 * k + 4], c->H - 1, c->d32);
     }
     double *acc = calloc((size_t)K * 5, sizeof(double));
     memset(z, 0, sizeof(double) * (size_t)K);
@@ -131,7 +165,7 @@ static void soft_step(const soft_ctx *c, const double *th_prev, double *q, doubl
             }
             const float *f = c->lab + 3 * p;
             for (int j = 0; j < 9; j++) {
-                q[9 * p + j] /= s;
+                q[9 * p + j] = as_out(c, q[9 * p + j] / s);
                 int k = slot_cluster(c, x, y, j);
                 if (k < 0) continue;
                 double Q = q[9 * p + j];
@@ -145,14 +179,15 @@ static void soft_step(const soft_ctx *c, const double *th_prev, double *q, doubl
         }
     for (int k = 0; k < K; k++)
         for (int e = 0; e < 5; e++)
-            th_next[5 * k + e] = z[k] > 0.0 ? acc[5 * k + e] / z[k] : th_prev[5 * k + e];
+            th_next[5 * k + e] = z[k] >= SOFT_Z_MIN ? as_out(c, acc[5 * k + e] / z[k])
+                                                     : th_prev[5 * k + e];
     free(acc);
     free(ex);
 }
 
 static int soft_setup(soft_ctx *c, int W, int H, int k, const float *lab, const float *contour,
-                      double m, double lambda, double sigma, double gamma, double T,
-                      double **wbuf) {
+                      double m, double lambda, double sigma, double gamma, double T, int d32,
+                      double **wbuf, float **w32buf) {
     int nx, ny;
     int K = orc_grid(W, H, k, &nx, &ny);
     if (K < 0 || T <= 0.0 || sigma <= 0.0) return -1;
@@ -169,20 +204,29 @@ static int soft_setup(soft_ctx *c, int W, int H, int k, const float *lab, const 
     c->gamma = gamma < 0.0 ? 2.0 * r : gamma;
     c->spw = m * m / (r * r);
     c->T = T;
+    c->d32 = d32;
+    float *w32 = malloc(sizeof(float) * (size_t)N);
+    orc_wmap(contour, N, (float)sigma, w32);
+    c->w32 = w32;
+    c->lambda32 = (float)lambda;
+    c->gamma32 = gamma < 0.0 ? orc_default_gamma(W, H, k) : (float)gamma;
+    c->spw32 = orc_spatial_weight(W, H, k, (float)m);
     *wbuf = w;
+    *w32buf = w32;
     return K;
 }
 
 /* theta: [iters+1][B][K][5]; q: [iters][B][H][W][9]; z: [iters][B][K]. */
 int orc_soft_forward(int Bn, int W, int H, int k, const float *lab, const float *contour,
                      double m, double lambda, double sigma, double gamma, double T, int iters,
-                     double *theta, double *q, double *z) {
+                     int d32, double *theta, double *q, double *z) {
     long N = (long)W * H;
     for (int b = 0; b < Bn; b++) {
         soft_ctx c;
         double *w;
+        float *w32;
         int K = soft_setup(&c, W, H, k, lab + 3 * N * b, contour + N * b, m, lambda, sigma,
-                           gamma, T, &w);
+                           gamma, T, d32, &w, &w32);
         if (K < 0) return -1;
         soft_init(&c, theta + 5L * K * b);
         for (int t = 0; t < iters; t++) {
@@ -191,6 +235,7 @@ int orc_soft_forward(int Bn, int W, int H, int k, const float *lab, const float 
             soft_step(&c, prev, q + 9 * N * ((long)t * Bn + b), next, z + (long)K * ((long)t * Bn + b));
         }
         free(w);
+        free(w32);
     }
     return 0;
 }
@@ -200,14 +245,15 @@ int orc_soft_forward(int Bn, int W, int H, int k, const float *lab, const float 
  * gcontour: [B][H][W]. */
 int orc_soft_backward(int Bn, int W, int H, int k, const float *lab, const float *contour,
                       double m, double lambda, double sigma, double gamma, double T, int iters,
-                      const double *gq_in, const double *gtheta_in,
+                      int d32, const double *gq_in, const double *gtheta_in,
                       double *glab, double *gcontour) {
     long N = (long)W * H;
     for (int b = 0; b < Bn; b++) {
         soft_ctx c;
         double *w;
+        float *w32;
         int K = soft_setup(&c, W, H, k, lab + 3 * N * b, contour + N * b, m, lambda, sigma,
-                           gamma, T, &w);
+                           gamma, T, d32, &w, &w32);
         if (K < 0) return -1;
         const float *f = c.lab;
         /* forward, keeping every iterate */
@@ -236,7 +282,7 @@ int orc_soft_backward(int Bn, int W, int H, int k, const float *lab, const float
             /* soft update backward: theta_next = sum Q feat / Z */
             memset(gth_prev, 0, sizeof(double) * 5 * (size_t)K);
             for (int kk = 0; kk < K; kk++)
-                if (!(Z[kk] > 0.0))
+                if (!(Z[kk] >= SOFT_Z_MIN))
                     for (int e = 0; e < 5; e++) gth_prev[5 * kk + e] += gth[5 * kk + e];
             for (int y = 0; y < H; y++)
                 for (int x = 0; x < W; x++) {
@@ -244,7 +290,7 @@ int orc_soft_backward(int Bn, int W, int H, int k, const float *lab, const float
                     double feat[5] = {f[3 * p], f[3 * p + 1], f[3 * p + 2], (double)x, (double)y};
                     for (int j = 0; j < 9; j++) {
                         int kk = slot_cluster(&c, x, y, j);
-                        if (kk < 0 || !(Z[kk] > 0.0)) continue;
+                        if (kk < 0 || !(Z[kk] >= SOFT_Z_MIN)) continue;
                         double s = 0.0;
                         for (int e = 0; e < 5; e++)
                             s += gth[5 * kk + e] * (feat[e] - thn[5 * kk + e]);
@@ -255,8 +301,8 @@ int orc_soft_backward(int Bn, int W, int H, int k, const float *lab, const float
                 }
             /* softmax backward and path backward */
             for (int kk = 0; kk < K; kk++) {
-                ex[2 * kk] = s_round(thp[5 * kk + 3], W - 1);
-                ex[2 * kk + 1] = s_round(thp[5 * kk + 4], H - 1);
+                ex[2 * kk] = s_round(thp[5 * kk + 3], W - 1, c.d32);
+                ex[2 * kk + 1] = s_round(thp[5 * kk + 4], H - 1, c.d32);
             }
             for (int y = 0; y < H; y++)
                 for (int x = 0; x < W; x++) {
@@ -319,7 +365,7 @@ int orc_soft_backward(int Bn, int W, int H, int k, const float *lab, const float
             gcontour[N * b + p] = gw[p] * (2.0 * cq / s2) * exp(-(cq * cq) / s2);
         }
         free(th); free(qq); free(zz); free(gf); free(gw); free(gth); free(gth_prev);
-        free(gQ); free(ex); free(w);
+        free(gQ); free(ex); free(w); free(w32);
     }
     return 0;
 }

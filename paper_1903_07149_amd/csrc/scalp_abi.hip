@@ -464,16 +464,159 @@ int scalp_batched_graph_create(const scalp_batch_desc_t* descs, int32_t n, const
     });
 }
 
-size_t scalp_soft_saved_bytes(const scalp_grid_t*, int32_t, int32_t) { return 0; }
-size_t scalp_soft_workspace_bytes(const scalp_grid_t*, int32_t) { return 0; }
-int scalp_soft_forward(const scalp_grid_t*, const scalp_params_t*, float, int32_t, const float*,
-                       const float*, float*, float*, void*, void*, size_t, void*) {
-    return SCALP_ERR_UNSUPPORTED;
+// ------------------------------------------------------------------ soft
+
+}  // extern "C"
+
+namespace {
+
+// saved: [A: T][B][9][N] float, [Bf: T][B][9][N] float, [Z: T][B][K] double
+struct SoftSaved {
+    size_t a, bf, z, total;
+};
+
+SoftSaved soft_saved_layout(const scalp_grid_t* g, long long B, long long T) {
+    const long long N = (long long)g->width * g->height, K = g->num_sp;
+    SoftSaved s;
+    s.a = 0;
+    s.bf = align_up((size_t)(T * B * 9 * N) * 4);
+    s.z = s.bf + align_up((size_t)(T * B * 9 * N) * 4);
+    s.total = s.z + align_up((size_t)(T * B * K) * 8);
+    return s;
 }
-int scalp_soft_backward(const scalp_grid_t*, const scalp_params_t*, float, int32_t, const float*,
-                        const float*, const float*, const float*, const void*, const float*,
-                        const float*, float*, float*, void*, size_t, void*) {
-    return SCALP_ERR_UNSUPPORTED;
+
+// workspace: [packed B*N float4][gd B*9*N][gf B*N float4][gth 2 x B*K*5]
+struct SoftWs {
+    size_t packed, gd, gf, gth0, gth1, total;
+};
+
+SoftWs soft_ws_layout(const scalp_grid_t* g, long long B) {
+    const long long N = (long long)g->width * g->height, K = g->num_sp;
+    SoftWs w;
+    w.packed = 0;
+    w.gd = align_up((size_t)(B * N) * 16);
+    w.gf = w.gd + align_up((size_t)(B * 9 * N) * 4);
+    w.gth0 = w.gf + align_up((size_t)(B * N) * 16);
+    w.gth1 = w.gth0 + align_up((size_t)(B * K * 5) * 4);
+    w.total = w.gth1 + align_up((size_t)(B * K * 5) * 4);
+    return w;
+}
+
+bool soft_args_ok(const scalp_grid_t* g, const scalp_params_t* p, float temperature,
+                  int32_t batch) {
+    if (!grid_valid(g) || !params_valid(p)) return false;
+    if (!(temperature > 0.0f) || !std::isfinite(temperature)) return false;
+    if (batch < 1 || p->iterations < 1) return false;
+    const long long N = (long long)g->width * g->height;
+    return (long long)batch * N < (1LL << 40);
+}
+
+int soft_cap_bytes(const scalp_params_t* p) {
+    return (p->lds_pixels > 0 ? p->lds_pixels : default_lds_pixels()) * 16;
+}
+
+std::once_flag g_soft_once;
+
+}  // namespace
+
+extern "C" {
+
+size_t scalp_soft_saved_bytes(const scalp_grid_t* g, int32_t batch, int32_t iterations) {
+    if (!grid_valid(g) || batch < 1 || iterations < 1) return 0;
+    return soft_saved_layout(g, batch, iterations).total;
+}
+
+size_t scalp_soft_workspace_bytes(const scalp_grid_t* g, int32_t batch) {
+    if (!grid_valid(g) || batch < 1) return 0;
+    return soft_ws_layout(g, batch).total;
+}
+
+int scalp_soft_forward(const scalp_grid_t* g, const scalp_params_t* p, float temperature,
+                       int32_t batch, const float* lab, const float* contour, float* centers_t,
+                       float* q_t, void* saved, void* ws, size_t ws_bytes, void* stream) {
+    if (!soft_args_ok(g, p, temperature, batch)) return SCALP_ERR_ARG;
+    if (!centers_t || !q_t || !saved) return SCALP_ERR_ARG;
+    if (!p->reuse_prepared && (!lab || !contour)) return SCALP_ERR_ARG;
+    const SoftWs W = soft_ws_layout(g, batch);
+    if (!ws || ws_bytes < W.total) return SCALP_ERR_WORKSPACE;
+    library_init();
+    std::call_once(g_soft_once, [] { lift_soft_lds_limits(); });
+    const hipStream_t s = (hipStream_t)stream;
+    const long long N = (long long)g->width * g->height, K = g->num_sp, B = batch;
+    const int T = p->iterations;
+    const Img im = img_of(g, p, 0, 0);
+    const SoftGeom geo = soft_geom(g->width, g->height, g->nx, g->ny, batch, im.spw, im.gamma,
+                                   p->lambda, temperature);
+    const SoftSaved S = soft_saved_layout(g, B, T);
+    char* wb = static_cast<char*>(ws);
+    char* sb = static_cast<char*>(saved);
+    float4* packed = reinterpret_cast<float4*>(wb + W.packed);
+    float* fa = reinterpret_cast<float*>(sb + S.a);
+    float* fb = reinterpret_cast<float*>(sb + S.bf);
+    double* z = reinterpret_cast<double*>(sb + S.z);
+    const int cap = soft_cap_bytes(p) / 16;
+    if (!p->reuse_prepared) CHECK_HIP(launch_prepare(B * N, lab, contour, p->sigma, packed, s));
+    CHECK_HIP(launch_soft_init(geo, packed, centers_t, s));
+    for (int t = 0; t < T; ++t) {
+        const long long qo = (long long)t * B * 9 * N;
+        CHECK_HIP(launch_soft_assign(geo, packed, centers_t + (long long)t * B * K * 5, q_t + qo,
+                                     fa + qo, fb + qo, cap, s));
+        CHECK_HIP(launch_soft_update(geo, q_t + qo, packed, centers_t + (long long)t * B * K * 5,
+                                     centers_t + (long long)(t + 1) * B * K * 5,
+                                     z + (long long)t * B * K, s));
+    }
+    return SCALP_OK;
+}
+
+int scalp_soft_backward(const scalp_grid_t* g, const scalp_params_t* p, float temperature,
+                        int32_t batch, const float* lab, const float* contour,
+                        const float* centers_t, const float* q_t, const void* saved,
+                        const float* grad_q, const float* grad_centers, float* grad_lab,
+                        float* grad_contour, void* ws, size_t ws_bytes, void* stream) {
+    if (!soft_args_ok(g, p, temperature, batch)) return SCALP_ERR_ARG;
+    if (!centers_t || !q_t || !saved || !grad_q || !grad_centers || !grad_lab || !grad_contour ||
+        !contour)
+        return SCALP_ERR_ARG;
+    if (!p->reuse_prepared && !lab) return SCALP_ERR_ARG;
+    const SoftWs W = soft_ws_layout(g, batch);
+    if (!ws || ws_bytes < W.total) return SCALP_ERR_WORKSPACE;
+    library_init();
+    std::call_once(g_soft_once, [] { lift_soft_lds_limits(); });
+    const hipStream_t s = (hipStream_t)stream;
+    const long long N = (long long)g->width * g->height, K = g->num_sp, B = batch;
+    const int T = p->iterations;
+    const Img im = img_of(g, p, 0, 0);
+    const SoftGeom geo = soft_geom(g->width, g->height, g->nx, g->ny, batch, im.spw, im.gamma,
+                                   p->lambda, temperature);
+    const SoftSaved S = soft_saved_layout(g, B, T);
+    char* wb = static_cast<char*>(ws);
+    const char* sb = static_cast<const char*>(saved);
+    float4* packed = reinterpret_cast<float4*>(wb + W.packed);
+    float* gd = reinterpret_cast<float*>(wb + W.gd);
+    float4* gf = reinterpret_cast<float4*>(wb + W.gf);
+    float* gth[2] = {reinterpret_cast<float*>(wb + W.gth0), reinterpret_cast<float*>(wb + W.gth1)};
+    const float* fa = reinterpret_cast<const float*>(sb + S.a);
+    const float* fb = reinterpret_cast<const float*>(sb + S.bf);
+    const double* z = reinterpret_cast<const double*>(sb + S.z);
+    const int cap = soft_cap_bytes(p) / 20;
+    if (!p->reuse_prepared) CHECK_HIP(launch_prepare(B * N, lab, contour, p->sigma, packed, s));
+    CHECK_HIP(launch_clear(reinterpret_cast<long long*>(gf), B * N * 2, s));
+    CHECK_HIP(launch_copy_f32(grad_centers, gth[0], B * K * 5, s));
+    int cur = 0;
+    for (int t = T - 1; t >= 0; --t) {
+        const long long qo = (long long)t * B * 9 * N;
+        const double* zt = z + (long long)t * B * K;
+        CHECK_HIP(launch_soft_bwd_update(geo, t == T - 1, q_t + qo, zt,
+                                         centers_t + (long long)(t + 1) * B * K * 5, packed,
+                                         gth[cur], grad_q, gd, gf, s));
+        CHECK_HIP(launch_soft_bwd_pass(geo, zt, gth[cur], gth[1 - cur], s));
+        CHECK_HIP(launch_soft_bwd_path(geo, packed, centers_t + (long long)t * B * K * 5, fa + qo,
+                                       fb + qo, gd, gf, gth[1 - cur], cap, s));
+        cur = 1 - cur;
+    }
+    CHECK_HIP(launch_soft_bwd_finish(geo, gf, gth[cur], contour, p->sigma, grad_lab, grad_contour,
+                                     s));
+    return SCALP_OK;
 }
 
 const char* scalp_strerror(int code) {

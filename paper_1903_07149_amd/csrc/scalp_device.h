@@ -1,0 +1,114 @@
+// scalp_device.h -- device helpers shared by the hard and soft kernels.
+#pragma once
+
+#include "scalp_internal.h"
+
+namespace scalp {
+namespace dev {
+
+// First coordinate of grid cell `idx` of `n` along an axis of `len` pixels:
+// pixel c is in cell floor(c * n / len), i.e. cell idx starts at
+// ceil(idx * len / n).
+__device__ __forceinline__ int cell_lo(int idx, int len, int n) {
+    return (int)(((long long)idx * len + n - 1) / n);
+}
+
+__device__ __forceinline__ float colour_dist(float4 f, float l, float a, float b) {
+    float dl = f.x - l;
+    float da = f.y - a;
+    float db = f.z - b;
+    return (dl * dl + da * da) + db * db;
+}
+
+__device__ __forceinline__ long long to_fixed(float v) {
+    return (long long)rintf(v * kFixScaleF);
+}
+
+// Accumulates the samples i = 1 .. n-1 of the path from the pixel at linear
+// index `idx` toward (dx, dy): on major-axis step i the minor offset is
+// floor((2 i |d_minor| + n) / (2 n)), kept incrementally as a remainder.
+// stepx / stepy are the index strides of one pixel in x / y.
+__device__ __forceinline__ void walk_path(const float4* __restrict__ base, int idx, int stepx,
+                                          int stepy, int dx, int dy, float l, float a, float b,
+                                          float& sc, float& sw) {
+    const int adx = dx < 0 ? -dx : dx;
+    const int ady = dy < 0 ? -dy : dy;
+    const bool xmaj = adx >= ady;
+    const int n = xmaj ? adx : ady;
+    const int am = xmaj ? ady : adx;
+    const int sx = dx < 0 ? -stepx : stepx;
+    const int sy = dy < 0 ? -stepy : stepy;
+    const int smaj = xmaj ? sx : sy;
+    const int sdiag = smaj + (xmaj ? sy : sx);
+    const int two_n = 2 * n;
+    const int inc = 2 * am;
+    int rem = n;
+    for (int i = 1; i < n; ++i) {
+        rem += inc;
+        const bool step = rem >= two_n;
+        rem -= step ? two_n : 0;
+        idx += step ? sdiag : smaj;
+        const float4 f = base[idx];
+        const float dl = f.x - l;
+        const float da = f.y - a;
+        const float db = f.z - b;
+        const float dc = (dl * dl + da * da) + db * db;
+        sc = sc + dc;
+        sw = sw + f.w;
+    }
+}
+
+__device__ __forceinline__ int round_coord(float v, int hi) {
+    int e = (int)floorf(v + 0.5f);
+    e = e < 0 ? 0 : e;
+    return e > hi ? hi : e;
+}
+
+// Workgroup index -> work item.  Workgroups are dispatched round-robin over
+// the 8 XCDs; give each XCD a contiguous run of items so that neighbouring
+// cells, which stage overlapping halos, share an L2.
+__device__ __forceinline__ int xcd_remap(int b, int G) {
+    const int q = G >> 3, rem = G & 7;
+    const int x = b & 7, slot = b >> 3;
+    return x < rem ? x * (q + 1) + slot : rem * (q + 1) + (x - rem) * q + slot;
+}
+
+__device__ __forceinline__ int find_image(const int* start, int n, int v) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (start[mid] <= v) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Pixel t of a cell of width cw and height ch, enumerated in 8-wide column
+// strips walked serpentine (down, up, ...): 64 consecutive indices form a
+// compact 8x8 block, so the lanes of a wave walk paths of similar length.
+__device__ __forceinline__ void cell_pixel(int t, int cw, int ch, int& x, int& y) {
+    const int nfull = cw >> 3, wr = cw & 7;
+    const int fullpx = nfull * 8 * ch;
+    int s, row, col;
+    if (t < fullpx) {
+        const int per = 8 * ch;
+        s = t / per;
+        const int r = t - s * per;
+        row = r >> 3;
+        col = 8 * s + (r & 7);
+    } else {
+        s = nfull;
+        const int r = t - fullpx;
+        row = r / wr;
+        col = 8 * nfull + (r - row * wr);
+    }
+    y = (s & 1) ? (ch - 1 - row) : row;
+    x = col;
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+}  // namespace dev
+}  // namespace scalp

@@ -80,4 +80,30 @@ int launch_project_batched(const Img* imgs, const int* sp_start, int n_img, cons
                            const int* ctrl, const int* plist, hipStream_t s);
 int persistent_grid(const Tuning& t);
 
+// ---- soft SCALP (scalp_soft.hip)
+struct SoftGeom {
+    int W, H, nx, ny, B;
+    float spw, gamma, lambda, temperature;
+};
+SoftGeom soft_geom(int W, int H, int nx, int ny, int B, float spw, float gamma, float lambda,
+                   float temperature);
+void lift_soft_lds_limits();
+int launch_soft_init(const SoftGeom& g, const float4* packed, float* theta0, hipStream_t st);
+int launch_soft_assign(const SoftGeom& g, const float4* packed, const float* theta_prev, float* q,
+                       float* fa, float* fb, int cap, hipStream_t st);
+int launch_soft_update(const SoftGeom& g, const float* q, const float4* packed,
+                       const float* theta_prev, float* theta_next, double* z, hipStream_t st);
+int launch_soft_bwd_update(const SoftGeom& g, int first, const float* q, const double* z,
+                           const float* theta, const float4* packed, const float* gth,
+                           const float* gq_in, float* gd, float4* gf, hipStream_t st);
+int launch_soft_bwd_pass(const SoftGeom& g, const double* z, const float* gth, float* gth_prev,
+                         hipStream_t st);
+int launch_soft_bwd_path(const SoftGeom& g, const float4* packed, const float* theta_prev,
+                         const float* fa, const float* fb, const float* gd, float4* gf,
+                         float* gth_prev, int cap, hipStream_t st);
+int launch_soft_bwd_finish(const SoftGeom& g, const float4* gf, const float* gth0,
+                           const float* contour, float sigma, float* glab, float* gcon,
+                           hipStream_t st);
+int launch_copy_f32(const float* src, float* dst, long long n, hipStream_t st);
+
 }  // namespace scalp

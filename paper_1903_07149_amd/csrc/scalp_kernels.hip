@@ -25,17 +25,13 @@
 // bit for bit.
 #include <algorithm>
 
-#include "scalp_internal.h"
+#include "scalp_device.h"
 
 namespace scalp {
 namespace {
 
-// First coordinate of grid cell `idx` of `n` along an axis of `len` pixels:
-// pixel c is in cell floor(c * n / len), i.e. cell idx starts at
-// ceil(idx * len / n).
-__device__ __forceinline__ int cell_lo(int idx, int len, int n) {
-    return (int)(((long long)idx * len + n - 1) / n);
-}
+using namespace dev;
+
 
 struct Cand {
     int k;            // superpixel index within the image, -1 outside the grid
@@ -50,51 +46,6 @@ struct CellShared {
     int rx0, ry0, rw, rh;
     unsigned long long bins[9][6];
 };
-
-__device__ __forceinline__ float colour_dist(float4 f, float l, float a, float b) {
-    float dl = f.x - l;
-    float da = f.y - a;
-    float db = f.z - b;
-    return (dl * dl + da * da) + db * db;
-}
-
-__device__ __forceinline__ long long to_fixed(float v) {
-    return (long long)rintf(v * kFixScaleF);
-}
-
-// Accumulates the samples i = 1 .. n-1 of the path from the pixel at linear
-// index `idx` toward (dx, dy): on major-axis step i the minor offset is
-// floor((2 i |d_minor| + n) / (2 n)), kept incrementally as a remainder.
-// stepx / stepy are the index strides of one pixel in x / y.
-__device__ __forceinline__ void walk_path(const float4* __restrict__ base, int idx, int stepx,
-                                          int stepy, int dx, int dy, float l, float a, float b,
-                                          float& sc, float& sw) {
-    const int adx = dx < 0 ? -dx : dx;
-    const int ady = dy < 0 ? -dy : dy;
-    const bool xmaj = adx >= ady;
-    const int n = xmaj ? adx : ady;
-    const int am = xmaj ? ady : adx;
-    const int sx = dx < 0 ? -stepx : stepx;
-    const int sy = dy < 0 ? -stepy : stepy;
-    const int smaj = xmaj ? sx : sy;
-    const int sdiag = smaj + (xmaj ? sy : sx);
-    const int two_n = 2 * n;
-    const int inc = 2 * am;
-    int rem = n;
-    for (int i = 1; i < n; ++i) {
-        rem += inc;
-        const bool step = rem >= two_n;
-        rem -= step ? two_n : 0;
-        idx += step ? sdiag : smaj;
-        const float4 f = base[idx];
-        const float dl = f.x - l;
-        const float da = f.y - a;
-        const float db = f.z - b;
-        const float dc = (dl * dl + da * da) + db * db;
-        sc = sc + dc;
-        sw = sw + f.w;
-    }
-}
 
 template <int WG, bool ACCUM>
 __device__ __forceinline__ void process_cell(const Img& im, int cell,
@@ -170,13 +121,8 @@ __device__ __forceinline__ void process_cell(const Img& im, int cell,
     }
     __syncthreads();
 
-    // Pixels of the cell in 8-wide column strips, serpentine (down, up, ...),
-    // 64 consecutive pixels per wave: compact 8x8 blocks, so the lanes of a
-    // wave walk paths of similar length.
     const int cw = x1 - x0, ch = y1 - y0;
     const int P = cw * ch;
-    const int nfull = cw >> 3, wr = cw & 7;
-    const int fullpx = nfull * 8 * ch;
     const int lane = tid & 63, wave = tid >> 6;
     const int nchunks = (P + 63) >> 6;
     const float oml = 1.0f - lambda;
@@ -184,21 +130,10 @@ __device__ __forceinline__ void process_cell(const Img& im, int cell,
     for (int chunk = wave; chunk < nchunks; chunk += WG / 64) {
         const int t = chunk * 64 + lane;
         if (t >= P) continue;
-        int s, row, col;
-        if (t < fullpx) {
-            const int per = 8 * ch;
-            s = t / per;
-            const int r = t - s * per;
-            row = r >> 3;
-            col = 8 * s + (r & 7);
-        } else {
-            s = nfull;
-            const int r = t - fullpx;
-            row = r / wr;
-            col = 8 * nfull + (r - row * wr);
-        }
-        const int y = y0 + ((s & 1) ? (ch - 1 - row) : row);
-        const int x = x0 + col;
+        int x, y;
+        cell_pixel(t, cw, ch, x, y);
+        x += x0;
+        y += y0;
         const int p = y * W + x;
         const float4 fp = img[p];
         const int lidx = (y - ry0) * rw + (x - rx0);
@@ -260,15 +195,6 @@ __device__ __forceinline__ void process_cell(const Img& im, int cell,
     __syncthreads();   // shared state is reused by the next cell of a persistent workgroup
 }
 
-// Workgroup index -> grid cell.  Workgroups are dispatched round-robin over
-// the 8 XCDs; give each XCD a contiguous run of cells so that neighbouring
-// cells, which stage overlapping halos, share an L2.
-__device__ __forceinline__ int xcd_remap(int b, int G) {
-    const int q = G >> 3, rem = G & 7;
-    const int x = b & 7, slot = b >> 3;
-    return x < rem ? x * (q + 1) + slot : rem * (q + 1) + (x - rem) * q + slot;
-}
-
 template <int WG, bool ACCUM>
 __global__ __launch_bounds__(WG) void k_assign(Img im, const float4* __restrict__ packed,
                                                const float* __restrict__ centres,
@@ -282,15 +208,6 @@ __global__ __launch_bounds__(WG) void k_assign(Img im, const float4* __restrict_
     const int cell = xcd_remap(blockIdx.x, gridDim.x);
     process_cell<WG, ACCUM>(im, cell, packed, centres, endpoints, labels, acc, lambda, cap,
                             lds_dyn, sh);
-}
-
-__device__ __forceinline__ int find_image(const int* start, int n, int v) {
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (start[mid] <= v) lo = mid; else hi = mid - 1;
-    }
-    return lo;
 }
 
 template <int WG>
@@ -435,12 +352,6 @@ __global__ __launch_bounds__(WG) void k_accumulate(Img im, const float* __restri
 }
 
 // ---------------------------------------------------------------- finalize
-
-__device__ __forceinline__ int round_coord(float v, int hi) {
-    int e = (int)floorf(v + 0.5f);
-    e = e < 0 ? 0 : e;
-    return e > hi ? hi : e;
-}
 
 __device__ __forceinline__ void finalize_one(const Img& im, int k, float* __restrict__ centres,
                                              int* __restrict__ endpoints,

@@ -1,0 +1,653 @@
+// scalp_soft.hip -- soft (differentiable) SCALP on gfx950.
+//
+// An extension of the paper's method: the distance D of Eqs. (1)-(3) over the
+// same 3x3 grid-neighbour candidates as Algorithm 1, a softmax with
+// temperature T over the candidates instead of the argmin, and soft
+// barycenters instead of the hard update.  Paths go to the rounded
+// barycenter floor(X_k + 0.5) (no Eq. (4) projection, which needs hard
+// membership); the rounding is piecewise constant, so it carries no gradient.
+//
+// Forward, per iteration:
+//   k_soft_assign  workgroup per (image, cell): LDS-staged halo, per-lane path
+//                  walks as in the hard kernel, softmax over the 9 slots;
+//                  writes Q and the factors A (Eq. (1)) and B (Eq. (2)).
+//   k_soft_update  workgroup per (image, superpixel): gathers Q over the 3x3
+//                  cell block in a fixed order (FP64 partial sums, tree
+//                  reduction): deterministic, no atomics.
+// Backward, per iteration in reverse:
+//   k_soft_bwd_update  thread per pixel: soft-update and softmax backward,
+//                      giving dL/dD for the 9 slots.
+//   k_soft_bwd_path    workgroup per (image, cell), one pass per candidate
+//                      slot: every lane re-walks its path (samples are
+//                      recomputed, never stored) and scatters
+//                      alpha_q += dL/dD * B (1-lambda) 2/|P|  and
+//                      dL/dw_q += dL/dD * A gamma/|P|  into LDS tiles; a
+//                      fold then turns alpha into dL/df_q = alpha_q (f_q - f_k)
+//                      and into the candidate's centre gradient.  The tiles
+//                      leave the workgroup as float atomics (not
+//                      bit-reproducible).
+#include <algorithm>
+
+#include "scalp_device.h"
+
+namespace scalp {
+namespace {
+
+using namespace dev;
+
+struct SoftImg {
+    int W, H, nx, ny, K, B;
+    long long N;
+    float spw, gamma, lambda, inv_t;
+    double temp;
+};
+
+// A superpixel whose soft mass is below a millionth of a pixel counts as
+// empty and keeps its centre (as an empty one does in the hard update).
+constexpr double kZMin = 1e-6;
+
+struct SoftCand {
+    int k;
+    float l, a, b, x, y;
+    int cx, cy;
+    float dcc, wc;
+    int staged;
+};
+
+struct SoftShared {
+    SoftCand cand[9];
+    int rx0, ry0, rw, rh;
+    float bins[9][5];
+};
+
+// Candidates of cell (ci, cj) from theta [K][5]; endpoint = rounded barycenter.
+__device__ __forceinline__ void load_candidates(const SoftImg& s, int ci, int cj,
+                                                const float* __restrict__ theta,
+                                                const float4* __restrict__ img, SoftShared& sh) {
+    const int tid = threadIdx.x;
+    if (tid < 9) {
+        SoftCand c;
+        const int ii = ci + tid / 3 - 1, jj = cj + tid % 3 - 1;
+        c.staged = 0;
+        if (ii >= 0 && ii < s.ny && jj >= 0 && jj < s.nx) {
+            const int k = ii * s.nx + jj;
+            const float* ck = theta + 5LL * k;
+            c.k = k;
+            c.l = ck[0]; c.a = ck[1]; c.b = ck[2]; c.x = ck[3]; c.y = ck[4];
+            c.cx = round_coord(c.x, s.W - 1);
+            c.cy = round_coord(c.y, s.H - 1);
+            const float4 fc = img[(long long)c.cy * s.W + c.cx];
+            c.dcc = colour_dist(fc, c.l, c.a, c.b);
+            c.wc = fc.w;
+        } else {
+            c.k = -1;
+            c.l = c.a = c.b = c.x = c.y = 0.0f;
+            c.cx = c.cy = 0;
+            c.dcc = c.wc = 0.0f;
+        }
+        sh.cand[tid] = c;
+    }
+}
+
+// Greedy LDS rectangle (cell grown by candidate endpoints within `cap`).
+__device__ __forceinline__ void plan_rect(int x0, int x1, int y0, int y1, int cap, SoftShared& sh) {
+    if (threadIdx.x == 0) {
+        int rx0 = x0, rx1 = x1, ry0 = y0, ry1 = y1;
+        if ((long long)(x1 - x0) * (y1 - y0) <= cap) {
+            for (int j = 0; j < 9; ++j) {
+                if (sh.cand[j].k < 0) continue;
+                const int cx = sh.cand[j].cx, cy = sh.cand[j].cy;
+                const int ax0 = min(rx0, cx), ax1 = max(rx1, cx + 1);
+                const int ay0 = min(ry0, cy), ay1 = max(ry1, cy + 1);
+                if ((long long)(ax1 - ax0) * (ay1 - ay0) <= cap) {
+                    rx0 = ax0; rx1 = ax1; ry0 = ay0; ry1 = ay1;
+                    sh.cand[j].staged = 1;
+                }
+            }
+            sh.rx0 = rx0; sh.ry0 = ry0; sh.rw = rx1 - rx0; sh.rh = ry1 - ry0;
+        } else {
+            sh.rx0 = x0; sh.ry0 = y0; sh.rw = 0; sh.rh = 0;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ forward
+
+template <int WG>
+__global__ __launch_bounds__(WG) void k_soft_init(SoftImg s, const float4* __restrict__ packed,
+                                                  float* __restrict__ theta0) {
+    __shared__ double red[6][WG];
+    const int tid = threadIdx.x;
+    const int b = blockIdx.x / s.K, k = blockIdx.x - b * s.K;
+    const int ci = k / s.nx, cj = k - ci * s.nx;
+    const int x0 = cell_lo(cj, s.W, s.nx), x1 = cell_lo(cj + 1, s.W, s.nx);
+    const int y0 = cell_lo(ci, s.H, s.ny), y1 = cell_lo(ci + 1, s.H, s.ny);
+    const float4* img = packed + (long long)b * s.N;
+    const int cw = x1 - x0, P = cw * (y1 - y0);
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int t = tid; t < P; t += WG) {
+        const int r = t / cw;
+        const int x = x0 + (t - r * cw), y = y0 + r;
+        const float4 f = img[(long long)y * s.W + x];
+        acc[0] += f.x; acc[1] += f.y; acc[2] += f.z; acc[3] += x; acc[4] += y; acc[5] += 1.0;
+    }
+    for (int v = 0; v < 6; ++v) red[v][tid] = acc[v];
+    __syncthreads();
+    for (int h = WG / 2; h > 0; h >>= 1) {
+        if (tid < h)
+            for (int v = 0; v < 6; ++v) red[v][tid] += red[v][tid + h];
+        __syncthreads();
+    }
+    if (tid < 5) theta0[(5LL * b) * s.K + 5LL * k + tid] = (float)(red[tid][0] / red[5][0]);
+}
+
+template <int WG>
+__global__ __launch_bounds__(WG) void k_soft_assign(SoftImg s, const float4* __restrict__ packed,
+                                                    const float* __restrict__ theta_prev,
+                                                    float* __restrict__ q, float* __restrict__ fa,
+                                                    float* __restrict__ fb, int cap) {
+    extern __shared__ float4 lds_dyn[];
+    __shared__ SoftShared sh;
+    const int item = xcd_remap(blockIdx.x, gridDim.x);
+    const int b = item / s.K, cell = item - b * s.K;
+    const int tid = threadIdx.x;
+    const int W = s.W, H = s.H;
+    const int ci = cell / s.nx, cj = cell - ci * s.nx;
+    const int x0 = cell_lo(cj, W, s.nx), x1 = cell_lo(cj + 1, W, s.nx);
+    const int y0 = cell_lo(ci, H, s.ny), y1 = cell_lo(ci + 1, H, s.ny);
+    const float4* __restrict__ img = packed + (long long)b * s.N;
+    load_candidates(s, ci, cj, theta_prev + 5LL * s.K * b, img, sh);
+    __syncthreads();
+    plan_rect(x0, x1, y0, y1, cap, sh);
+    __syncthreads();
+    const int rx0 = sh.rx0, ry0 = sh.ry0, rw = sh.rw;
+    const int area = rw * sh.rh;
+    for (int e = tid; e < area; e += WG) {
+        const int r = e / rw;
+        lds_dyn[e] = img[(long long)(ry0 + r) * W + rx0 + (e - r * rw)];
+    }
+    __syncthreads();
+    const int cw = x1 - x0, ch = y1 - y0, P = cw * ch;
+    const int lane = tid & 63, wave = tid >> 6;
+    const float lambda = s.lambda, oml = 1.0f - lambda;
+    const long long base = 9LL * s.N * b;
+    for (int chunk = wave; chunk * 64 < P; chunk += WG / 64) {
+        const int t = chunk * 64 + lane;
+        if (t >= P) continue;
+        int x, y;
+        cell_pixel(t, cw, ch, x, y);
+        x += x0;
+        y += y0;
+        const int p = y * W + x;
+        const float4 fp = img[p];
+        const int lidx = (y - ry0) * rw + (x - rx0);
+        float D[9], Av[9], Bv[9];
+        float dmin = INFINITY;
+#pragma unroll
+        for (int j = 0; j < 9; ++j) {
+            D[j] = INFINITY;
+            Av[j] = 0.0f;
+            Bv[j] = 0.0f;
+            if (sh.cand[j].k < 0) continue;
+            const float l = sh.cand[j].l, a = sh.cand[j].a, bb = sh.cand[j].b;
+            const int dx = sh.cand[j].cx - x, dy = sh.cand[j].cy - y;
+            const float dcp = colour_dist(fp, l, a, bb);
+            float sc = dcp, sw = fp.w;
+            if (sh.cand[j].staged)
+                walk_path(lds_dyn, lidx, 1, rw, dx, dy, l, a, bb, sc, sw);
+            else
+                walk_path(img, p, 1, W, dx, dy, l, a, bb, sc, sw);
+            const int adx = dx < 0 ? -dx : dx, ady = dy < 0 ? -dy : dy;
+            const int n = adx > ady ? adx : ady;
+            if (n > 0) {
+                sc = sc + sh.cand[j].dcc;
+                sw = sw + sh.cand[j].wc;
+            }
+            const float np = (float)(n + 1);
+            const float A = lambda * dcp + oml * (sc / np);
+            const float Bw = 1.0f + s.gamma * (sw / np);
+            const float ex = (float)x - sh.cand[j].x, ey = (float)y - sh.cand[j].y;
+            D[j] = A * Bw + (ex * ex + ey * ey) * s.spw;
+            Av[j] = A;
+            Bv[j] = Bw;
+            dmin = fminf(dmin, D[j]);
+        }
+        // softmax in FP64 (the FP32 distances differ by far more than FP32's
+        // exponent range allows at small T), rounded once to FP32
+        double e[9], sum = 0.0;
+#pragma unroll
+        for (int j = 0; j < 9; ++j) {
+            e[j] = sh.cand[j].k < 0 ? 0.0 : exp(-((double)D[j] - (double)dmin) / s.temp);
+            sum += e[j];
+        }
+#pragma unroll
+        for (int j = 0; j < 9; ++j) {
+            const long long o = base + (long long)j * s.N + p;
+            q[o] = (float)(e[j] / sum);
+            fa[o] = Av[j];
+            fb[o] = Bv[j];
+        }
+    }
+}
+
+template <int WG>
+__device__ __forceinline__ void block_sum6(double (&v)[6], double (*red)[WG]) {
+    const int tid = threadIdx.x;
+    for (int i = 0; i < 6; ++i) red[i][tid] = v[i];
+    __syncthreads();
+    for (int h = WG / 2; h > 0; h >>= 1) {
+        if (tid < h)
+            for (int i = 0; i < 6; ++i) red[i][tid] += red[i][tid + h];
+        __syncthreads();
+    }
+    for (int i = 0; i < 6; ++i) v[i] = red[i][0];
+}
+
+// Soft update of superpixel k: Z = sum Q, f_k = sum Q f / Z, X_k = sum Q X / Z
+// over the pixels of the 3x3 cell block around k, each read through the slot
+// under which it sees k.
+template <int WG>
+__global__ __launch_bounds__(WG) void k_soft_update(SoftImg s, const float* __restrict__ q,
+                                                    const float4* __restrict__ packed,
+                                                    const float* __restrict__ theta_prev,
+                                                    float* __restrict__ theta_next,
+                                                    double* __restrict__ z) {
+    __shared__ double red[6][WG];
+    const int tid = threadIdx.x;
+    const int b = blockIdx.x / s.K, k = blockIdx.x - b * s.K;
+    const int ci = k / s.nx, cj = k - ci * s.nx;
+    const int X0 = cell_lo(max(cj - 1, 0), s.W, s.nx), X1 = cell_lo(min(cj + 2, s.nx), s.W, s.nx);
+    const int Y0 = cell_lo(max(ci - 1, 0), s.H, s.ny), Y1 = cell_lo(min(ci + 2, s.ny), s.H, s.ny);
+    const int bw = X1 - X0, area = bw * (Y1 - Y0);
+    const float4* img = packed + (long long)b * s.N;
+    const float* qb = q + 9LL * s.N * b;
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int e = tid; e < area; e += WG) {
+        const int r = e / bw;
+        const int x = X0 + (e - r * bw), y = Y0 + r;
+        const int cip = (int)(((long long)y * s.ny) / s.H), cjp = (int)(((long long)x * s.nx) / s.W);
+        const int j = (ci - cip + 1) * 3 + (cj - cjp + 1);
+        const long long p = (long long)y * s.W + x;
+        const double Q = qb[(long long)j * s.N + p];
+        const float4 f = img[p];
+        acc[0] += Q;
+        acc[1] += Q * f.x;
+        acc[2] += Q * f.y;
+        acc[3] += Q * f.z;
+        acc[4] += Q * x;
+        acc[5] += Q * y;
+    }
+    block_sum6<WG>(acc, red);
+    if (tid < 5) {
+        const long long o = 5LL * s.K * b + 5LL * k + tid;
+        theta_next[o] = acc[0] >= kZMin ? (float)(acc[tid + 1] / acc[0]) : theta_prev[o];
+    }
+    if (tid == 0) z[(long long)s.K * b + k] = acc[0];
+}
+
+// ------------------------------------------------------------------ backward
+
+// Soft-update backward (theta_t = sum Q feat / Z) and softmax backward:
+// gd[j] = dL/dD_pj.  gf += dL/df_p through the update.
+__global__ void k_soft_bwd_update(SoftImg s, int first, const float* __restrict__ q,
+                                  const double* __restrict__ z, const float* __restrict__ theta,
+                                  const float4* __restrict__ packed,
+                                  const float* __restrict__ gth, const float* __restrict__ gq_in,
+                                  float* __restrict__ gd, float4* __restrict__ gf) {
+    const long long total = (long long)s.B * s.N;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int b = (int)(i / s.N);
+        const long long p = i - (long long)b * s.N;
+        const int y = (int)(p / s.W), x = (int)(p - (long long)y * s.W);
+        const int ci = (int)(((long long)y * s.ny) / s.H), cj = (int)(((long long)x * s.nx) / s.W);
+        const float4 f = packed[i];
+        const float feat[5] = {f.x, f.y, f.z, (float)x, (float)y};
+        const long long qb = 9LL * s.N * b + p;
+        float Q[9], G[9];
+        float gfl = 0.0f, gfa = 0.0f, gfb = 0.0f, dot = 0.0f;
+#pragma unroll
+        for (int j = 0; j < 9; ++j) {
+            const int ii = ci + j / 3 - 1, jj = cj + j % 3 - 1;
+            Q[j] = q[qb + (long long)j * s.N];
+            G[j] = first ? gq_in[qb + (long long)j * s.N] : 0.0f;
+            if (ii < 0 || ii >= s.ny || jj < 0 || jj >= s.nx) continue;
+            const int k = ii * s.nx + jj;
+            const double Zd = z[(long long)s.K * b + k];
+            if (Zd >= kZMin) {
+                const float Z = (float)Zd;
+                const float* g = gth + 5LL * s.K * b + 5LL * k;
+                const float* th = theta + 5LL * s.K * b + 5LL * k;
+                float acc = 0.0f;
+                for (int c = 0; c < 5; ++c) acc += g[c] * (feat[c] - th[c]);
+                G[j] += acc / Z;
+                const float w = Q[j] / Z;
+                gfl += g[0] * w;
+                gfa += g[1] * w;
+                gfb += g[2] * w;
+            }
+            dot += Q[j] * G[j];
+        }
+#pragma unroll
+        for (int j = 0; j < 9; ++j) gd[qb + (long long)j * s.N] = -s.inv_t * Q[j] * (G[j] - dot);
+        float4 o = gf[i];
+        o.x += gfl;
+        o.y += gfa;
+        o.z += gfb;
+        gf[i] = o;
+    }
+}
+
+// dL/dTheta_{t-1} starts as the pass-through of superpixels whose soft mass
+// was zero (they kept their previous centre) and receives the path terms.
+__global__ void k_soft_bwd_pass(SoftImg s, const double* __restrict__ z,
+                                const float* __restrict__ gth, float* __restrict__ gth_prev) {
+    const long long total = 5LL * s.B * s.K;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+         i += (long long)gridDim.x * blockDim.x)
+        gth_prev[i] = z[i / 5] >= kZMin ? 0.0f : gth[i];
+}
+
+template <int WG>
+__global__ __launch_bounds__(WG) void k_soft_bwd_path(SoftImg s, const float4* __restrict__ packed,
+                                                      const float* __restrict__ theta_prev,
+                                                      const float* __restrict__ fa,
+                                                      const float* __restrict__ fb,
+                                                      const float* __restrict__ gd,
+                                                      float4* __restrict__ gf,
+                                                      float* __restrict__ gth_prev, int cap) {
+    extern __shared__ float4 lds_dyn[];
+    __shared__ SoftShared sh;
+    float4* acc = lds_dyn;                                     // [cap] dL/d(l,a,b,w)
+    float* alpha = reinterpret_cast<float*>(lds_dyn + cap);    // [cap]
+    const int item = xcd_remap(blockIdx.x, gridDim.x);
+    const int b = item / s.K, cell = item - b * s.K;
+    const int tid = threadIdx.x;
+    const int W = s.W, H = s.H;
+    const int ci = cell / s.nx, cj = cell - ci * s.nx;
+    const int x0 = cell_lo(cj, W, s.nx), x1 = cell_lo(cj + 1, W, s.nx);
+    const int y0 = cell_lo(ci, H, s.ny), y1 = cell_lo(ci + 1, H, s.ny);
+    const float4* __restrict__ img = packed + (long long)b * s.N;
+    float4* __restrict__ gimg = gf + (long long)b * s.N;
+    load_candidates(s, ci, cj, theta_prev + 5LL * s.K * b, img, sh);
+    for (int t = tid; t < 45; t += WG) (&sh.bins[0][0])[t] = 0.0f;
+    __syncthreads();
+    plan_rect(x0, x1, y0, y1, cap, sh);
+    __syncthreads();
+    const int rx0 = sh.rx0, ry0 = sh.ry0, rw = sh.rw;
+    const int area = rw * sh.rh;
+    for (int e = tid; e < area; e += WG) {
+        acc[e] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        alpha[e] = 0.0f;
+    }
+    __syncthreads();
+    const int cw = x1 - x0, ch = y1 - y0, P = cw * ch;
+    const int lane = tid & 63, wave = tid >> 6;
+    const float lambda = s.lambda, oml = 1.0f - lambda;
+    const long long base = 9LL * s.N * b;
+    for (int j = 0; j < 9; ++j) {
+        const SoftCand c = sh.cand[j];
+        if (c.k < 0) continue;                                  // uniform
+        float gk[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+        for (int chunk = wave; chunk * 64 < P; chunk += WG / 64) {
+            const int t = chunk * 64 + lane;
+            if (t >= P) continue;
+            int x, y;
+            cell_pixel(t, cw, ch, x, y);
+            x += x0;
+            y += y0;
+            const int p = y * W + x;
+            const long long o = base + (long long)j * s.N + p;
+            const float g = gd[o];
+            if (g == 0.0f) continue;
+            const float A = fa[o], Bw = fb[o];
+            const int dx = c.cx - x, dy = c.cy - y;
+            const int adx = dx < 0 ? -dx : dx, ady = dy < 0 ? -dy : dy;
+            const int n = adx > ady ? adx : ady;
+            const float inv_np = 1.0f / (float)(n + 1);
+            const float cf = 2.0f * g * Bw * oml * inv_np;      // per path sample, times (f_q - f_k)
+            const float cw_ = g * A * s.gamma * inv_np;         // per path sample: dL/dw_q
+            const float4 fp = img[p];
+            const float lf = 2.0f * g * Bw * lambda;            // lambda term of p
+            const float dl = fp.x - c.l, da = fp.y - c.a, db = fp.z - c.b;
+            gk[0] -= lf * dl;
+            gk[1] -= lf * da;
+            gk[2] -= lf * db;
+            gk[3] -= 2.0f * g * s.spw * ((float)x - c.x);
+            gk[4] -= 2.0f * g * s.spw * ((float)y - c.y);
+            // the path, samples i = 0 .. n (p itself included)
+            const bool xmaj = adx >= ady;
+            const int am = xmaj ? ady : adx;
+            const int two_n = 2 * n, inc = 2 * am;
+            int rem = n;
+            if (c.staged) {
+                const int stx = dx < 0 ? -1 : 1, sty = dy < 0 ? -rw : rw;
+                const int smaj = xmaj ? stx : sty;
+                const int sdiag = smaj + (xmaj ? sty : stx);
+                int li = (y - ry0) * rw + (x - rx0);
+                atomicAdd(&acc[li].x, lf * dl);
+                atomicAdd(&acc[li].y, lf * da);
+                atomicAdd(&acc[li].z, lf * db);
+                for (int i = 0; i <= n; ++i) {
+                    if (i > 0) {
+                        rem += inc;
+                        const bool st = rem >= two_n;
+                        rem -= st ? two_n : 0;
+                        li += st ? sdiag : smaj;
+                    }
+                    atomicAdd(&alpha[li], cf);
+                    atomicAdd(&acc[li].w, cw_);
+                }
+            } else {
+                const int stx = dx < 0 ? -1 : 1, sty = dy < 0 ? -W : W;
+                const int smaj = xmaj ? stx : sty;
+                const int sdiag = smaj + (xmaj ? sty : stx);
+                int gi = p;
+                unsafeAtomicAdd(&gimg[gi].x, lf * dl);
+                unsafeAtomicAdd(&gimg[gi].y, lf * da);
+                unsafeAtomicAdd(&gimg[gi].z, lf * db);
+                for (int i = 0; i <= n; ++i) {
+                    if (i > 0) {
+                        rem += inc;
+                        const bool st = rem >= two_n;
+                        rem -= st ? two_n : 0;
+                        gi += st ? sdiag : smaj;
+                    }
+                    const float4 fq = img[gi];
+                    const float el = fq.x - c.l, ea = fq.y - c.a, eb = fq.z - c.b;
+                    unsafeAtomicAdd(&gimg[gi].x, cf * el);
+                    unsafeAtomicAdd(&gimg[gi].y, cf * ea);
+                    unsafeAtomicAdd(&gimg[gi].z, cf * eb);
+                    unsafeAtomicAdd(&gimg[gi].w, cw_);
+                    gk[0] -= cf * el;
+                    gk[1] -= cf * ea;
+                    gk[2] -= cf * eb;
+                }
+            }
+        }
+        __syncthreads();
+        if (c.staged) {
+            // fold: dL/df_q += alpha_q (f_q - f_k); the candidate's colour
+            // gradient takes the opposite sum.  Clears alpha for the next slot.
+            const int fx0 = max(min(x0, c.cx), rx0), fx1 = min(max(x1, c.cx + 1), rx0 + rw);
+            const int fy0 = max(min(y0, c.cy), ry0), fy1 = min(max(y1, c.cy + 1), ry0 + sh.rh);
+            const int fw = fx1 - fx0, fa_ = fw * (fy1 - fy0);
+            for (int e = tid; e < fa_; e += WG) {
+                const int r = e / fw;
+                const int x = fx0 + (e - r * fw), y = fy0 + r;
+                const int li = (y - ry0) * rw + (x - rx0);
+                const float al = alpha[li];
+                if (al != 0.0f) {
+                    const float4 fq = img[(long long)y * W + x];
+                    const float el = al * (fq.x - c.l), ea = al * (fq.y - c.a),
+                                eb = al * (fq.z - c.b);
+                    float4 v = acc[li];
+                    v.x += el;
+                    v.y += ea;
+                    v.z += eb;
+                    acc[li] = v;
+                    gk[0] -= el;
+                    gk[1] -= ea;
+                    gk[2] -= eb;
+                    alpha[li] = 0.0f;
+                }
+            }
+        }
+        for (int v = 0; v < 5; ++v) {
+            const float sv = wave_sum(gk[v]);
+            if (lane == 0 && sv != 0.0f) atomicAdd(&sh.bins[j][v], sv);
+        }
+        __syncthreads();
+    }
+    // flush the workgroup's tiles
+    for (int e = tid; e < area; e += WG) {
+        const float4 v = acc[e];
+        if (v.x != 0.0f || v.y != 0.0f || v.z != 0.0f || v.w != 0.0f) {
+            const int r = e / rw;
+            float4* d = &gimg[(long long)(ry0 + r) * W + rx0 + (e - r * rw)];
+            unsafeAtomicAdd(&d->x, v.x);
+            unsafeAtomicAdd(&d->y, v.y);
+            unsafeAtomicAdd(&d->z, v.z);
+            unsafeAtomicAdd(&d->w, v.w);
+        }
+    }
+    if (tid < 45) {
+        const int j = tid / 5, v = tid - 5 * (tid / 5);
+        const int k = sh.cand[j].k;
+        if (k >= 0 && sh.bins[j][v] != 0.0f)
+            unsafeAtomicAdd(&gth_prev[5LL * s.K * b + 5LL * k + v], sh.bins[j][v]);
+    }
+}
+
+// Theta_0 = cell means: dL/df_p += dL/dTheta_0 / |cell|; then the outputs:
+// dL/dlab = dL/df and dL/dC = dL/dw * 2C/sigma^2 exp(-C^2/sigma^2).
+__global__ void k_soft_bwd_finish(SoftImg s, const float4* __restrict__ gf,
+                                  const float* __restrict__ gth0,
+                                  const float* __restrict__ contour, float sigma,
+                                  float* __restrict__ glab, float* __restrict__ gcon) {
+    const long long total = (long long)s.B * s.N;
+    const double s2 = (double)sigma * (double)sigma;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int b = (int)(i / s.N);
+        const long long p = i - (long long)b * s.N;
+        const int y = (int)(p / s.W), x = (int)(p - (long long)y * s.W);
+        const int ci = (int)(((long long)y * s.ny) / s.H), cj = (int)(((long long)x * s.nx) / s.W);
+        const int cnt = (cell_lo(cj + 1, s.W, s.nx) - cell_lo(cj, s.W, s.nx)) *
+                        (cell_lo(ci + 1, s.H, s.ny) - cell_lo(ci, s.H, s.ny));
+        const float* g0 = gth0 + 5LL * s.K * b + 5LL * (ci * s.nx + cj);
+        const float4 v = gf[i];
+        glab[3 * i] = v.x + g0[0] / (float)cnt;
+        glab[3 * i + 1] = v.y + g0[1] / (float)cnt;
+        glab[3 * i + 2] = v.z + g0[2] / (float)cnt;
+        const double c = contour[i];
+        gcon[i] = (float)((double)v.w * (2.0 * c / s2) * exp(-(c * c) / s2));
+    }
+}
+
+__global__ void k_copy_f32(const float* __restrict__ src, float* __restrict__ dst, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+constexpr int kSoftWG = 256;
+
+unsigned grid_for(long long n) {
+    return (unsigned)std::max<long long>(1, std::min<long long>((n + 255) / 256, 65536));
+}
+
+}  // namespace
+
+SoftGeom soft_geom(int W, int H, int nx, int ny, int B, float spw, float gamma, float lambda,
+                   float temperature) {
+    SoftGeom g;
+    g.W = W; g.H = H; g.nx = nx; g.ny = ny; g.B = B;
+    g.spw = spw; g.gamma = gamma; g.lambda = lambda; g.temperature = temperature;
+    return g;
+}
+
+static SoftImg to_img(const SoftGeom& g) {
+    SoftImg s;
+    s.W = g.W; s.H = g.H; s.nx = g.nx; s.ny = g.ny; s.K = g.nx * g.ny; s.B = g.B;
+    s.N = (long long)g.W * g.H;
+    s.spw = g.spw; s.gamma = g.gamma; s.lambda = g.lambda; s.inv_t = 1.0f / g.temperature;
+    s.temp = (double)g.temperature;
+    return s;
+}
+
+void lift_soft_lds_limits() {
+    const size_t cap = 160 * 1024 - sizeof(SoftShared) - 64;
+    for (const void* k : {reinterpret_cast<const void*>(k_soft_assign<kSoftWG>),
+                          reinterpret_cast<const void*>(k_soft_bwd_path<kSoftWG>)}) {
+        static_cast<void>(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                              (int)cap));
+        static_cast<void>(hipGetLastError());
+    }
+}
+
+int launch_soft_init(const SoftGeom& g, const float4* packed, float* theta0, hipStream_t st) {
+    const SoftImg s = to_img(g);
+    hipLaunchKernelGGL(k_soft_init<kSoftWG>, dim3(s.B * s.K), dim3(kSoftWG), 0, st, s, packed,
+                       theta0);
+    return hipGetLastError();
+}
+
+int launch_soft_assign(const SoftGeom& g, const float4* packed, const float* theta_prev, float* q,
+                       float* fa, float* fb, int cap, hipStream_t st) {
+    const SoftImg s = to_img(g);
+    hipLaunchKernelGGL(k_soft_assign<kSoftWG>, dim3(s.B * s.K), dim3(kSoftWG),
+                       (size_t)cap * sizeof(float4), st, s, packed, theta_prev, q, fa, fb, cap);
+    return hipGetLastError();
+}
+
+int launch_soft_update(const SoftGeom& g, const float* q, const float4* packed,
+                       const float* theta_prev, float* theta_next, double* z, hipStream_t st) {
+    const SoftImg s = to_img(g);
+    hipLaunchKernelGGL(k_soft_update<kSoftWG>, dim3(s.B * s.K), dim3(kSoftWG), 0, st, s, q, packed,
+                       theta_prev, theta_next, z);
+    return hipGetLastError();
+}
+
+int launch_soft_bwd_update(const SoftGeom& g, int first, const float* q, const double* z,
+                           const float* theta, const float4* packed, const float* gth,
+                           const float* gq_in, float* gd, float4* gf, hipStream_t st) {
+    const SoftImg s = to_img(g);
+    hipLaunchKernelGGL(k_soft_bwd_update, dim3(grid_for(s.B * s.N)), dim3(256), 0, st, s, first, q,
+                       z, theta, packed, gth, gq_in, gd, gf);
+    return hipGetLastError();
+}
+
+int launch_soft_bwd_pass(const SoftGeom& g, const double* z, const float* gth, float* gth_prev,
+                         hipStream_t st) {
+    const SoftImg s = to_img(g);
+    hipLaunchKernelGGL(k_soft_bwd_pass, dim3(grid_for(5LL * s.B * s.K)), dim3(256), 0, st, s, z,
+                       gth, gth_prev);
+    return hipGetLastError();
+}
+
+int launch_soft_bwd_path(const SoftGeom& g, const float4* packed, const float* theta_prev,
+                         const float* fa, const float* fb, const float* gd, float4* gf,
+                         float* gth_prev, int cap, hipStream_t st) {
+    const SoftImg s = to_img(g);
+    hipLaunchKernelGGL(k_soft_bwd_path<kSoftWG>, dim3(s.B * s.K), dim3(kSoftWG),
+                       (size_t)cap * (sizeof(float4) + sizeof(float)), st, s, packed, theta_prev,
+                       fa, fb, gd, gf, gth_prev, cap);
+    return hipGetLastError();
+}
+
+int launch_soft_bwd_finish(const SoftGeom& g, const float4* gf, const float* gth0,
+                           const float* contour, float sigma, float* glab, float* gcon,
+                           hipStream_t st) {
+    const SoftImg s = to_img(g);
+    hipLaunchKernelGGL(k_soft_bwd_finish, dim3(grid_for(s.B * s.N)), dim3(256), 0, st, s, gf, gth0,
+                       contour, sigma, glab, gcon);
+    return hipGetLastError();
+}
+
+int launch_copy_f32(const float* src, float* dst, long long n, hipStream_t st) {
+    hipLaunchKernelGGL(k_copy_f32, dim3(grid_for(n)), dim3(256), 0, st, src, dst, n);
+    return hipGetLastError();
+}
+
+}  // namespace scalp

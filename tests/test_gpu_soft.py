@@ -1,0 +1,202 @@
+"""Soft SCALP on the GPU against the oracle's FP32-distance mode (d32: the same
+FP32 distance as the hard path, FP64 softmax and update sums, Q and Theta
+rounded to FP32 where produced).
+
+Tolerances: both sides compute bit-identical FP32 distances, so Q differs only
+where the two FP64 exponentials (each within 1 ulp) round to different FP32
+values: |dQ| <= 1e-6.  Theta differs only by the order of its FP64 sums
+before the single FP32 rounding: relative 1e-6.  The GPU backward runs in FP32
+with float atomics against the FP64 chain rule at the same forward values:
+relative error of the whole gradient <= 1e-3 and of any element <= 1e-2 of the
+largest, for accumulations of up to ~1e5 FP32 terms per element.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from paper_1903_07149_amd import synth
+from gpu_util import dev, host, needs_gpu, say, torch
+
+pytestmark = [pytest.mark.gpu, needs_gpu]
+
+
+def _batch(B, size, regions, seed0, k=None):
+    labs, cons = [], []
+    for b in range(B):
+        img = synth.make_image(size[0], size[1], regions, 10.0, seed0 + b)
+        labs.append(img.lab)
+        # spread the contour so that dw/dC is not ~0 almost everywhere
+        c = img.contour + 0.2 * np.random.default_rng(seed0 + b).random(img.contour.shape)
+        cons.append(np.clip(c, 0, 1).astype(np.float32))
+    return np.stack(labs), np.stack(cons)
+
+
+def _endpoint_margin(theta):
+    """Distance from a rounding boundary of the soft barycenter coordinates that a
+    later iteration rounds to a path endpoint.  Coordinates exactly on a half are
+    excluded: in FP64 that needs every other soft weight to underflow to 0
+    (D gaps above 745 T), far beyond FP32's underflow, so the GPU lands on the
+    same half exactly and rounds the same way."""
+    xy = theta[1:-1, ..., 3:5]
+    d = np.abs(xy - np.floor(xy) - 0.5)
+    d = d[d > 0]
+    return float(d.min()) if d.size else float("inf")
+
+
+def _engine(W, H, k, B, T, iters, **kw):
+    from paper_1903_07149_amd.soft import SoftScalp
+    return SoftScalp(W, H, k, B, temperature=T, iterations=iters, **kw)
+
+
+CASES = [  # (W, H, k, B, T, iterations, seed)
+    (96, 80, 30, 2, 0.5, 3, 600),
+    (64, 64, 16, 2, 5.0, 4, 610),
+    (70, 45, 12, 1, 50.0, 2, 620),
+]
+
+
+def _round_xy(theta, W, H):
+    xy = theta[..., 3:5]
+    e = np.floor(xy + np.float32(0.5)) if xy.dtype == np.float32 else np.floor(xy + 0.5)
+    return np.stack([np.clip(e[..., 0], 0, W - 1), np.clip(e[..., 1], 0, H - 1)], axis=-1)
+
+
+def compare_forward(c_t, q_t, th_o, q_o, W, H):
+    """Per-iteration comparison.  Iteration t is compared while the path endpoints
+    both sides derive from Theta_{t-1} agree; where they first differ, the differing
+    coordinates must lie within 1e-2 of a rounding half in the FP64 oracle (both
+    roundings are then valid), and later iterations are not compared.
+    Returns the number of iterations compared."""
+    q_ref = q_o.transpose(0, 1, 4, 2, 3)            # -> [T][B][9][H][W]
+    T = q_t.shape[0]
+    for t in range(T):
+        eg = _round_xy(c_t[t], W, H)
+        eo = _round_xy(th_o[t], W, H)
+        if not (eg == eo).all():
+            bad = eg != eo
+            frac = th_o[t][..., 3:5] - np.floor(th_o[t][..., 3:5])
+            print(f"iteration {t + 1}: {int(bad.sum())} endpoint coordinates round differently")
+            assert (np.abs(frac - 0.5)[bad] < 1e-2).all()
+            return t
+        dq = np.abs(q_t[t] - q_ref[t]).max()
+        dth = (np.abs(c_t[t + 1] - th_o[t + 1]) / (np.abs(th_o[t + 1]) + 1.0)).max()
+        print(f"iteration {t + 1}: max |dQ| = {dq:.3e}, max rel dTheta = {dth:.3e}")
+        assert dq <= 1e-6, t
+        assert dth <= 1e-6, t
+    return T
+
+
+@pytest.mark.parametrize("W,H,k,B,T,iters,seed", CASES)
+def test_soft_forward_matches_oracle(orc, W, H, k, B, T, iters, seed):
+    lab, con = _batch(B, (W, H), 8, seed)
+    th_o, q_o, z_o = orc.soft_forward(lab, con, k, iterations=iters, T=T, d32=True)
+    eng = _engine(W, H, k, B, T, iters)
+    say("soft forward", W, H, k, B, T, iters)
+    c_t, q_t, saved = eng.forward(dev(lab), dev(con))
+    c_t, q_t = host(c_t), host(q_t)
+    assert compare_forward(c_t, q_t, th_o, q_o, W, H) == iters
+    assert np.allclose(q_t.sum(axis=2), 1.0, atol=1e-5)
+
+
+@pytest.mark.parametrize("W,H,k,B,T,iters,seed", CASES)
+def test_soft_backward_matches_oracle(orc, W, H, k, B, T, iters, seed):
+    lab, con = _batch(B, (W, H), 8, seed)
+    rng = np.random.default_rng(seed + 1)
+    K = orc.grid(W, H, k).num_sp
+    gq = rng.normal(0, 1, (B, 9, H, W)).astype(np.float32)
+    gth = rng.normal(0, 1, (B, K, 5)).astype(np.float32)
+    glab_o, gcon_o = orc.soft_backward(lab, con, k, gq.transpose(0, 2, 3, 1), gth,
+                                       iterations=iters, T=T, d32=True)
+    eng = _engine(W, H, k, B, T, iters)
+    L, C = dev(lab), dev(con)
+    say("soft backward", W, H, k, B, T, iters)
+    c_t, q_t, saved = eng.forward(L, C)
+    glab, gcon = (host(t) for t in eng.backward(L, C, c_t, q_t, saved, dev(gq), dev(gth)))
+    for got, ref, name in ((glab, glab_o, "lab"), (gcon, gcon_o, "contour")):
+        rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        amax = np.abs(got - ref).max() / np.abs(ref).max()
+        print(f"grad {name}: rel {rel:.3e}, max/amax {amax:.3e}, |ref|max {np.abs(ref).max():.3e}")
+        assert rel <= 1e-3, name
+        assert amax <= 1e-2, name
+
+
+def test_autograd_function_and_lds_fallback(orc):
+    from paper_1903_07149_amd.soft import scalp_soft
+    W, H, k, B, T, iters = 80, 64, 20, 2, 2.0, 3
+    lab, con = _batch(B, (W, H), 6, 700)
+    rng = np.random.default_rng(5)
+    K = orc.grid(W, H, k).num_sp
+    gq = rng.normal(0, 1, (B, 9, H, W)).astype(np.float32)
+    gth = rng.normal(0, 1, (B, K, 5)).astype(np.float32)
+    glab_o, gcon_o = orc.soft_backward(lab, con, k, gq.transpose(0, 2, 3, 1), gth,
+                                       iterations=iters, T=T, d32=True)
+    results = []
+    for lds in (0, 1, 300):                       # default; no LDS halo; partial halo
+        eng = _engine(W, H, k, B, T, iters, lds_pixels=lds)
+        L = dev(lab).requires_grad_(True)
+        C = dev(con).requires_grad_(True)
+        say("autograd", lds)
+        q, th = scalp_soft(L, C, eng)
+        loss = (q * dev(gq)).sum() + (th * dev(gth)).sum()
+        loss.backward()
+        results.append((host(L.grad), host(C.grad)))
+    for glab, gcon in results:
+        assert np.linalg.norm(glab - glab_o) / np.linalg.norm(glab_o) <= 1e-3
+        assert np.linalg.norm(gcon - gcon_o) / np.linalg.norm(gcon_o) <= 1e-3
+
+
+def test_soft_low_temperature_is_hard(orc):
+    """Integer Lab on 4x4-pixel cells: T -> 0 gives one-hot Q at the hard assignment."""
+    from paper_1903_07149_amd.scalp import Scalp
+    W = H = 16
+    rng = np.random.default_rng(4)
+    lab = rng.integers(0, 60, (H, W, 3)).astype(np.float32)
+    con = (rng.integers(0, 5, (H, W)) / 4.0).astype(np.float32)
+    eng = _engine(W, H, 16, 1, 1e-3, 1)
+    say("soft T->0")
+    c_t, q_t, _ = eng.forward(dev(lab[None]), dev(con[None]))
+    s = Scalp(W, H, 16)
+    c0, e0, _ = s.init_grid(dev(lab), dev(con))
+    assert (host(c_t)[0, 0] == host(c0)).all()
+    hard = host(s.assign(dev(lab), dev(con), c0, e0))
+    g = orc.grid(W, H, 16)
+    yy, xx = np.mgrid[0:H, 0:W]
+    j = host(q_t)[0, 0].argmax(axis=0)
+    soft_lbl = (yy * g.ny // H + j // 3 - 1) * g.nx + (xx * g.nx // W + j % 3 - 1)
+    assert (soft_lbl == hard).all()
+
+
+def test_soft_full_size_workload(orc):
+    """The benchmark's soft workload (16 x 512x512, k = 400, T = 0.5, 5 iterations),
+    forward and backward in one launch configuration: invariants on the whole batch,
+    and image 3 of the batch against the oracle."""
+    orc.set_threads(min(16, os.cpu_count() or 1))
+    wls = synth.soft_workloads()
+    imgs = [synth.workload_image(w) for w in wls]
+    lab = np.stack([i.lab for i in imgs])
+    con = np.stack([i.contour for i in imgs])
+    L, C = dev(lab), dev(con)
+    rng = np.random.default_rng(9)
+    K = orc.grid(512, 512, 400).num_sp
+    gq = rng.normal(0, 1, (16, 9, 512, 512)).astype(np.float32)
+    gth = rng.normal(0, 1, (16, K, 5)).astype(np.float32)
+    eng = _engine(512, 512, 400, 16, 0.5, 5)
+    say("soft full size, 5 iterations")
+    c_t, q_t, saved = eng.forward(L, C)
+    glab, gcon = (host(t) for t in eng.backward(L, C, c_t, q_t, saved, dev(gq), dev(gth)))
+    c_t, q_t = host(c_t), host(q_t)
+    assert np.allclose(q_t.sum(axis=2), 1.0, atol=1e-5) and (q_t >= 0).all()
+    assert np.isfinite(glab).all() and np.isfinite(gcon).all()
+    assert (c_t[..., 3] >= 0).all() and (c_t[..., 3] <= 511).all()
+    assert (c_t[..., 4] >= 0).all() and (c_t[..., 4] <= 511).all()
+    i = 3
+    th_o, q_o, _ = orc.soft_forward(lab[i:i + 1], con[i:i + 1], 400, iterations=5, T=0.5, d32=True)
+    assert compare_forward(c_t[:, i:i + 1], q_t[:, i:i + 1], th_o, q_o, 512, 512) == 5
+    glab_o, gcon_o = orc.soft_backward(lab[i:i + 1], con[i:i + 1], 400,
+                                       gq[i:i + 1].transpose(0, 2, 3, 1), gth[i:i + 1],
+                                       iterations=5, T=0.5, d32=True)
+    for got, ref in ((glab[i:i + 1], glab_o), (gcon[i:i + 1], gcon_o)):
+        rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        print(f"full-size gradient relative error {rel:.3e}")
+        assert rel <= 1e-3

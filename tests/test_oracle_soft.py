@@ -111,3 +111,49 @@ def test_soft_forward_shapes_and_simplex(orc):
     assert np.allclose(z.sum(-1), 32 * 32)
     # corner pixels see only 4 of the 9 neighbours
     assert (q[:, :, 0, 0, [0, 1, 2, 3, 6]] == 0).all()
+
+
+def test_d32_mode_matches_fp64_and_hard(orc):
+    """The FP32-distance mode agrees with the all-FP64 mode to FP32 accuracy where
+    the problem is well conditioned (T = 50), and its first soft step at T -> 0 is
+    exactly the hard oracle's assignment."""
+    lab, con = _crop_batch(2)
+    k = 16
+    th64, q64, _ = orc.soft_forward(lab, con, k, iterations=2, T=50.0)
+    th32, q32, _ = orc.soft_forward(lab, con, k, iterations=2, T=50.0, d32=True)
+    assert np.abs(q64 - q32).max() < 1e-4
+    assert (np.abs(th64 - th32) / (np.abs(th64) + 1)).max() < 1e-4
+    assert (th32 == th32.astype(np.float32)).all() and (q32 == q32.astype(np.float32)).all()
+    g = orc.grid(32, 32, k)
+    rng = np.random.default_rng(3)
+    gq = rng.normal(0, 1, (2, 32, 32, 9))
+    gth = rng.normal(0, 1, (2, g.num_sp, 5))
+    a64 = orc.soft_backward(lab, con, k, gq, gth, iterations=2, T=50.0)
+    a32 = orc.soft_backward(lab, con, k, gq, gth, iterations=2, T=50.0, d32=True)
+    for x, y in zip(a64, a32):
+        assert np.linalg.norm(x - y) / np.linalg.norm(x) < 1e-3
+    # T -> 0 (FP64 exp underflows: Q is exactly one-hot) on the hard oracle's state
+    th, q, _ = orc.soft_forward(lab[:1], con[:1], k, iterations=1, T=1e-6, d32=True)
+    c0, e0, _ = orc.init_grid(g, lab[0])
+    assert (th[0, 0].astype(np.float32) == c0).all()
+    hard, _, _ = orc.assign(g, lab[0], orc.wmap(con[0]), c0, e0)
+    yy, xx = np.mgrid[0:32, 0:32]
+    j = q[0, 0].argmax(axis=-1)
+    lbl = (yy * g.ny // 32 + j // 3 - 1) * g.nx + (xx * g.nx // 32 + j % 3 - 1)
+    assert (lbl == hard).all()
+
+
+def test_tiny_mass_keeps_centre(orc):
+    """A superpixel whose soft mass falls below 1e-6 keeps its previous centre."""
+    W = H = 32                                     # 4 x 4 cells of 8 x 8
+    lab = np.full((H, W, 3), [50.0, 60.0, -60.0], np.float32)
+    lab[:, :12] = [50.0, -60.0, 60.0]              # colour edge through the middle of column 1
+    con = np.zeros((H, W), np.float32)
+    for d32 in (False, True):
+        th, q, z = orc.soft_forward(lab[None], con[None], 16, iterations=2, T=0.05, d32=d32)
+        # the cells of column 1 average both colours: every pixel is far closer to a pure
+        # neighbour, so their soft mass vanishes and they keep their centres
+        light = z[0, 0] < 1e-6
+        assert light.sum() == 4 and light.reshape(4, 4)[:, 1].all()
+        assert (th[1, 0][light] == th[0, 0][light]).all()
+        assert (z[0, 0][~light] > 1.0).all()
