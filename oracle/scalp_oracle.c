@@ -144,7 +144,7 @@ static float colour_dist(const float *f, const float *ck) {
 
 /* centre = {l, a, b, x, y}; (cx, cy) = endpoint of the path. */
 static float hard_distance(const hard_ctx *c, int x, int y, const float *centre,
-                           int cx, int cy, int *samples) {
+                           int cx, int cy, int *samples, float *A_out, float *B_out) {
     int dx = cx - x, dy = cy - y;
     int n = abs(dx) > abs(dy) ? abs(dx) : abs(dy);
     float sc = 0.0f, sw = 0.0f;
@@ -164,6 +164,8 @@ static float hard_distance(const hard_ctx *c, int x, int y, const float *centre,
     float ex = (float)x - centre[3];
     float ey = (float)y - centre[4];
     float ds = ex * ex + ey * ey;                        /* d_s, Sec. II-A */
+    if (A_out) *A_out = A;
+    if (B_out) *B_out = B;
     return A * B + ds * c->spw;                          /* Eq. (3) */
 }
 
@@ -173,21 +175,9 @@ float orc_distance_ab(int W, int H, const float *lab, const float *w, float lamb
                       float spw, int x, int y, const float *centre, int cx, int cy,
                       float *A_out, float *B_out, int *np1) {
     hard_ctx c = {W, H, lab, w, lambda, gamma, spw};
-    int dx = cx - x, dy = cy - y;
-    int n = abs(dx) > abs(dy) ? abs(dx) : abs(dy);
-    float D = hard_distance(&c, x, y, centre, cx, cy, NULL);
-    /* the factors, recomputed in the same order as in hard_distance */
-    float sc = 0.0f, sw = 0.0f;
-    for (int i = 0; i <= n; i++) {
-        long q = (long)(y + path_offset(i, n, dy)) * W + (x + path_offset(i, n, dx));
-        sc = sc + colour_dist(lab + 3 * q, centre);
-        sw = sw + w[q];
-    }
-    float dcp = colour_dist(lab + 3 * ((long)y * W + x), centre);
-    float np = (float)(n + 1);
-    *A_out = lambda * dcp + (1.0f - lambda) * (sc / np);
-    *B_out = 1.0f + gamma * (sw / np);
-    *np1 = n + 1;
+    int samples = 0;
+    float D = hard_distance(&c, x, y, centre, cx, cy, &samples, A_out, B_out);
+    *np1 = samples;
     return D;
 }
 
@@ -195,7 +185,7 @@ float orc_distance(int W, int H, const float *lab, const float *w,
                    float lambda, float gamma, float spw,
                    int x, int y, const float *centre, int cx, int cy) {
     hard_ctx c = {W, H, lab, w, lambda, gamma, spw};
-    return hard_distance(&c, x, y, centre, cx, cy, NULL);
+    return hard_distance(&c, x, y, centre, cx, cy, NULL, NULL, NULL);
 }
 
 /* ------------------------------------------------------------------ */
@@ -222,7 +212,7 @@ void orc_assign(int W, int H, int nx, int ny, const float *lab, const float *w,
                     int k = ii * nx + jj;
                     float D = hard_distance(&c, x, y, centres + 5 * (long)k,
                                             endpoints[2 * k], endpoints[2 * k + 1],
-                                            &samples);
+                                            &samples, NULL, NULL);
                     if (D < best) { best = D; bestk = k; }
                 }
             }
