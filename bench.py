@@ -28,6 +28,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -256,6 +258,59 @@ def bench_batched(torch, args):
             "single_path_ms": round(ms1, 3)}
 
 
+def bench_soft(torch, args):
+    from paper_1903_07149_amd import synth
+    from paper_1903_07149_amd.scalp import Scalp
+    from paper_1903_07149_amd.soft import SoftScalp
+
+    wls = synth.soft_workloads()
+    imgs = [synth.workload_image(w) for w in wls]
+    B, H, W, k, iters, T = len(wls), wls[0].height, wls[0].width, wls[0].k, wls[0].iterations, 0.5
+    lab = torch.from_numpy(np.stack([i.lab for i in imgs])).cuda()
+    con = torch.from_numpy(np.stack([i.contour for i in imgs])).cuda()
+    eng = SoftScalp(W, H, k, B, temperature=T, iterations=iters)
+    gen = torch.Generator(device="cuda").manual_seed(0)
+    gq = torch.randn((B, 9, H, W), device="cuda", generator=gen)
+    gth = torch.randn((B, eng.K, 5), device="cuda", generator=gen)
+    for _ in range(2):
+        c_t, q_t, saved = eng.forward(lab, con)
+        eng.backward(lab, con, c_t, q_t, saved, gq, gth)
+    torch.cuda.synchronize()
+    reps = 5
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(reps)]
+    for r in range(reps):
+        ev[r][0].record()
+        c_t, q_t, saved = eng.forward(lab, con)
+        ev[r][1].record()
+        eng.backward(lab, con, c_t, q_t, saved, gq, gth)
+        ev[r][2].record()
+    torch.cuda.synchronize()
+    fwd = sum(e[0].elapsed_time(e[1]) for e in ev) / reps
+    bwd = sum(e[1].elapsed_time(e[2]) for e in ev) / reps
+    # the hard path on the same 16 images (one by one, same k and iterations)
+    s = Scalp(W, H, k, iterations=iters)
+    outs = [s.new_state() for _ in range(B)]
+    for b in range(B):
+        s.run(lab[b], con[b], out=outs[b])
+    torch.cuda.synchronize()
+    h0 = torch.cuda.Event(enable_timing=True)
+    h1 = torch.cuda.Event(enable_timing=True)
+    h0.record()
+    for _ in range(reps):
+        for b in range(B):
+            s.run(lab[b], con[b], out=outs[b])
+    h1.record()
+    torch.cuda.synchronize()
+    hard = h0.elapsed_time(h1) / reps
+    px_it = B * H * W * iters
+    return {"workload": f"{B} x {W}x{H} Voronoi images, k={k}, T={T}, {iters} iterations",
+            "fwd_bwd_mpx_iter_s": round(px_it / ((fwd + bwd) * 1e-3) / 1e6, 1),
+            "fwd_ms": round(fwd, 3), "bwd_ms": round(bwd, 3),
+            "fwd_mpx_iter_s": round(px_it / (fwd * 1e-3) / 1e6, 1),
+            "hard_same_images_mpx_iter_s": round(px_it / (hard * 1e-3) / 1e6, 1),
+            "hard_same_images_ms": round(hard, 3)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -281,6 +336,8 @@ def main():
     if not args.no_extensions:
         log("batched")
         out["extensions"] = {"batched": bench_batched(torch, args)}
+        log("soft")
+        out["extensions"]["soft"] = bench_soft(torch, args)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(img, 2000, 10)
