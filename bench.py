@@ -82,15 +82,17 @@ def traffic_for(digest: str):
 
 
 def bench_hard(torch, args):
-    from paper_1903_07149_amd import counts, synth
+    from paper_1903_07149_amd import autotune, counts, synth
     from paper_1903_07149_amd.scalp import Scalp
 
     wl = synth.HD
     img = synth.workload_image(wl)
     H, W = img.contour.shape
-    s = Scalp(W, H, wl.k, iterations=wl.iterations)
     lab = torch.from_numpy(img.lab).cuda()
     con = torch.from_numpy(img.contour).cuda()
+    tuned = autotune.tune(W, H, wl.k, lab, con, use_cache=False)
+    log(f"autotuned launch shape: {tuned}")
+    s = Scalp(W, H, wl.k, iterations=wl.iterations, **tuned)
     c, e, l, n = s.new_state()
     iters = wl.iterations
 
@@ -160,7 +162,7 @@ def bench_hard(torch, args):
     traffic = traffic_for(digest)
     roofline = {
         "bound": "alu",
-        "kernel": "k_assign<256,true> (fused assignment + update sums)",
+        "kernel": f"k_assign<{s.params.wg_size},true> (fused assignment + update sums)",
         "achieved": round(achieved, 3),
         "peak": round(VALU_FP32_PEAK_TFLOPS, 2),
         "unit": "TFLOP/s",
@@ -182,11 +184,11 @@ def bench_hard(torch, args):
             dst.copy_(src)
         torch.cuda.synchronize()
         log("copy probe: 3 x 512 MiB device copies")
-    return img, {
+    return img, tuned, {
         "value": value, "ms_per_step": ms_step, "graph_ms_per_step": graph_ms,
         "graph_value": N * iters / (graph_ms * 1e-3) / 1e6, "roofline": roofline,
         "config": {"workload": wl.name, "width": W, "height": H, "k": wl.k,
-                   "num_sp": s.grid.num_sp, "iterations": iters,
+                   "num_sp": s.grid.num_sp, "iterations": iters, "launch": tuned,
                    "step": "pack + grid init + 10 x (fused assign/update, finalize/projection)"},
     }
 
@@ -210,13 +212,13 @@ def cpu_baseline(img, k, iters):
                       f"{el:.1f} s on {threads} OpenMP threads"}
 
 
-def bench_batched(torch, args):
+def bench_batched(torch, args, tuned):
     from paper_1903_07149_amd import synth
     from paper_1903_07149_amd.scalp import Scalp, ScalpBatch
 
     wls = synth.batch_workloads()
     imgs = [synth.workload_image(w) for w in wls]
-    b = ScalpBatch([(w.width, w.height, w.k) for w in wls], iterations=10)
+    b = ScalpBatch([(w.width, w.height, w.k) for w in wls], iterations=10, **tuned)
     lab = torch.cat([torch.from_numpy(i.lab.reshape(-1, 3)) for i in imgs]).cuda()
     con = torch.cat([torch.from_numpy(i.contour.reshape(-1)) for i in imgs]).cuda()
     st = b.new_state()
@@ -237,7 +239,7 @@ def bench_batched(torch, args):
     # the same images, one by one, through the single-image path
     singles = []
     for w, i in zip(wls, imgs):
-        s = Scalp(w.width, w.height, w.k, iterations=10)
+        s = Scalp(w.width, w.height, w.k, iterations=10, **tuned)
         singles.append((s, torch.from_numpy(i.lab).cuda(), torch.from_numpy(i.contour).cuda(),
                         s.new_state()))
     for s, la, co, out in singles:
@@ -323,7 +325,7 @@ def main():
         print("bench.py needs a GPU (torch.cuda.is_available() is False)", file=sys.stderr)
         sys.exit(1)
     log("hard SCALP, 1920x1080, k=2000, 10 iterations")
-    img, hard = bench_hard(torch, args)
+    img, tuned, hard = bench_hard(torch, args)
     out = {
         "metric": METRIC, "value": round(hard["value"], 1), "unit": "Mpixel-iter/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -335,7 +337,7 @@ def main():
     }
     if not args.no_extensions:
         log("batched")
-        out["extensions"] = {"batched": bench_batched(torch, args)}
+        out["extensions"] = {"batched": bench_batched(torch, args, tuned)}
         log("soft")
         out["extensions"]["soft"] = bench_soft(torch, args)
     if not args.no_cpu_baseline:

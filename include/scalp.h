@@ -74,7 +74,7 @@ typedef struct {
     int32_t lds_pixels;      /* tuning: LDS halo budget in pixels (16 B each),
                                 0..9728; 0 selects the default (4800)        */
     int32_t wg_size;         /* tuning: assignment workgroup size, 0 (default
-                                256), 256 or 512                             */
+                                1024), 256, 512 or 1024                      */
 } scalp_params_t;
 
 /* Fills the paper's defaults (Sec. III-A.3: m = 10, lambda = 0.5,

@@ -1,0 +1,75 @@
+"""Autotuner for the assignment kernel's launch shape.
+
+Two knobs change speed but never results (every configuration is checked
+bit-exact against the oracle by the GPU tests): the workgroup size (waves
+sharing one grid cell's LDS halo) and the LDS halo budget in texels (which
+bounds how many candidate endpoints a cell can stage, and how many
+workgroups fit on a CU).  The tuner times one fused assignment pass
+(`scalp_assign_accumulate`) per configuration with HIP events on the
+workload's own image and superpixel state, and caches the winner in a JSON
+file keyed by device architecture and workload shape.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+import torch
+
+from .scalp import Scalp
+
+CANDIDATES = [dict(wg_size=w, lds_pixels=p) for w in (256, 512, 1024)
+              for p in (1, 1600, 2400, 3200, 4800)]
+CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_cache.json")
+
+
+def _key(width: int, height: int, k: int) -> str:
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    return f"{arch}/{width}x{height}/k{k}"
+
+
+def time_config(s: Scalp, lab, contour, cfg: dict, reps: int = 5, warm_iters: int = 3) -> float:
+    """Average milliseconds of one fused assignment pass with `cfg`, from the
+    superpixel state after `warm_iters` iterations."""
+    c, e, l, n = s.new_state()
+    s.init_grid(lab, contour, out=(c, e, l))
+    for _ in range(warm_iters):
+        s.assign_accumulate(c, e, l)
+        s.finalize(l, c, e, n)
+    s.assign_accumulate(c, e, l, **cfg)          # warm-up launch of this shape
+    s.finalize(l, c.clone(), e.clone(), n)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(reps)]
+    for a, b in ev:
+        a.record()
+        s.assign_accumulate(c, e, l, **cfg)
+        b.record()
+        s.finalize(l, c.clone(), e.clone(), n)   # clears the sums; state stays fixed
+    torch.cuda.synchronize()
+    return sum(a.elapsed_time(b) for a, b in ev) / reps
+
+
+def tune(width: int, height: int, k: int, lab, contour, candidates=None, use_cache=True,
+         verbose=False) -> dict:
+    key = _key(width, height, k)
+    cache = {}
+    if use_cache and os.path.exists(CACHE):
+        with open(CACHE) as f:
+            cache = json.load(f)
+        if key in cache:
+            return cache[key]["best"]
+    s = Scalp(width, height, k)
+    results = []
+    for cfg in candidates or CANDIDATES:
+        ms = time_config(s, lab, contour, cfg)
+        results.append((ms, cfg))
+        if verbose:
+            print(f"[autotune] {key} {cfg}: {ms:.4f} ms")
+    results.sort(key=lambda r: r[0])
+    best = results[0][1]
+    cache[key] = {"best": best, "ms": results[0][0],
+                  "all": [{"cfg": c, "ms": m} for m, c in results]}
+    if use_cache:
+        with open(CACHE, "w") as f:
+            json.dump(cache, f, indent=1)
+    return best

@@ -39,13 +39,14 @@ bool params_valid(const scalp_params_t* p) {
     if (!std::isfinite(p->gamma)) return false;
     if (p->iterations < 0) return false;
     if (p->lds_pixels < 0 || p->lds_pixels > kMaxLdsPixels) return false;
-    if (p->wg_size != 0 && p->wg_size != 256 && p->wg_size != 512) return false;
+    if (p->wg_size != 0 && p->wg_size != 256 && p->wg_size != 512 && p->wg_size != 1024)
+        return false;
     return true;
 }
 
 Tuning tuning_of(const scalp_params_t* p) {
     Tuning t;
-    t.wg = p->wg_size == 512 ? 512 : 256;
+    t.wg = p->wg_size == 0 ? 1024 : p->wg_size;
     t.lds_pixels = p->lds_pixels > 0 ? p->lds_pixels : default_lds_pixels();
     return t;
 }

@@ -27,7 +27,8 @@ __device__ __forceinline__ long long to_fixed(float v) {
 // Accumulates the samples i = 1 .. n-1 of the path from the pixel at linear
 // index `idx` toward (dx, dy): on major-axis step i the minor offset is
 // floor((2 i |d_minor| + n) / (2 n)), kept incrementally as a remainder.
-// stepx / stepy are the index strides of one pixel in x / y.
+// stepx / stepy are the index strides of one pixel in x / y.  (Global-memory
+// variant, used when a candidate's endpoint lies outside the LDS halo.)
 __device__ __forceinline__ void walk_path(const float4* __restrict__ base, int idx, int stepx,
                                           int stepy, int dx, int dy, float l, float a, float b,
                                           float& sc, float& sw) {
@@ -56,6 +57,68 @@ __device__ __forceinline__ void walk_path(const float4* __restrict__ base, int i
         sc = sc + dc;
         sw = sw + f.w;
     }
+}
+
+// The same walk over the LDS halo.  The remainder is kept biased by -2n in
+// 32-bit unsigned arithmetic, so the minor-axis step is exactly the carry of
+// "remainder + 2|d_minor|" (one add with carry-out, two selects, two adds
+// per sample).  The loop is unrolled by two with the texel of the next
+// sample loaded before the current one is accumulated, so each LDS load has
+// a sample's worth of work to hide behind.
+__device__ __forceinline__ void walk_path_lds(const float4* lds, int idx, int rw, int dx, int dy,
+                                              float l, float a, float b, float& sc, float& sw) {
+    const int adx = dx < 0 ? -dx : dx;
+    const int ady = dy < 0 ? -dy : dy;
+    const bool xmaj = adx >= ady;
+    const int n = xmaj ? adx : ady;
+    if (n < 2) return;
+    const unsigned am = (unsigned)(xmaj ? ady : adx);
+    const int sx = dx < 0 ? -16 : 16;
+    const int sy = dy < 0 ? -16 * rw : 16 * rw;
+    const int smaj = xmaj ? sx : sy;
+    const int sdiag = smaj + (xmaj ? sy : sx);
+    const unsigned inc = 2u * am;
+    const unsigned bias = 0u - 2u * (unsigned)n;          // 2^32 - 2n
+    unsigned e = 0u - (unsigned)n;                        // remainder n, biased
+    const char* q = reinterpret_cast<const char*>(lds + idx);
+#define SCALP_STEP()                                              \
+    do {                                                          \
+        unsigned t_;                                              \
+        const bool c_ = __builtin_add_overflow(e, inc, &t_);      \
+        e = t_ + (c_ ? bias : 0u);                                \
+        q += c_ ? sdiag : smaj;                                   \
+    } while (0)
+#define SCALP_ACC(f)                                              \
+    do {                                                          \
+        const float dl_ = (f).x - l;                              \
+        const float da_ = (f).y - a;                              \
+        const float db_ = (f).z - b;                              \
+        const float dc_ = (dl_ * dl_ + da_ * da_) + db_ * db_;    \
+        sc = sc + dc_;                                            \
+        sw = sw + (f).w;                                          \
+    } while (0)
+    SCALP_STEP();
+    float4 fa = *reinterpret_cast<const float4*>(q);      // sample 1
+    int left = n - 2;                                      // samples 2 .. n-1 still to load
+    while (left >= 2) {
+        SCALP_STEP();
+        const float4 fb = *reinterpret_cast<const float4*>(q);
+        SCALP_ACC(fa);
+        SCALP_STEP();
+        fa = *reinterpret_cast<const float4*>(q);
+        SCALP_ACC(fb);
+        left -= 2;
+    }
+    if (left == 1) {
+        SCALP_STEP();
+        const float4 fb = *reinterpret_cast<const float4*>(q);
+        SCALP_ACC(fa);
+        SCALP_ACC(fb);
+    } else {
+        SCALP_ACC(fa);
+    }
+#undef SCALP_STEP
+#undef SCALP_ACC
 }
 
 __device__ __forceinline__ int round_coord(float v, int hi) {

@@ -149,7 +149,7 @@ __device__ __forceinline__ void process_cell(const Img& im, int cell,
             float sc = dcp;      // sample i = 0 is p itself
             float sw = fp.w;
             if (sh.cand[j].staged)
-                walk_path(lds, lidx, 1, rw, dx, dy, l, a, b, sc, sw);
+                walk_path_lds(lds, lidx, rw, dx, dy, l, a, b, sc, sw);
             else
                 walk_path(img, p, 1, W, dx, dy, l, a, b, sc, sw);
             const int adx = dx < 0 ? -dx : dx, ady = dy < 0 ? -dy : dy;
@@ -555,8 +555,11 @@ void lift_lds_limits() {
     allow_lds(k_assign<256, false>, cap);
     allow_lds(k_assign<512, true>, cap);
     allow_lds(k_assign<512, false>, cap);
+    allow_lds(k_assign<1024, true>, cap);
+    allow_lds(k_assign<1024, false>, cap);
     allow_lds(k_assign_persistent<256>, cap);
     allow_lds(k_assign_persistent<512>, cap);
+    allow_lds(k_assign_persistent<1024>, cap);
 }
 
 int launch_prepare(long long n, const float* lab, const float* contour, float sigma,
@@ -602,6 +605,11 @@ static int launch_assign_t(const Img& im, const float4* packed, const float* cen
 int launch_assign(const Img& im, const float4* packed, const float* centres,
                   const int* endpoints, int* labels, long long* acc, int* ctrl, float lambda,
                   bool accumulate, const Tuning& t, hipStream_t s) {
+    if (t.wg == 1024)
+        return accumulate ? launch_assign_t<1024, true>(im, packed, centres, endpoints, labels,
+                                                        acc, ctrl, lambda, t, s)
+                          : launch_assign_t<1024, false>(im, packed, centres, endpoints, labels,
+                                                         acc, ctrl, lambda, t, s);
     if (t.wg == 512)
         return accumulate ? launch_assign_t<512, true>(im, packed, centres, endpoints, labels, acc,
                                                        ctrl, lambda, t, s)
@@ -628,6 +636,9 @@ int launch_assign_persistent(const Img* imgs, const int* cell_start, int n_img, 
                              const float4* packed, const float* centres, const int* endpoints,
                              int* labels, long long* acc, int* ctrl, float lambda,
                              const Tuning& t, int grid, hipStream_t s) {
+    if (t.wg == 1024)
+        return launch_persistent_t<1024>(imgs, cell_start, n_img, total_cells, packed, centres,
+                                         endpoints, labels, acc, ctrl, lambda, t, grid, s);
     if (t.wg == 512)
         return launch_persistent_t<512>(imgs, cell_start, n_img, total_cells, packed, centres,
                                         endpoints, labels, acc, ctrl, lambda, t, grid, s);
@@ -641,7 +652,10 @@ int persistent_grid(const Tuning& t) {
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return -1;
     hipError_t e;
-    if (t.wg == 512)
+    if (t.wg == 1024)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_assign_persistent<1024>, 1024,
+                                                         dyn_lds(t));
+    else if (t.wg == 512)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_assign_persistent<512>, 512,
                                                          dyn_lds(t));
     else

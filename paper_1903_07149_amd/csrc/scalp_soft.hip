@@ -194,7 +194,7 @@ __global__ __launch_bounds__(WG) void k_soft_assign(SoftImg s, const float4* __r
             const float dcp = colour_dist(fp, l, a, bb);
             float sc = dcp, sw = fp.w;
             if (sh.cand[j].staged)
-                walk_path(lds_dyn, lidx, 1, rw, dx, dy, l, a, bb, sc, sw);
+                walk_path_lds(lds_dyn, lidx, rw, dx, dy, l, a, bb, sc, sw);
             else
                 walk_path(img, p, 1, W, dx, dy, l, a, bb, sc, sw);
             const int adx = dx < 0 ? -dx : dx, ady = dy < 0 ? -dy : dy;

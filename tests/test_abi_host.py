@@ -67,7 +67,7 @@ def test_bad_arguments_are_rejected_on_host():
     assert lib.scalp_assign(ctypes.byref(g), ctypes.byref(p), fake, fake, fake, fake, fake,
                             None, ws, None) == L.SCALP_ERR_WORKSPACE
     for field, val in [("lambda_", 1.5), ("lambda_", -0.1), ("sigma", 0.0), ("m", -1.0),
-                       ("iterations", -1), ("lds_pixels", 100000), ("wg_size", 128),
+                       ("iterations", -1), ("lds_pixels", 100000), ("wg_size", 128), ("wg_size", 768),
                        ("gamma", float("nan"))]:
         pp = L.default_params(**{field: val})
         assert lib.scalp_assign(*args(g, pp, ws)) == L.SCALP_ERR_ARG, field

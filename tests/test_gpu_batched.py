@@ -16,7 +16,8 @@ def _batch(n, seed0, lo, hi, per_px):
     return synth.batch_workloads(n=n, seed0=seed0, lo=lo, hi=hi, per_px=per_px)
 
 
-@pytest.mark.parametrize("tune", [dict(), dict(wg_size=512), dict(lds_pixels=700)])
+@pytest.mark.parametrize("tune", [dict(), dict(wg_size=256), dict(wg_size=512),
+                                  dict(lds_pixels=700)])
 def test_batched_equals_single_and_oracle(orc, tune):
     from paper_1903_07149_amd.scalp import Scalp, ScalpBatch
     orc.set_threads(min(16, os.cpu_count() or 1))
