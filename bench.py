@@ -44,7 +44,8 @@ HBM_PEAK_GBPS = 8000.0
 LDS_PEAK_TBPS = 256 * 128 * 2.4e9 / 1e12
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "assign_hd_traffic.json")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1903_07149_amd", "csrc", "scalp_kernels.hip")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1903_07149_amd", "csrc", f)
+                  for f in ("scalp_kernels.hip", "scalp_device.h", "scalp_internal.h")]
 
 
 def log(*a):
@@ -52,8 +53,13 @@ def log(*a):
 
 
 def source_digest() -> str:
-    with open(KERNEL_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Fingerprint of the assignment kernel's sources (the traffic figures taken
+    with hardware counters are only reported while it matches)."""
+    h = hashlib.sha256()
+    for path in KERNEL_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def parse():
@@ -65,6 +71,8 @@ def parse():
     ap.add_argument("--no-extensions", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 512 MiB device copy (counter calibration)")
+    ap.add_argument("--launch", default=None,
+                    help="WG,LDS_PIXELS: fixed assignment launch shape instead of autotuning")
     return ap.parse_args()
 
 
@@ -90,8 +98,13 @@ def bench_hard(torch, args):
     H, W = img.contour.shape
     lab = torch.from_numpy(img.lab).cuda()
     con = torch.from_numpy(img.contour).cuda()
-    tuned = autotune.tune(W, H, wl.k, lab, con, use_cache=False)
-    log(f"autotuned launch shape: {tuned}")
+    if args.launch:
+        wg, ldsp = (int(v) for v in args.launch.split(","))
+        tuned = {"wg_size": wg, "lds_pixels": ldsp}
+        log(f"fixed launch shape: {tuned}")
+    else:
+        tuned = autotune.tune(W, H, wl.k, lab, con, use_cache=False)
+        log(f"autotuned launch shape: {tuned}")
     s = Scalp(W, H, wl.k, iterations=wl.iterations, **tuned)
     c, e, l, n = s.new_state()
     iters = wl.iterations

@@ -450,13 +450,24 @@ __device__ void project_one(const Img& im, int k, const float* __restrict__ cent
     const int bw = X1 - X0, area = bw * (Y1 - Y0);
     unsigned long long best = ~0ULL;
     int found = 0;
-    for (int e = tid; e < area; e += WG) {
-        const int r = e / bw;
-        const int x = X0 + (e - r * bw), y = Y0 + r;
-        if (lb[(long long)y * W + x] == k) {
-            ++found;
-            const unsigned long long key = proj_key(x, y, W, xk, yk);
-            best = key < best ? key : best;
+    // four independent label loads in flight per thread per round
+    for (int e0 = tid; e0 < area; e0 += 4 * WG) {
+        int lbl[4], xs[4], ys[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = e0 + u * WG;
+            const int r = e / bw;
+            xs[u] = X0 + (e - r * bw);
+            ys[u] = Y0 + r;
+            lbl[u] = e < area ? lb[(long long)ys[u] * W + xs[u]] : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (lbl[u] == k) {
+                ++found;
+                const unsigned long long key = proj_key(xs[u], ys[u], W, xk, yk);
+                best = key < best ? key : best;
+            }
         }
     }
     block_min_sum<WG>(best, found);
@@ -518,6 +529,7 @@ __global__ void k_write_bytes(unsigned char* __restrict__ dst, ByteChunk c) {
 }
 
 constexpr int kSmallWG = 256;
+constexpr int kProjectWG = 1024;
 constexpr int kProjectBlocks = 256;
 
 size_t dyn_lds(const Tuning& t) { return (size_t)t.lds_pixels * sizeof(float4); }
@@ -692,7 +704,7 @@ int launch_finalize_batched(const Img* imgs, const int* sp_start, int n_img, int
 
 int launch_project(const Img& im, const float* centres, const int* counts, const int* labels,
                    int* endpoints, const int* ctrl, const int* plist, hipStream_t s) {
-    hipLaunchKernelGGL(k_project<kSmallWG>, dim3(kProjectBlocks), dim3(kSmallWG), 0, s, im,
+    hipLaunchKernelGGL(k_project<kProjectWG>, dim3(kProjectBlocks), dim3(kProjectWG), 0, s, im,
                        centres, counts, labels, endpoints, ctrl, plist);
     return hipGetLastError();
 }
@@ -700,7 +712,7 @@ int launch_project(const Img& im, const float* centres, const int* counts, const
 int launch_project_batched(const Img* imgs, const int* sp_start, int n_img, const float* centres,
                            const int* counts, const int* labels, int* endpoints,
                            const int* ctrl, const int* plist, hipStream_t s) {
-    hipLaunchKernelGGL(k_project_batched<kSmallWG>, dim3(kProjectBlocks), dim3(kSmallWG), 0, s,
+    hipLaunchKernelGGL(k_project_batched<kProjectWG>, dim3(kProjectBlocks), dim3(kProjectWG), 0, s,
                        imgs, sp_start, n_img, centres, counts, labels, endpoints, ctrl, plist);
     return hipGetLastError();
 }
