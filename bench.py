@@ -45,7 +45,7 @@ LDS_PEAK_TBPS = 256 * 128 * 2.4e9 / 1e12
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "assign_hd_traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1903_07149_amd", "csrc", f)
-                  for f in ("scalp_kernels.hip", "scalp_device.h", "scalp_internal.h")]
+                  for f in ("scalp_kernels.hip", "scalp_device.h")]
 
 
 def log(*a):
@@ -283,10 +283,30 @@ def bench_soft(torch, args):
     B, H, W, k, iters, T = len(wls), wls[0].height, wls[0].width, wls[0].k, wls[0].iterations, 0.5
     lab = torch.from_numpy(np.stack([i.lab for i in imgs])).cuda()
     con = torch.from_numpy(np.stack([i.contour for i in imgs])).cuda()
-    eng = SoftScalp(W, H, k, B, temperature=T, iterations=iters)
     gen = torch.Generator(device="cuda").manual_seed(0)
     gq = torch.randn((B, 9, H, W), device="cuda", generator=gen)
-    gth = torch.randn((B, eng.K, 5), device="cuda", generator=gen)
+    K = SoftScalp(W, H, k, 1, temperature=T, iterations=1).K
+    gth = torch.randn((B, K, 5), device="cuda", generator=gen)
+
+    def fwd_bwd_ms(e):
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record()
+        c_t, q_t, saved = e.forward(lab, con)
+        e.backward(lab, con, c_t, q_t, saved, gq, gth)
+        t1.record()
+        torch.cuda.synchronize()
+        return t0.elapsed_time(t1)
+
+    # workgroup size of the soft path kernels: timed once per candidate
+    shapes = []
+    for wg in (256, 512, 1024):
+        e = SoftScalp(W, H, k, B, temperature=T, iterations=iters, wg_size=wg)
+        fwd_bwd_ms(e)
+        shapes.append((fwd_bwd_ms(e), wg))
+        del e
+    soft_wg = min(shapes)[1]
+    eng = SoftScalp(W, H, k, B, temperature=T, iterations=iters, wg_size=soft_wg)
     for _ in range(2):
         c_t, q_t, saved = eng.forward(lab, con)
         eng.backward(lab, con, c_t, q_t, saved, gq, gth)
@@ -319,6 +339,7 @@ def bench_soft(torch, args):
     hard = h0.elapsed_time(h1) / reps
     px_it = B * H * W * iters
     return {"workload": f"{B} x {W}x{H} Voronoi images, k={k}, T={T}, {iters} iterations",
+            "wg_size": soft_wg,
             "fwd_bwd_mpx_iter_s": round(px_it / ((fwd + bwd) * 1e-3) / 1e6, 1),
             "fwd_ms": round(fwd, 3), "bwd_ms": round(bwd, 3),
             "fwd_mpx_iter_s": round(px_it / (fwd * 1e-3) / 1e6, 1),

@@ -83,10 +83,11 @@ int persistent_grid(const Tuning& t);
 // ---- soft SCALP (scalp_soft.hip)
 struct SoftGeom {
     int W, H, nx, ny, B;
+    int wg;   // workgroup size of the path kernels (256, 512 or 1024)
     float spw, gamma, lambda, temperature;
 };
 SoftGeom soft_geom(int W, int H, int nx, int ny, int B, float spw, float gamma, float lambda,
-                   float temperature);
+                   float temperature, int wg);
 void lift_soft_lds_limits();
 int launch_soft_init(const SoftGeom& g, const float4* packed, float* theta0, hipStream_t st);
 int launch_soft_assign(const SoftGeom& g, const float4* packed, const float* theta_prev, float* q,

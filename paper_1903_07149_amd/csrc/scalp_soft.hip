@@ -181,14 +181,16 @@ __global__ __launch_bounds__(WG) void k_soft_assign(SoftImg s, const float4* __r
         const int p = y * W + x;
         const float4 fp = img[p];
         const int lidx = (y - ry0) * rw + (x - rx0);
-        float D[9], Av[9], Bv[9];
-        float dmin = INFINITY;
-#pragma unroll
+        // D of each slot goes to the Q buffer (k_soft_softmax turns it into
+        // Q); A and B go straight to the saved factors.
+#pragma unroll 1
         for (int j = 0; j < 9; ++j) {
-            D[j] = INFINITY;
-            Av[j] = 0.0f;
-            Bv[j] = 0.0f;
-            if (sh.cand[j].k < 0) continue;
+            const long long o = base + (long long)j * s.N + p;
+            if (sh.cand[j].k < 0) {
+                fa[o] = 0.0f;
+                fb[o] = 0.0f;
+                continue;
+            }
             const float l = sh.cand[j].l, a = sh.cand[j].a, bb = sh.cand[j].b;
             const int dx = sh.cand[j].cx - x, dy = sh.cand[j].cy - y;
             const float dcp = colour_dist(fp, l, a, bb);
@@ -207,26 +209,46 @@ __global__ __launch_bounds__(WG) void k_soft_assign(SoftImg s, const float4* __r
             const float A = lambda * dcp + oml * (sc / np);
             const float Bw = 1.0f + s.gamma * (sw / np);
             const float ex = (float)x - sh.cand[j].x, ey = (float)y - sh.cand[j].y;
-            D[j] = A * Bw + (ex * ex + ey * ey) * s.spw;
-            Av[j] = A;
-            Bv[j] = Bw;
+            const float D = A * Bw + (ex * ex + ey * ey) * s.spw;
+            q[o] = D;
+            fa[o] = A;
+            fb[o] = Bw;
+        }
+    }
+}
+
+// Q_pj = softmax_j(-D_pj / T) in FP64 over the slots inside the grid, rounded
+// once to FP32 (the FP32 distances differ by far more than FP32's exponent
+// range allows at small T).  In place over the D values.  A separate kernel
+// so that the FP64 exponentials do not raise the register count of the path
+// walk.
+__global__ void k_soft_softmax(SoftImg s, float* __restrict__ q) {
+    const long long total = (long long)s.B * s.N;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int b = (int)(i / s.N);
+        const long long p = i - (long long)b * s.N;
+        const int y = (int)(p / s.W), x = (int)(p - (long long)y * s.W);
+        const int ci = (int)(((long long)y * s.ny) / s.H), cj = (int)(((long long)x * s.nx) / s.W);
+        const long long base = 9LL * s.N * b + p;
+        float D[9];
+        bool ok[9];
+        float dmin = INFINITY;
+#pragma unroll
+        for (int j = 0; j < 9; ++j) {
+            const int ii = ci + j / 3 - 1, jj = cj + j % 3 - 1;
+            ok[j] = ii >= 0 && ii < s.ny && jj >= 0 && jj < s.nx;
+            D[j] = ok[j] ? q[base + (long long)j * s.N] : INFINITY;
             dmin = fminf(dmin, D[j]);
         }
-        // softmax in FP64 (the FP32 distances differ by far more than FP32's
-        // exponent range allows at small T), rounded once to FP32
         double e[9], sum = 0.0;
 #pragma unroll
         for (int j = 0; j < 9; ++j) {
-            e[j] = sh.cand[j].k < 0 ? 0.0 : exp(-((double)D[j] - (double)dmin) / s.temp);
+            e[j] = ok[j] ? exp(-((double)D[j] - (double)dmin) / s.temp) : 0.0;
             sum += e[j];
         }
 #pragma unroll
-        for (int j = 0; j < 9; ++j) {
-            const long long o = base + (long long)j * s.N + p;
-            q[o] = (float)(e[j] / sum);
-            fa[o] = Av[j];
-            fb[o] = Bv[j];
-        }
+        for (int j = 0; j < 9; ++j) q[base + (long long)j * s.N] = (float)(e[j] / sum);
     }
 }
 
@@ -560,9 +582,9 @@ unsigned grid_for(long long n) {
 }  // namespace
 
 SoftGeom soft_geom(int W, int H, int nx, int ny, int B, float spw, float gamma, float lambda,
-                   float temperature) {
+                   float temperature, int wg) {
     SoftGeom g;
-    g.W = W; g.H = H; g.nx = nx; g.ny = ny; g.B = B;
+    g.W = W; g.H = H; g.nx = nx; g.ny = ny; g.B = B; g.wg = wg;
     g.spw = spw; g.gamma = gamma; g.lambda = lambda; g.temperature = temperature;
     return g;
 }
@@ -578,8 +600,12 @@ static SoftImg to_img(const SoftGeom& g) {
 
 void lift_soft_lds_limits() {
     const size_t cap = 160 * 1024 - sizeof(SoftShared) - 64;
-    for (const void* k : {reinterpret_cast<const void*>(k_soft_assign<kSoftWG>),
-                          reinterpret_cast<const void*>(k_soft_bwd_path<kSoftWG>)}) {
+    for (const void* k : {reinterpret_cast<const void*>(k_soft_assign<256>),
+                          reinterpret_cast<const void*>(k_soft_assign<512>),
+                          reinterpret_cast<const void*>(k_soft_assign<1024>),
+                          reinterpret_cast<const void*>(k_soft_bwd_path<256>),
+                          reinterpret_cast<const void*>(k_soft_bwd_path<512>),
+                          reinterpret_cast<const void*>(k_soft_bwd_path<1024>)}) {
         static_cast<void>(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                               (int)cap));
         static_cast<void>(hipGetLastError());
@@ -593,11 +619,23 @@ int launch_soft_init(const SoftGeom& g, const float4* packed, float* theta0, hip
     return hipGetLastError();
 }
 
+template <int WG>
+static int soft_assign_t(const SoftImg& s, const float4* packed, const float* theta_prev, float* q,
+                         float* fa, float* fb, int cap, hipStream_t st) {
+    hipLaunchKernelGGL(k_soft_assign<WG>, dim3(s.B * s.K), dim3(WG), (size_t)cap * sizeof(float4),
+                       st, s, packed, theta_prev, q, fa, fb, cap);
+    return hipGetLastError();
+}
+
 int launch_soft_assign(const SoftGeom& g, const float4* packed, const float* theta_prev, float* q,
                        float* fa, float* fb, int cap, hipStream_t st) {
     const SoftImg s = to_img(g);
-    hipLaunchKernelGGL(k_soft_assign<kSoftWG>, dim3(s.B * s.K), dim3(kSoftWG),
-                       (size_t)cap * sizeof(float4), st, s, packed, theta_prev, q, fa, fb, cap);
+    int e;
+    if (g.wg == 1024) e = soft_assign_t<1024>(s, packed, theta_prev, q, fa, fb, cap, st);
+    else if (g.wg == 512) e = soft_assign_t<512>(s, packed, theta_prev, q, fa, fb, cap, st);
+    else e = soft_assign_t<256>(s, packed, theta_prev, q, fa, fb, cap, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_soft_softmax, dim3(grid_for(s.B * s.N)), dim3(256), 0, st, s, q);
     return hipGetLastError();
 }
 
@@ -626,14 +664,25 @@ int launch_soft_bwd_pass(const SoftGeom& g, const double* z, const float* gth, f
     return hipGetLastError();
 }
 
+template <int WG>
+static int soft_bwd_path_t(const SoftImg& s, const float4* packed, const float* theta_prev,
+                           const float* fa, const float* fb, const float* gd, float4* gf,
+                           float* gth_prev, int cap, hipStream_t st) {
+    hipLaunchKernelGGL(k_soft_bwd_path<WG>, dim3(s.B * s.K), dim3(WG),
+                       (size_t)cap * (sizeof(float4) + sizeof(float)), st, s, packed, theta_prev,
+                       fa, fb, gd, gf, gth_prev, cap);
+    return hipGetLastError();
+}
+
 int launch_soft_bwd_path(const SoftGeom& g, const float4* packed, const float* theta_prev,
                          const float* fa, const float* fb, const float* gd, float4* gf,
                          float* gth_prev, int cap, hipStream_t st) {
     const SoftImg s = to_img(g);
-    hipLaunchKernelGGL(k_soft_bwd_path<kSoftWG>, dim3(s.B * s.K), dim3(kSoftWG),
-                       (size_t)cap * (sizeof(float4) + sizeof(float)), st, s, packed, theta_prev,
-                       fa, fb, gd, gf, gth_prev, cap);
-    return hipGetLastError();
+    if (g.wg == 1024)
+        return soft_bwd_path_t<1024>(s, packed, theta_prev, fa, fb, gd, gf, gth_prev, cap, st);
+    if (g.wg == 512)
+        return soft_bwd_path_t<512>(s, packed, theta_prev, fa, fb, gd, gf, gth_prev, cap, st);
+    return soft_bwd_path_t<256>(s, packed, theta_prev, fa, fb, gd, gf, gth_prev, cap, st);
 }
 
 int launch_soft_bwd_finish(const SoftGeom& g, const float4* gf, const float* gth0,
