@@ -41,7 +41,7 @@ def hipcc() -> str:
 
 
 def sources() -> list[str]:
-    return [os.path.join(CSRC, s) for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+    return [os.path.join(CSRC, s) for s in SOURCES]
 
 
 def build(verbose: bool = False, extra: list[str] | None = None, out: str = LIB) -> str:
@@ -54,6 +54,22 @@ def build(verbose: bool = False, extra: list[str] | None = None, out: str = LIB)
     subprocess.run(cmd, check=True)
     os.replace(tmp, out)
     return out
+
+
+PROBE_SRC = os.path.join(CSRC, "peaks_probe.hip")
+PROBE_BIN = os.path.join(HERE, "peaks_probe")
+
+
+def build_probe(verbose: bool = False) -> str:
+    """Compile the peak-rate microbenchmark (always recompiles)."""
+    flags = [f for f in HIPCC_FLAGS if f not in ("-shared", "-fPIC")]
+    tmp = PROBE_BIN + ".tmp"
+    cmd = [hipcc(), *flags, PROBE_SRC, "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, PROBE_BIN)
+    return PROBE_BIN
 
 
 def disassemble(out_dir: str) -> list[str]:
@@ -71,5 +87,6 @@ def disassemble(out_dir: str) -> list[str]:
 
 if __name__ == "__main__":
     build(verbose=True)
+    build_probe(verbose=True)
     print(LIB)
     sys.exit(0)
