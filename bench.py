@@ -273,6 +273,38 @@ def bench_batched(torch, args, tuned):
             "single_path_ms": round(ms1, 3)}
 
 
+def bench_window(torch, args, img, tuned):
+    """Algorithm 1's own candidate rule (windows around each barycenter) on the
+    headline workload, one whole job per step as for the headline."""
+    from paper_1903_07149_amd import synth
+    from paper_1903_07149_amd._lib import ASSIGN_WINDOW
+    from paper_1903_07149_amd.scalp import Scalp
+
+    wl = synth.HD
+    H, W = img.contour.shape
+    lab = torch.from_numpy(img.lab).cuda()
+    con = torch.from_numpy(img.contour).cuda()
+    s = Scalp(W, H, wl.k, iterations=wl.iterations, assign_mode=ASSIGN_WINDOW, **tuned)
+    out = s.new_state()
+    for _ in range(args.warmup):
+        s.run(lab, con, out=out)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    reps = max(1, args.steps // 2)
+    t0.record()
+    for _ in range(reps):
+        s.run(lab, con, out=out)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / reps
+    g3 = Scalp(W, H, wl.k, iterations=wl.iterations, **tuned).run(lab, con)
+    agree = float((out[2] == g3.labels).float().mean().item())
+    return {"workload": f"{wl.name}, window of Algorithm 1", "mpx_iter_s":
+            round(W * H * wl.iterations / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(ms, 3),
+            "label_agreement_with_3x3_form": round(agree, 4)}
+
+
 def bench_soft(torch, args):
     from paper_1903_07149_amd import synth
     from paper_1903_07149_amd.scalp import Scalp
@@ -374,6 +406,8 @@ def main():
         out["extensions"] = {"batched": bench_batched(torch, args, tuned)}
         log("soft")
         out["extensions"]["soft"] = bench_soft(torch, args)
+        log("window form")
+        out["extensions"]["window_form"] = bench_window(torch, args, img, tuned)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(img, 2000, 10)

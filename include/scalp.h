@@ -75,7 +75,21 @@ typedef struct {
                                 0..9728; 0 selects the default (4800)        */
     int32_t wg_size;         /* tuning: assignment workgroup size, 0 (default
                                 1024), 256, 512 or 1024                      */
+    int32_t assign_mode;     /* SCALP_ASSIGN_GRID3X3 (default) or
+                                SCALP_ASSIGN_WINDOW, see below               */
 } scalp_params_t;
+
+/* Candidate rule of the assignment.
+ *   SCALP_ASSIGN_GRID3X3: every pixel compares the superpixels of the 3x3 grid
+ *     cells around its own cell (pixel-centric; labels are always grid
+ *     neighbours).
+ *   SCALP_ASSIGN_WINDOW: Algorithm 1 as written: every superpixel k compares
+ *     itself with the pixels of a (2R+1) x (2R+1) window centred on its
+ *     rounded barycenter, R = r rounded to a whole pixel; a pixel takes the
+ *     first strict minimum in ascending k over the windows covering it and
+ *     keeps its previous label where no window covers it (labels are then
+ *     in/out for scalp_assign).  Single-image entry points only. */
+enum { SCALP_ASSIGN_GRID3X3 = 0, SCALP_ASSIGN_WINDOW = 1 };
 
 /* Fills the paper's defaults (Sec. III-A.3: m = 10, lambda = 0.5,
  * sigma = 0.25, gamma = 2r) with 10 iterations and projection on.
@@ -88,8 +102,9 @@ int scalp_default_params(scalp_params_t* out);
 int scalp_make_grid(int32_t width, int32_t height, int32_t k, scalp_grid_t* out);
 
 /* Bytes of device workspace the single-image entry points need for grid g:
- * the packed (l, a, b, w) image (16 B per pixel) plus 68 B per superpixel
- * (integer accumulators, projection queue) and 256 B of control words.
+ * the packed (l, a, b, w) image (16 B per pixel), 8 B per pixel of window
+ * minima, 68 B per superpixel (integer accumulators, projection queue) and
+ * 256 B of control words.
  * 0 if g is invalid. */
 size_t scalp_workspace_bytes(const scalp_grid_t* g);
 
@@ -114,7 +129,7 @@ int scalp_init_grid(const scalp_grid_t* g, const scalp_params_t* p, const float*
  * over the superpixels of the 3x3 grid cells around its own cell, and takes
  * the first strict minimum in ascending superpixel order.  FP32 arithmetic
  * in a fixed per-pixel order (no contraction), so labels are reproducible
- * bit for bit.  labels: output. */
+ * bit for bit.  labels: output (in/out with SCALP_ASSIGN_WINDOW). */
 int scalp_assign(const scalp_grid_t* g, const scalp_params_t* p, const float* lab,
                  const float* contour, const float* centers, const int32_t* endpoints,
                  int32_t* labels, void* workspace, size_t workspace_bytes, void* stream);

@@ -81,6 +81,12 @@ def _declare(L):
     L.orc_init_grid.restype = None
     L.orc_run.argtypes = [_i, _i, _i, _p, _p, _f, _f, _f, _f, _i, _i, _i, _p, _p, _p, _p]
     L.orc_run.restype = _l
+    L.orc_window_radius.argtypes = [_i, _i, _i]; L.orc_window_radius.restype = _i
+    L.orc_assign_window.argtypes = [_i, _i, _i, _i, _p, _p, _p, _p, _f, _f, _f, _p, _p]
+    L.orc_assign_window.restype = None
+    L.orc_run_window.argtypes = [_i, _i, _i, _p, _p, _f, _f, _f, _f, _i, _i, _i, _p, _p, _p,
+                                 _p]
+    L.orc_run_window.restype = _l
     L.orc_set_threads.argtypes = [_i]; L.orc_set_threads.restype = None
     L.orc_max_threads.argtypes = []; L.orc_max_threads.restype = _i
     L.orc_distance_ab.argtypes = [_i, _i, _p, _p, _f, _f, _f, _i, _i, _p, _i, _i, _p, _p, _p]
@@ -198,6 +204,32 @@ def assign(g: Grid, lab, w, centres, endpoints, lam=0.5, gamma=None, spw=None,
     return labels, best, samples.value
 
 
+def window_radius(g: Grid) -> int:
+    return int(lib().orc_window_radius(g.width, g.height, g.k))
+
+
+def assign_window(g: Grid, lab, w, centres, endpoints, labels, lam=0.5, gamma=None, spw=None,
+                  m: float = 10.0, R: int | None = None):
+    """Cluster-centric assignment of Algorithm 1 (windows of half-width R around the
+    rounded barycenters).  `labels` holds the previous labels (kept where no window
+    covers a pixel).  Returns (labels, best D; +inf where uncovered)."""
+    lab = _f32(lab)
+    w = _f32(w)
+    centres = _f32(centres)
+    endpoints = _i32(endpoints)
+    out = _i32(labels).copy()
+    if gamma is None:
+        gamma = default_gamma(g)
+    if spw is None:
+        spw = spatial_weight(g, m)
+    if R is None:
+        R = window_radius(g)
+    best = np.empty((g.height, g.width), np.float32)
+    lib().orc_assign_window(g.width, g.height, g.num_sp, R, _ptr(lab), _ptr(w), _ptr(centres),
+                            _ptr(endpoints), lam, gamma, spw, _ptr(out), _ptr(best))
+    return out, best
+
+
 def update(g: Grid, lab, labels, centres, mode: int = MEAN_PLAIN):
     """Returns (new centres float32[K][5], counts int32[K])."""
     lab = _f32(lab)
@@ -263,6 +295,26 @@ def run(lab, contour, k: int, iterations: int = 10, m: float = 10.0, lam: float 
     if s < 0:
         raise ValueError("oracle run rejected its arguments")
     return RunResult(labels, centres, ep, counts, int(s))
+
+
+def run_window(lab, contour, k: int, iterations: int = 10, m: float = 10.0, lam: float = 0.5,
+               sigma: float = 0.25, gamma: float = -1.0, project: bool = True,
+               mode: int = MEAN_PLAIN) -> RunResult:
+    """Whole run with the window assignment of Algorithm 1."""
+    lab = _f32(lab)
+    contour = _f32(contour)
+    H, W = contour.shape
+    g = grid(W, H, k)
+    centres = np.empty((g.num_sp, 5), np.float32)
+    ep = np.empty((g.num_sp, 2), np.int32)
+    labels = np.empty((H, W), np.int32)
+    counts = np.zeros(g.num_sp, np.int32)
+    s = lib().orc_run_window(W, H, k, _ptr(lab), _ptr(contour), m, lam, sigma, gamma, iterations,
+                             int(project), mode, _ptr(centres), _ptr(ep), _ptr(labels),
+                             _ptr(counts))
+    if s < 0:
+        raise ValueError("oracle run rejected its arguments")
+    return RunResult(labels, centres, ep, counts, 0)
 
 
 def soft_forward(lab, contour, k: int, iterations: int = 5, m: float = 10.0,

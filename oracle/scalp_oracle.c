@@ -226,6 +226,54 @@ void orc_assign(int W, int H, int nx, int ny, const float *lab, const float *w,
 }
 
 /* ------------------------------------------------------------------ */
+/* Assignment, cluster-centric form of Algorithm 1                      */
+/* ------------------------------------------------------------------ */
+
+/* Half-width of the (2r+1) x (2r+1) window of Algorithm 1, r rounded to a
+ * whole number of pixels. */
+int orc_window_radius(int W, int H, int k) {
+    return (int)floor(orc_grid_r(W, H, k) + 0.5);
+}
+
+/* Algorithm 1 as written: d <- infinity; for each cluster k in ascending
+ * order, for each pixel p of the window of half-width R centred on the
+ * rounded barycenter of k, compute D(p, C_k) along the path to k's endpoint
+ * and keep it if strictly smaller than d(p).  Pixels no window covers keep
+ * the label they had (labels is in/out). */
+void orc_assign_window(int W, int H, int K, int R, const float *lab, const float *w,
+                       const float *centres, const int *endpoints,
+                       float lambda, float gamma, float spw, int *labels, float *best_out) {
+    hard_ctx c = {W, H, lab, w, lambda, gamma, spw};
+    long N = (long)W * H;
+    float *d = malloc(sizeof(float) * (size_t)N);
+    for (long p = 0; p < N; p++) d[p] = INFINITY;
+    for (int k = 0; k < K; k++) {
+        const float *ck = centres + 5 * (long)k;
+        int wx = (int)floorf(ck[3] + 0.5f), wy = (int)floorf(ck[4] + 0.5f);
+        if (wx < 0) wx = 0;
+        if (wx > W - 1) wx = W - 1;
+        if (wy < 0) wy = 0;
+        if (wy > H - 1) wy = H - 1;
+        for (int y = wy - R; y <= wy + R; y++) {
+            if (y < 0 || y >= H) continue;
+            for (int x = wx - R; x <= wx + R; x++) {
+                if (x < 0 || x >= W) continue;
+                float D = hard_distance(&c, x, y, ck, endpoints[2 * k], endpoints[2 * k + 1],
+                                        NULL, NULL, NULL);
+                long p = (long)y * W + x;
+                if (D < d[p]) {
+                    d[p] = D;
+                    labels[p] = k;
+                }
+            }
+        }
+    }
+    if (best_out)
+        for (long p = 0; p < N; p++) best_out[p] = d[p];
+    free(d);
+}
+
+/* ------------------------------------------------------------------ */
 /* Update (Algorithm 1): mean Lab and barycenter of each superpixel    */
 /* ------------------------------------------------------------------ */
 
@@ -340,6 +388,11 @@ void orc_init_grid(int W, int H, int nx, int ny, const float *lab, int mode,
 /* Whole run: init, then `iters` x (assign, update, project)           */
 /* ------------------------------------------------------------------ */
 
+long orc_run_window(int W, int H, int k, const float *lab, const float *contour,
+                    float m, float lambda, float sigma, float gamma, int iters,
+                    int project, int mode, float *centres, int *endpoints, int *labels,
+                    int *counts);
+
 long orc_run(int W, int H, int k, const float *lab, const float *contour,
              float m, float lambda, float sigma, float gamma, int iters,
              int project, int mode, float *centres, int *endpoints, int *labels,
@@ -367,6 +420,34 @@ long orc_run(int W, int H, int k, const float *lab, const float *contour,
     }
     free(w);
     return samples;
+}
+
+/* The same run with the window assignment of Algorithm 1. */
+long orc_run_window(int W, int H, int k, const float *lab, const float *contour,
+                    float m, float lambda, float sigma, float gamma, int iters,
+                    int project, int mode, float *centres, int *endpoints, int *labels,
+                    int *counts) {
+    int nx, ny;
+    int K = orc_grid(W, H, k, &nx, &ny);
+    if (K < 0) return -1;
+    long N = (long)W * H;
+    float *w = malloc(sizeof(float) * (size_t)N);
+    orc_wmap(contour, N, sigma, w);
+    float spw = orc_spatial_weight(W, H, k, m);
+    if (gamma < 0.0f) gamma = orc_default_gamma(W, H, k);
+    int R = orc_window_radius(W, H, k);
+    orc_init_grid(W, H, nx, ny, lab, mode, centres, endpoints, labels);
+    for (int it = 0; it < iters; it++) {
+        orc_assign_window(W, H, K, R, lab, w, centres, endpoints, lambda, gamma, spw, labels,
+                          NULL);
+        orc_update(W, H, K, lab, labels, mode, centres, counts);
+        if (project)
+            orc_project(W, H, K, labels, centres, counts, endpoints);
+        else
+            orc_round_endpoints(W, H, K, centres, endpoints);
+    }
+    free(w);
+    return 0;
 }
 
 void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }

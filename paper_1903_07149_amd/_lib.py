@@ -50,7 +50,12 @@ class Params(ctypes.Structure):
     _fields_ = [("m", ctypes.c_float), ("lambda_", ctypes.c_float), ("sigma", ctypes.c_float),
                 ("gamma", ctypes.c_float), ("iterations", ctypes.c_int32),
                 ("project", ctypes.c_int32), ("reuse_prepared", ctypes.c_int32),
-                ("lds_pixels", ctypes.c_int32), ("wg_size", ctypes.c_int32)]
+                ("lds_pixels", ctypes.c_int32), ("wg_size", ctypes.c_int32),
+                ("assign_mode", ctypes.c_int32)]
+
+
+ASSIGN_GRID3X3 = 0
+ASSIGN_WINDOW = 1
 
 
 class BatchDesc(ctypes.Structure):

@@ -41,6 +41,8 @@ bool params_valid(const scalp_params_t* p) {
     if (p->lds_pixels < 0 || p->lds_pixels > kMaxLdsPixels) return false;
     if (p->wg_size != 0 && p->wg_size != 256 && p->wg_size != 512 && p->wg_size != 1024)
         return false;
+    if (p->assign_mode != SCALP_ASSIGN_GRID3X3 && p->assign_mode != SCALP_ASSIGN_WINDOW)
+        return false;
     return true;
 }
 
@@ -67,8 +69,9 @@ Img img_of(const scalp_grid_t* g, const scalp_params_t* p, long long pix, int sp
 }
 
 // Single-image workspace: [packed float4 N][acc int64 8K][ctrl int32 64][plist int32 K]
+// [window minima uint64 N]
 struct Layout {
-    size_t packed, acc, ctrl, plist, total;
+    size_t packed, acc, ctrl, plist, keys, total;
 };
 
 Layout layout_of(long long N, long long K) {
@@ -77,7 +80,8 @@ Layout layout_of(long long N, long long K) {
     L.acc = align_up((size_t)N * 16);
     L.ctrl = L.acc + (size_t)K * kAccStride * 8;   // acc and ctrl are contiguous (cleared together)
     L.plist = align_up(L.ctrl + kCtrlWords * 4);
-    L.total = align_up(L.plist + (size_t)K * 4);
+    L.keys = align_up(L.plist + (size_t)K * 4);
+    L.total = align_up(L.keys + (size_t)N * 8);
     return L;
 }
 
@@ -86,12 +90,19 @@ struct Views {
     long long* acc;
     int* ctrl;
     int* plist;
+    unsigned long long* keys;
 };
 
 Views views_of(void* ws, const Layout& L) {
     char* b = static_cast<char*>(ws);
     return Views{reinterpret_cast<float4*>(b + L.packed), reinterpret_cast<long long*>(b + L.acc),
-                 reinterpret_cast<int*>(b + L.ctrl), reinterpret_cast<int*>(b + L.plist)};
+                 reinterpret_cast<int*>(b + L.ctrl), reinterpret_cast<int*>(b + L.plist),
+                 reinterpret_cast<unsigned long long*>(b + L.keys)};
+}
+
+// Half-width of Algorithm 1's window: r = sqrt(N/k) rounded to whole pixels.
+int window_radius(const scalp_grid_t* g) {
+    return (int)std::floor(grid_r(g->width, g->height, g->k_requested) + 0.5);
 }
 
 long long clear_words(const Layout& L) { return (long long)((L.ctrl + kCtrlWords * 4 - L.acc) / 8); }
@@ -121,12 +132,27 @@ int enq_init(const Img& im, const Views& v, float* centers, int* endpoints, int*
     return e;
 }
 
+// One window-form pass and its sums (the update cannot be fused: a pixel's
+// label is known only after every window covering it).
+int enq_window_pass(const Img& im, const scalp_params_t* p, const Views& v, int R,
+                    const float* centers, const int* endpoints, int* labels, long long clear_n,
+                    hipStream_t s) {
+    int e = launch_assign_window(im, v.packed, centers, endpoints, labels, v.keys, R, p->lambda,
+                                 tuning_of(p), s);
+    if (e == hipSuccess) e = launch_clear(v.acc, clear_n, s);
+    if (e == hipSuccess) e = launch_accumulate_packed(im, v.packed, labels, v.acc, s);
+    return e;
+}
+
 int enq_iterations(const Img& im, const scalp_params_t* p, const Views& v, float* centers,
-                   int* endpoints, int* labels, int* counts, hipStream_t s) {
+                   int* endpoints, int* labels, int* counts, hipStream_t s, int R,
+                   long long clear_n) {
     const Tuning t = tuning_of(p);
     for (int it = 0; it < p->iterations; ++it) {
-        int e = launch_assign(im, v.packed, centers, endpoints, labels, v.acc, v.ctrl, p->lambda,
-                              true, t, s);
+        int e = p->assign_mode == SCALP_ASSIGN_WINDOW
+                    ? enq_window_pass(im, p, v, R, centers, endpoints, labels, clear_n, s)
+                    : launch_assign(im, v.packed, centers, endpoints, labels, v.acc, v.ctrl,
+                                    p->lambda, true, t, s);
         if (e == hipSuccess)
             e = launch_finalize(im, centers, endpoints, counts, v.acc, labels, v.ctrl, v.plist,
                                 p->project != 0, s);
@@ -189,6 +215,7 @@ int scalp_default_params(scalp_params_t* out) {
     out->reuse_prepared = 0;
     out->lds_pixels = 0;
     out->wg_size = 0;
+    out->assign_mode = SCALP_ASSIGN_GRID3X3;
     return SCALP_OK;
 }
 
@@ -254,8 +281,12 @@ int scalp_assign(const scalp_grid_t* g, const scalp_params_t* p, const float* la
     const hipStream_t s = (hipStream_t)stream;
     const Views v = views_of(ws, layout_of((long long)g->width * g->height, g->num_sp));
     if (!p->reuse_prepared) CHECK_HIP(enq_prepare(g, p, lab, contour, v, s));
-    CHECK_HIP(launch_assign(img_of(g, p, 0, 0), v.packed, centers, endpoints, labels, v.acc,
-                            v.ctrl, p->lambda, false, tuning_of(p), s));
+    if (p->assign_mode == SCALP_ASSIGN_WINDOW)
+        CHECK_HIP(launch_assign_window(img_of(g, p, 0, 0), v.packed, centers, endpoints, labels,
+                                       v.keys, window_radius(g), p->lambda, tuning_of(p), s));
+    else
+        CHECK_HIP(launch_assign(img_of(g, p, 0, 0), v.packed, centers, endpoints, labels, v.acc,
+                                v.ctrl, p->lambda, false, tuning_of(p), s));
     return SCALP_OK;
 }
 
@@ -286,9 +317,14 @@ int scalp_assign_accumulate(const scalp_grid_t* g, const scalp_params_t* p, cons
     if (rc != SCALP_OK) return rc;
     if (!centers || !endpoints || !labels) return SCALP_ERR_ARG;
     library_init();
-    const Views v = views_of(ws, layout_of((long long)g->width * g->height, g->num_sp));
-    CHECK_HIP(launch_assign(img_of(g, p, 0, 0), v.packed, centers, endpoints, labels, v.acc,
-                            v.ctrl, p->lambda, true, tuning_of(p), (hipStream_t)stream));
+    const Layout L = layout_of((long long)g->width * g->height, g->num_sp);
+    const Views v = views_of(ws, L);
+    if (p->assign_mode == SCALP_ASSIGN_WINDOW)
+        CHECK_HIP(enq_window_pass(img_of(g, p, 0, 0), p, v, window_radius(g), centers, endpoints,
+                                  labels, clear_words(L), (hipStream_t)stream));
+    else
+        CHECK_HIP(launch_assign(img_of(g, p, 0, 0), v.packed, centers, endpoints, labels, v.acc,
+                                v.ctrl, p->lambda, true, tuning_of(p), (hipStream_t)stream));
     return SCALP_OK;
 }
 
@@ -318,11 +354,13 @@ int scalp_run(const scalp_grid_t* g, const scalp_params_t* p, const float* lab,
     if (!p->reuse_prepared && (!lab || !contour)) return SCALP_ERR_ARG;
     library_init();
     const hipStream_t s = (hipStream_t)stream;
-    const Views v = views_of(ws, layout_of((long long)g->width * g->height, g->num_sp));
+    const Layout L = layout_of((long long)g->width * g->height, g->num_sp);
+    const Views v = views_of(ws, L);
     const Img im = img_of(g, p, 0, 0);
     if (!p->reuse_prepared) CHECK_HIP(enq_prepare(g, p, lab, contour, v, s));
     CHECK_HIP(enq_init(im, v, centers, endpoints, counts, labels, s));
-    CHECK_HIP(enq_iterations(im, p, v, centers, endpoints, labels, counts, s));
+    CHECK_HIP(enq_iterations(im, p, v, centers, endpoints, labels, counts, s, window_radius(g),
+                             clear_words(L)));
     return SCALP_OK;
 }
 
@@ -333,11 +371,14 @@ int scalp_graph_create(const scalp_grid_t* g, const scalp_params_t* p, float* ce
     if (rc != SCALP_OK) return rc;
     if (!centers || !endpoints || !labels || !counts || !out) return SCALP_ERR_ARG;
     library_init();
-    const Views v = views_of(ws, layout_of((long long)g->width * g->height, g->num_sp));
+    const Layout L = layout_of((long long)g->width * g->height, g->num_sp);
+    const Views v = views_of(ws, L);
     const Img im = img_of(g, p, 0, 0);
     const scalp_params_t pc = *p;
+    const int R = window_radius(g);
+    const long long cw = clear_words(L);
     return capture(out, [&](hipStream_t s) {
-        return enq_iterations(im, &pc, v, centers, endpoints, labels, counts, s);
+        return enq_iterations(im, &pc, v, centers, endpoints, labels, counts, s, R, cw);
     });
 }
 
@@ -435,6 +476,7 @@ int scalp_run_batched(const scalp_batch_desc_t* descs, int32_t n, const scalp_pa
                       void* stream) {
     BatchLayout BL;
     if (!batch_layout(descs, n, &BL) || !params_valid(p)) return SCALP_ERR_ARG;
+    if (p->assign_mode != SCALP_ASSIGN_GRID3X3) return SCALP_ERR_UNSUPPORTED;
     if (!centers || !endpoints || !labels || !counts) return SCALP_ERR_ARG;
     if (!p->reuse_prepared && (!lab || !contour)) return SCALP_ERR_ARG;
     if (!ws || ws_bytes < BL.total) return SCALP_ERR_WORKSPACE;
@@ -452,6 +494,7 @@ int scalp_batched_graph_create(const scalp_batch_desc_t* descs, int32_t n, const
                                size_t ws_bytes, scalp_graph_handle* out) {
     BatchLayout BL;
     if (!batch_layout(descs, n, &BL) || !params_valid(p)) return SCALP_ERR_ARG;
+    if (p->assign_mode != SCALP_ASSIGN_GRID3X3) return SCALP_ERR_UNSUPPORTED;
     if (!centers || !endpoints || !labels || !counts || !out) return SCALP_ERR_ARG;
     if (!p->reuse_prepared && (!lab || !contour)) return SCALP_ERR_ARG;
     if (!ws || ws_bytes < BL.total) return SCALP_ERR_WORKSPACE;
@@ -506,6 +549,7 @@ SoftWs soft_ws_layout(const scalp_grid_t* g, long long B) {
 bool soft_args_ok(const scalp_grid_t* g, const scalp_params_t* p, float temperature,
                   int32_t batch) {
     if (!grid_valid(g) || !params_valid(p)) return false;
+    if (p->assign_mode != SCALP_ASSIGN_GRID3X3) return false;   // soft slots are the 3x3 cells
     if (!(temperature > 0.0f) || !std::isfinite(temperature)) return false;
     if (batch < 1 || p->iterations < 1) return false;
     const long long N = (long long)g->width * g->height;

@@ -58,6 +58,12 @@ int launch_assign(const Img& im, const float4* packed, const float* centres,
                   bool accumulate, const Tuning& t, hipStream_t s);
 int launch_accumulate(const Img& im, const float* lab, const int* labels, long long* acc,
                       hipStream_t s);
+// Window form of the assignment (Algorithm 1 as written); labels in/out.
+int launch_assign_window(const Img& im, const float4* packed, const float* centres,
+                         const int* endpoints, int* labels, unsigned long long* keys, int R,
+                         float lambda, const Tuning& t, hipStream_t s);
+int launch_accumulate_packed(const Img& im, const float4* packed, const int* labels,
+                             long long* acc, hipStream_t s);
 int launch_finalize(const Img& im, float* centres, int* endpoints, int* counts,
                     long long* acc, const int* labels, int* ctrl, int* plist, bool project,
                     hipStream_t s);

@@ -237,6 +237,100 @@ __global__ __launch_bounds__(WG) void k_assign_persistent(const Img* __restrict_
     }
 }
 
+// ---------------------------------------------------------------- window form
+
+// Algorithm 1 as written: one workgroup per cluster k scans the window of
+// half-width R around k's rounded barycenter, computes D for every pixel of
+// it along the path to k's endpoint, and offers (D, k) to the pixel with a
+// 64-bit atomic minimum of (FP32 bits of D, k): D >= 0, so the minimum is the
+// smallest D and, among equal D, the smallest k, which is exactly the result
+// of visiting clusters in ascending order with a strict "<".
+template <int WG>
+__global__ __launch_bounds__(WG) void k_assign_window(Img im, const float4* __restrict__ packed,
+                                                      const float* __restrict__ centres,
+                                                      const int* __restrict__ endpoints,
+                                                      unsigned long long* __restrict__ keys,
+                                                      int R, float lambda, int cap) {
+    extern __shared__ float4 lds_dyn[];
+    __shared__ int rect[4];
+    const int tid = threadIdx.x;
+    const int k = xcd_remap(blockIdx.x, gridDim.x);
+    const int W = im.W, H = im.H;
+    const float4* __restrict__ img = packed + im.pix;
+    const float* ck = centres + 5LL * (im.sp + k);
+    const float l = ck[0], a = ck[1], b = ck[2], xk = ck[3], yk = ck[4];
+    const int wx = round_coord(xk, W - 1), wy = round_coord(yk, H - 1);
+    const int cx = min(max(endpoints[2LL * (im.sp + k)], 0), W - 1);
+    const int cy = min(max(endpoints[2LL * (im.sp + k) + 1], 0), H - 1);
+    const int x0 = max(wx - R, 0), x1 = min(wx + R, W - 1) + 1;
+    const int y0 = max(wy - R, 0), y1 = min(wy + R, H - 1) + 1;
+    // the paths of the window end at (cx, cy): stage bbox(window, endpoint)
+    const int rx0 = min(x0, cx), rx1 = max(x1, cx + 1);
+    const int ry0 = min(y0, cy), ry1 = max(y1, cy + 1);
+    const bool staged = (long long)(rx1 - rx0) * (ry1 - ry0) <= cap;
+    const int rw = rx1 - rx0;
+    if (staged) {
+        const int area = rw * (ry1 - ry0);
+        for (int e = tid; e < area; e += WG) {
+            const int r = e / rw;
+            lds_dyn[e] = img[(long long)(ry0 + r) * W + rx0 + (e - r * rw)];
+        }
+    }
+    (void)rect;
+    __syncthreads();
+    const float4 fc = img[(long long)cy * W + cx];
+    const float dcc = colour_dist(fc, l, a, b), wc = fc.w;
+    const int cw = x1 - x0, ch = y1 - y0, P = cw * ch;
+    const int lane = tid & 63, wave = tid >> 6;
+    const float oml = 1.0f - lambda;
+    for (int chunk = wave; chunk * 64 < P; chunk += WG / 64) {
+        const int t = chunk * 64 + lane;
+        if (t >= P) continue;
+        int x, y;
+        cell_pixel(t, cw, ch, x, y);
+        x += x0;
+        y += y0;
+        const int p = y * W + x;
+        const float4 fp = img[p];
+        const int dx = cx - x, dy = cy - y;
+        const float dcp = colour_dist(fp, l, a, b);
+        float sc = dcp, sw = fp.w;
+        if (staged)
+            walk_path_lds(lds_dyn, (y - ry0) * rw + (x - rx0), rw, dx, dy, l, a, b, sc, sw);
+        else
+            walk_path(img, p, 1, W, dx, dy, l, a, b, sc, sw);
+        const int adx = dx < 0 ? -dx : dx, ady = dy < 0 ? -dy : dy;
+        const int n = adx > ady ? adx : ady;
+        if (n > 0) {
+            sc = sc + dcc;
+            sw = sw + wc;
+        }
+        const float np = (float)(n + 1);
+        const float A = lambda * dcp + oml * (sc / np);
+        const float B = 1.0f + im.gamma * (sw / np);
+        const float ex = (float)x - xk, ey = (float)y - yk;
+        const float D = A * B + (ex * ex + ey * ey) * im.spw;
+        const unsigned long long key = ((unsigned long long)__float_as_uint(D) << 32) | (unsigned)k;
+        atomicMin(&keys[im.pix + p], key);
+    }
+}
+
+__global__ void k_fill_u64(unsigned long long* __restrict__ p, long long n, unsigned long long v) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// Labels from the window minima; pixels no window covered keep their label.
+__global__ void k_window_labels(const unsigned long long* __restrict__ keys, int* __restrict__ labels,
+                                long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const unsigned long long key = keys[i];
+        if (key != ~0ULL) labels[i] = (int)(unsigned)(key & 0xffffffffULL);
+    }
+}
+
 // ---------------------------------------------------------------- prepare
 
 __global__ void k_prepare(long long n, const float* __restrict__ lab,
@@ -307,8 +401,21 @@ __global__ __launch_bounds__(WG) void k_init_cells_batched(const Img* __restrict
 
 // ---------------------------------------------------------------- update from labels
 
+// Colour source of the update: the caller's lab array, or the packed texels.
+struct LabSource {
+    const float* lab;
+    const float4* packed;
+    __device__ __forceinline__ float3 operator()(long long p) const {
+        if (packed) {
+            const float4 f = packed[p];
+            return make_float3(f.x, f.y, f.z);
+        }
+        return make_float3(lab[3 * p], lab[3 * p + 1], lab[3 * p + 2]);
+    }
+};
+
 template <int WG>
-__global__ __launch_bounds__(WG) void k_accumulate(Img im, const float* __restrict__ lab,
+__global__ __launch_bounds__(WG) void k_accumulate(Img im, LabSource src,
                                                    const int* __restrict__ labels,
                                                    long long* __restrict__ acc) {
     __shared__ unsigned long long bins[9][6];
@@ -327,10 +434,11 @@ __global__ __launch_bounds__(WG) void k_accumulate(Img im, const float* __restri
         const long long p = (long long)y * im.W + x;
         const int k = labels[p];
         if (k < 0 || k >= K) continue;
+        const float3 f = src(p);
         unsigned long long v[6] = {1ULL, (unsigned long long)x, (unsigned long long)y,
-                                   (unsigned long long)to_fixed(lab[3 * p]),
-                                   (unsigned long long)to_fixed(lab[3 * p + 1]),
-                                   (unsigned long long)to_fixed(lab[3 * p + 2])};
+                                   (unsigned long long)to_fixed(f.x),
+                                   (unsigned long long)to_fixed(f.y),
+                                   (unsigned long long)to_fixed(f.z)};
         const int ki = k / im.nx, kj = k - ki * im.nx;
         const int di = ki - ci + 1, dj = kj - cj + 1;
         if (di >= 0 && di < 3 && dj >= 0 && dj < 3) {
@@ -563,6 +671,9 @@ int launch_write_bytes(void* dst, const void* src, size_t n, hipStream_t s) {
 
 void lift_lds_limits() {
     const size_t cap = 160 * 1024 - sizeof(CellShared) - 64;
+    allow_lds(k_assign_window<256>, cap);
+    allow_lds(k_assign_window<512>, cap);
+    allow_lds(k_assign_window<1024>, cap);
     allow_lds(k_assign<256, true>, cap);
     allow_lds(k_assign<256, false>, cap);
     allow_lds(k_assign<512, true>, cap);
@@ -677,9 +788,45 @@ int persistent_grid(const Tuning& t) {
     return cus * per;
 }
 
+template <int WG>
+static int launch_window_t(const Img& im, const float4* packed, const float* centres,
+                           const int* endpoints, unsigned long long* keys, int R, float lambda,
+                           const Tuning& t, hipStream_t s) {
+    hipLaunchKernelGGL(k_assign_window<WG>, dim3(im.nx * im.ny), dim3(WG), dyn_lds(t), s, im,
+                       packed, centres, endpoints, keys, R, lambda, t.lds_pixels);
+    return hipGetLastError();
+}
+
+int launch_assign_window(const Img& im, const float4* packed, const float* centres,
+                         const int* endpoints, int* labels, unsigned long long* keys, int R,
+                         float lambda, const Tuning& t, hipStream_t s) {
+    const long long n = (long long)im.W * im.H;
+    const unsigned blocks = (unsigned)std::min<long long>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_fill_u64, dim3(blocks), dim3(256), 0, s, keys + im.pix, n, ~0ULL);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    int r;
+    if (t.wg == 1024) r = launch_window_t<1024>(im, packed, centres, endpoints, keys, R, lambda, t, s);
+    else if (t.wg == 512) r = launch_window_t<512>(im, packed, centres, endpoints, keys, R, lambda, t, s);
+    else r = launch_window_t<256>(im, packed, centres, endpoints, keys, R, lambda, t, s);
+    if (r != hipSuccess) return r;
+    hipLaunchKernelGGL(k_window_labels, dim3(blocks), dim3(256), 0, s, keys + im.pix,
+                       labels + im.pix, n);
+    return hipGetLastError();
+}
+
 int launch_accumulate(const Img& im, const float* lab, const int* labels, long long* acc,
                       hipStream_t s) {
-    hipLaunchKernelGGL(k_accumulate<kSmallWG>, dim3(im.nx * im.ny), dim3(kSmallWG), 0, s, im, lab,
+    const LabSource src{lab, nullptr};
+    hipLaunchKernelGGL(k_accumulate<kSmallWG>, dim3(im.nx * im.ny), dim3(kSmallWG), 0, s, im, src,
+                       labels, acc);
+    return hipGetLastError();
+}
+
+int launch_accumulate_packed(const Img& im, const float4* packed, const int* labels,
+                             long long* acc, hipStream_t s) {
+    const LabSource src{nullptr, packed};
+    hipLaunchKernelGGL(k_accumulate<kSmallWG>, dim3(im.nx * im.ny), dim3(kSmallWG), 0, s, im, src,
                        labels, acc);
     return hipGetLastError();
 }
