@@ -305,6 +305,28 @@ def bench_window(torch, args, img, tuned):
             "label_agreement_with_3x3_form": round(agree, 4)}
 
 
+def quality(torch, tuned):
+    """Sec. III-A.2 metrics against the synthetic ground truth for the distance
+    settings of Sec. III-B, on the 481x321 workload (k = 250, 10 iterations)."""
+    from paper_1903_07149_amd import synth
+    from paper_1903_07149_amd.metrics import metrics
+    from paper_1903_07149_amd.scalp import Scalp
+
+    img = synth.workload_image(synth.BSD_SHAPE)
+    H, W = img.contour.shape
+    lab = torch.from_numpy(img.lab).cuda()
+    con = torch.from_numpy(img.contour).cuda()
+    gt = torch.from_numpy(img.gt).cuda()
+    out = {}
+    for name, kw in [("slic", dict(lam=1.0, gamma=0.0)), ("path_colour", dict(lam=0.5, gamma=0.0)),
+                     ("contour", dict(lam=1.0)), ("scalp", dict())]:
+        s = Scalp(W, H, 250, **kw, **tuned)
+        r = s.run(lab, con)
+        m = metrics(r.labels, gt, num_sp=s.K)
+        out[name] = {k: round(v, 4) for k, v in m.items() if k in ("br", "asa", "ue", "co")}
+    return out
+
+
 def bench_soft(torch, args):
     from paper_1903_07149_amd import synth
     from paper_1903_07149_amd.scalp import Scalp
@@ -408,6 +430,8 @@ def main():
         out["extensions"]["soft"] = bench_soft(torch, args)
         log("window form")
         out["extensions"]["window_form"] = bench_window(torch, args, img, tuned)
+        log("quality metrics")
+        out["extensions"]["quality_481x321"] = quality(torch, tuned)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(img, 2000, 10)

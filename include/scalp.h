@@ -246,6 +246,27 @@ int scalp_soft_backward(const scalp_grid_t* g, const scalp_params_t* p, float te
                         float* grad_contour, void* workspace, size_t workspace_bytes,
                         void* stream);
 
+/* ---- Quality metrics (Sec. III-A.2) ------------------------------------ */
+
+/* Boundary recall (Eq. (5)), achievable segmentation accuracy (Eq. (6)),
+ * undersegmentation error (Eq. (7)) and compactness (Eq. (8)) of the label
+ * map `labels` (int32 [H][W], values in [0, num_sp)) against the
+ * ground-truth partition `gt` (int32 [H][W], values in [0, num_regions)).
+ * A pixel is a boundary pixel when a 4-neighbour inside the image has
+ * another label; BR counts ground-truth boundary pixels with a superpixel
+ * boundary pixel at Euclidean distance < epsilon (the paper uses 2);
+ * perimeters count 4-connected pixel edges, the image border included.
+ * Pixels whose label or region is out of range are left out of the overlap
+ * table and the perimeters.  out: device double[6] = {BR, ASA, UE, CO,
+ * number of ground-truth boundary pixels, number of superpixel boundary
+ * pixels}.  Sums are integers, or FP64 in a fixed order: the result is
+ * deterministic.  SCALP_ERR_ARG if num_sp * num_regions > 2^30. */
+size_t scalp_metrics_workspace_bytes(int32_t width, int32_t height, int32_t num_sp,
+                                     int32_t num_regions);
+int scalp_metrics(int32_t width, int32_t height, const int32_t* labels, int32_t num_sp,
+                  const int32_t* gt, int32_t num_regions, float epsilon, double* out,
+                  void* workspace, size_t workspace_bytes, void* stream);
+
 /* Static description of a code. */
 const char* scalp_strerror(int code);
 

@@ -26,7 +26,8 @@ EXPORTED = [
     "scalp_finalize", "scalp_run", "scalp_graph_create",
     "scalp_graph_launch", "scalp_graph_destroy", "scalp_batch_workspace_bytes",
     "scalp_run_batched", "scalp_batched_graph_create", "scalp_soft_saved_bytes",
-    "scalp_soft_workspace_bytes", "scalp_soft_forward", "scalp_soft_backward", "scalp_strerror",
+    "scalp_soft_workspace_bytes", "scalp_soft_forward", "scalp_soft_backward",
+    "scalp_metrics_workspace_bytes", "scalp_metrics", "scalp_strerror",
 ]
 
 
@@ -108,6 +109,8 @@ def lib() -> ctypes.CDLL:
                                    ctypes.c_int),
             "scalp_soft_backward": ([gp, pp, f32, i32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
                                      _SZ, _P], ctypes.c_int),
+            "scalp_metrics_workspace_bytes": ([i32, i32, i32, i32], _SZ),
+            "scalp_metrics": ([i32, i32, _P, i32, _P, i32, f32, _P, _P, _SZ, _P], ctypes.c_int),
             "scalp_strerror": ([ctypes.c_int], ctypes.c_char_p),
         }
         for name, (args, res) in sig.items():

@@ -664,6 +664,33 @@ int scalp_soft_backward(const scalp_grid_t* g, const scalp_params_t* p, float te
     return SCALP_OK;
 }
 
+// ------------------------------------------------------------------ metrics
+
+static bool metrics_args_ok(int32_t W, int32_t H, int32_t K, int32_t R) {
+    if (W < 1 || H < 1 || K < 1 || R < 1) return false;
+    if ((long long)W * H >= (1LL << 31)) return false;
+    return (long long)K * R <= (1LL << 30);
+}
+
+size_t scalp_metrics_workspace_bytes(int32_t width, int32_t height, int32_t num_sp,
+                                     int32_t num_regions) {
+    if (!metrics_args_ok(width, height, num_sp, num_regions)) return 0;
+    return metrics_workspace_bytes((long long)width * height, num_sp, num_regions);
+}
+
+int scalp_metrics(int32_t width, int32_t height, const int32_t* labels, int32_t num_sp,
+                  const int32_t* gt, int32_t num_regions, float epsilon, double* out,
+                  void* ws, size_t ws_bytes, void* stream) {
+    if (!metrics_args_ok(width, height, num_sp, num_regions)) return SCALP_ERR_ARG;
+    if (!labels || !gt || !out) return SCALP_ERR_ARG;
+    if (!(epsilon > 0.0f) || epsilon > 64.0f) return SCALP_ERR_ARG;
+    if (!ws || ws_bytes < metrics_workspace_bytes((long long)width * height, num_sp, num_regions))
+        return SCALP_ERR_WORKSPACE;
+    CHECK_HIP(launch_metrics(width, height, labels, num_sp, gt, num_regions, epsilon, out, ws,
+                             (hipStream_t)stream));
+    return SCALP_OK;
+}
+
 const char* scalp_strerror(int code) {
     switch (code) {
         case SCALP_OK: return "ok";

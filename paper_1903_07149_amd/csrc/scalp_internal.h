@@ -113,4 +113,9 @@ int launch_soft_bwd_finish(const SoftGeom& g, const float4* gf, const float* gth
                            hipStream_t st);
 int launch_copy_f32(const float* src, float* dst, long long n, hipStream_t st);
 
+// ---- quality metrics (scalp_metrics.hip)
+size_t metrics_workspace_bytes(long long N, int K, int R);
+int launch_metrics(int W, int H, const int* S, int K, const int* G, int R, float eps, double* out,
+                   void* ws, hipStream_t st);
+
 }  // namespace scalp

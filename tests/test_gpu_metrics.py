@@ -1,0 +1,59 @@
+"""GPU quality metrics (scalp_metrics) against the numpy definitions, and the
+distance ablation of Sec. III-B on synthetic ground truth."""
+import numpy as np
+import pytest
+
+from oracle import metrics as M
+from paper_1903_07149_amd import synth
+from gpu_util import dev, host, needs_gpu, say, torch
+
+pytestmark = [pytest.mark.gpu, needs_gpu]
+
+
+@pytest.mark.parametrize("eps", [2.0, 1.0, 3.5])
+@pytest.mark.parametrize("H,W,K,R,seed", [(37, 53, 9, 5, 1), (128, 96, 40, 12, 2), (1, 70, 4, 3, 3),
+                                          (64, 1, 2, 2, 4)])
+def test_metrics_match_definitions(H, W, K, R, seed, eps):
+    from paper_1903_07149_amd.metrics import metrics
+    rng = np.random.default_rng(seed)
+    # blocky label maps, so that boundaries are sparse and structured
+    sp = np.kron(rng.integers(0, K, (H // 4 + 1, W // 4 + 1)), np.ones((4, 4)))[:H, :W]
+    gt = np.kron(rng.integers(0, R, (H // 6 + 1, W // 6 + 1)), np.ones((6, 6)))[:H, :W]
+    sp, gt = sp.astype(np.int32), gt.astype(np.int32)
+    say("metrics", H, W, K, R, eps)
+    got = metrics(dev(sp), dev(gt), num_sp=K, num_regions=R, epsilon=eps)
+    ref = M.all_metrics(sp, gt, eps)
+    assert got["br"] == ref["br"] and got["asa"] == ref["asa"] and got["ue"] == ref["ue"]
+    assert abs(got["co"] - ref["co"]) <= 1e-12 * max(1.0, ref["co"])
+    assert got["gt_boundary"] == int(M.boundary(gt).sum())
+    assert got["sp_boundary"] == int(M.boundary(sp).sum())
+
+
+def test_metrics_of_a_run_and_ablation():
+    """Metrics of SCALP label maps against the Voronoi ground truth, for the four
+    distance settings of Sec. III-B: SLIC (lambda = 1, gamma = 0), + path colour
+    (lambda = 0.5), + contour (gamma = 2r), and full SCALP."""
+    from paper_1903_07149_amd.metrics import metrics
+    from paper_1903_07149_amd.scalp import Scalp
+    img = synth.workload_image(synth.BSD_SHAPE)
+    H, W = img.contour.shape
+    lab, con, gt = dev(img.lab), dev(img.contour), dev(img.gt)
+    rows = {}
+    for name, kw in [("slic", dict(lam=1.0, gamma=0.0)), ("path_colour", dict(lam=0.5, gamma=0.0)),
+                     ("contour", dict(lam=1.0)), ("scalp", dict())]:
+        s = Scalp(W, H, 250, **kw)
+        say("ablation", name)
+        r = s.run(lab, con)
+        m = metrics(r.labels, gt, num_sp=s.K)
+        ref = M.all_metrics(host(r.labels), img.gt)
+        assert m["br"] == ref["br"] and m["asa"] == ref["asa"] and m["ue"] == ref["ue"]
+        assert abs(m["co"] - ref["co"]) <= 1e-12
+        rows[name] = m
+        print(name, {k: round(v, 4) for k, v in m.items()})
+    # Sec. III-B/III-C: the path terms make superpixels more homogeneous and more
+    # compact than SLIC's (BR saturates at 1 here: SLIC's noisy boundaries cover
+    # nearly every pixel, so it is not compared)
+    assert rows["scalp"]["ue"] < rows["slic"]["ue"]
+    assert rows["scalp"]["asa"] > rows["slic"]["asa"]
+    assert rows["scalp"]["co"] > rows["slic"]["co"]
+    assert rows["scalp"]["sp_boundary"] < rows["slic"]["sp_boundary"]
