@@ -305,6 +305,73 @@ def bench_window(torch, args, img, tuned):
             "label_agreement_with_3x3_form": round(agree, 4)}
 
 
+def _time(torch, fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        fn()
+    t1.record()
+    torch.cuda.synchronize()
+    return t0.elapsed_time(t1) / reps
+
+
+def bench_multiscale(torch, args, tuned):
+    """Twelve decompositions (6 to 600 superpixels) of the 481x321 image as one
+    ragged batch, then their boundary-frequency map: the input of the
+    precision-recall evaluation of Sec. III-A.2."""
+    from paper_1903_07149_amd import synth
+    from paper_1903_07149_amd.maps import MultiScale, boundary_map
+
+    img = synth.workload_image(synth.BSD_SHAPE)
+    H, W = img.contour.shape
+    ms = MultiScale(W, H, **{k: v for k, v in tuned.items()})
+    lab_b, con_b = ms.stack(torch.from_numpy(img.lab).cuda(), torch.from_numpy(img.contour).cuda())
+    state = ms.batch.new_state()
+    n = len(ms.ks)
+
+    def step():
+        ms.batch.run(lab_b, con_b, out=state)
+        boundary_map(state[2].reshape(n, H, W))
+
+    ms_step = _time(torch, step, max(2, args.steps))
+    return {"workload": f"481x321, k in {ms.ks}, 10 iterations, one batch + boundary map",
+            "ms_per_image": round(ms_step, 3), "images_per_s": round(1e3 / ms_step, 1),
+            "mpx_iter_s": round(n * W * H * 10 / (ms_step * 1e-3) / 1e6, 1)}
+
+
+def bench_contour(torch, args, img):
+    """The contour prior computed on the device (normalised gradient
+    magnitude), standalone and fused into the packing step, on 1920x1080."""
+    from paper_1903_07149_amd import synth
+    from paper_1903_07149_amd._lib import CONTOUR_GRADIENT
+    from paper_1903_07149_amd.maps import contour_from_lab
+    from paper_1903_07149_amd.scalp import Scalp
+
+    H, W = img.contour.shape
+    N = W * H
+    lab = torch.from_numpy(img.lab).cuda()
+    con = torch.from_numpy(img.contour).cuda()
+    given = Scalp(W, H, synth.HD.k)
+    fused = Scalp(W, H, synth.HD.k, contour_source=CONTOUR_GRADIENT)
+    reps = max(5, args.steps)
+    t_map = _time(torch, lambda: contour_from_lab(lab), reps)
+    t_given = _time(torch, lambda: given.prepare(lab, con), reps)
+    t_fused = _time(torch, lambda: fused.prepare(lab, None), reps)
+    # algorithmic bytes: the map reads lab twice (max, then values) and writes
+    # C; plain packing reads lab and C and writes (l, a, b, w); fused packing
+    # reads lab twice and writes (l, a, b, w)
+    gbs = lambda b, ms: round(b / (ms * 1e-3) / 1e9, 1)
+    return {"workload": "1920x1080",
+            "contour_map_ms": round(t_map, 4), "contour_map_GBps": gbs(28 * N, t_map),
+            "pack_given_prior_ms": round(t_given, 4), "pack_given_prior_GBps": gbs(32 * N, t_given),
+            "pack_computed_prior_ms": round(t_fused, 4),
+            "pack_computed_prior_GBps": gbs(40 * N, t_fused),
+            "two_step_ms": round(t_map + t_given, 4)}
+
+
 def quality(torch, tuned):
     """Sec. III-A.2 metrics against the synthetic ground truth for the distance
     settings of Sec. III-B, on the 481x321 workload (k = 250, 10 iterations)."""
@@ -430,6 +497,10 @@ def main():
         out["extensions"]["soft"] = bench_soft(torch, args)
         log("window form")
         out["extensions"]["window_form"] = bench_window(torch, args, img, tuned)
+        log("multi-scale")
+        out["extensions"]["multiscale_481x321"] = bench_multiscale(torch, args, tuned)
+        log("contour prior")
+        out["extensions"]["contour_prior"] = bench_contour(torch, args, img)
         log("quality metrics")
         out["extensions"]["quality_481x321"] = quality(torch, tuned)
     if not args.no_cpu_baseline:

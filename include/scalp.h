@@ -77,6 +77,8 @@ typedef struct {
                                 1024), 256, 512 or 1024                      */
     int32_t assign_mode;     /* SCALP_ASSIGN_GRID3X3 (default) or
                                 SCALP_ASSIGN_WINDOW, see below               */
+    int32_t contour_source;  /* SCALP_CONTOUR_INPUT (default) or
+                                SCALP_CONTOUR_GRADIENT, see below            */
 } scalp_params_t;
 
 /* Candidate rule of the assignment.
@@ -91,8 +93,19 @@ typedef struct {
  *     in/out for scalp_assign).  Single-image entry points only. */
 enum { SCALP_ASSIGN_GRID3X3 = 0, SCALP_ASSIGN_WINDOW = 1 };
 
+/* Where the contour prior C of Sec. II-D comes from when an entry point packs
+ * the image.
+ *   SCALP_CONTOUR_INPUT: the caller's contour map (float32 [H][W] in [0, 1]).
+ *   SCALP_CONTOUR_GRADIENT: computed from lab while packing, with the values
+ *     scalp_contour_from_lab gives (normalised gradient magnitude, per image);
+ *     the contour argument is ignored and may be NULL.  Not for the soft
+ *     entry points (SCALP_ERR_UNSUPPORTED): their backward returns dL/dC
+ *     for a given C. */
+enum { SCALP_CONTOUR_INPUT = 0, SCALP_CONTOUR_GRADIENT = 1 };
+
 /* Fills the paper's defaults (Sec. III-A.3: m = 10, lambda = 0.5,
- * sigma = 0.25, gamma = 2r) with 10 iterations and projection on.
+ * sigma = 0.25, gamma = 2r) with 10 iterations, projection on, the 3x3 grid
+ * candidate rule and the caller's contour map.
  * out: host pointer.  Returns SCALP_ERR_ARG if out is NULL. */
 int scalp_default_params(scalp_params_t* out);
 
@@ -266,6 +279,26 @@ size_t scalp_metrics_workspace_bytes(int32_t width, int32_t height, int32_t num_
 int scalp_metrics(int32_t width, int32_t height, const int32_t* labels, int32_t num_sp,
                   const int32_t* gt, int32_t num_regions, float epsilon, double* out,
                   void* workspace, size_t workspace_bytes, void* stream);
+
+/* ---- Per-pixel maps -------------------------------------------------------- */
+
+/* Multi-scale boundary map: labels holds n label maps int32 [n][H][W] of one
+ * image (e.g. decompositions at several k, Sec. III-A.2 uses 12 scales from 6
+ * to 600 superpixels); out float32 [H][W] receives, per pixel, the fraction
+ * c/n (FP32 division) of maps in which it is a boundary pixel (a 4-neighbour
+ * inside the image has another label). */
+int scalp_boundary_map(int32_t width, int32_t height, const int32_t* labels, int32_t n,
+                       float* out, void* stream);
+
+/* A soft contour prior C in [0, 1] (Sec. II-D) computed from the image: the
+ * central-difference gradient magnitude of lab (float32 [H][W][3];
+ * replicated borders; sqrt of the sum over channels of gx^2 + gy^2 with
+ * g = (f(+1) - f(-1)) / 2) divided by its maximum over the image, in FP64
+ * and rounded once to FP32; all zeros for a constant image.  A detector-free
+ * stand-in for the learned detectors of Sec. II-E.  workspace: at least
+ * 8 bytes of device memory.  out: float32 [H][W]. */
+int scalp_contour_from_lab(int32_t width, int32_t height, const float* lab, float* out,
+                           void* workspace, size_t workspace_bytes, void* stream);
 
 /* Static description of a code. */
 const char* scalp_strerror(int code);

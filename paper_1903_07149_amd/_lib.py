@@ -27,7 +27,8 @@ EXPORTED = [
     "scalp_graph_launch", "scalp_graph_destroy", "scalp_batch_workspace_bytes",
     "scalp_run_batched", "scalp_batched_graph_create", "scalp_soft_saved_bytes",
     "scalp_soft_workspace_bytes", "scalp_soft_forward", "scalp_soft_backward",
-    "scalp_metrics_workspace_bytes", "scalp_metrics", "scalp_strerror",
+    "scalp_metrics_workspace_bytes", "scalp_metrics", "scalp_boundary_map",
+    "scalp_contour_from_lab", "scalp_strerror",
 ]
 
 
@@ -52,11 +53,13 @@ class Params(ctypes.Structure):
                 ("gamma", ctypes.c_float), ("iterations", ctypes.c_int32),
                 ("project", ctypes.c_int32), ("reuse_prepared", ctypes.c_int32),
                 ("lds_pixels", ctypes.c_int32), ("wg_size", ctypes.c_int32),
-                ("assign_mode", ctypes.c_int32)]
+                ("assign_mode", ctypes.c_int32), ("contour_source", ctypes.c_int32)]
 
 
 ASSIGN_GRID3X3 = 0
 ASSIGN_WINDOW = 1
+CONTOUR_INPUT = 0
+CONTOUR_GRADIENT = 1
 
 
 class BatchDesc(ctypes.Structure):
@@ -111,6 +114,8 @@ def lib() -> ctypes.CDLL:
                                      _SZ, _P], ctypes.c_int),
             "scalp_metrics_workspace_bytes": ([i32, i32, i32, i32], _SZ),
             "scalp_metrics": ([i32, i32, _P, i32, _P, i32, f32, _P, _P, _SZ, _P], ctypes.c_int),
+            "scalp_boundary_map": ([i32, i32, _P, i32, _P, _P], ctypes.c_int),
+            "scalp_contour_from_lab": ([i32, i32, _P, _P, _P, _SZ, _P], ctypes.c_int),
             "scalp_strerror": ([ctypes.c_int], ctypes.c_char_p),
         }
         for name, (args, res) in sig.items():
@@ -140,12 +145,20 @@ def make_grid(width: int, height: int, k: int) -> Grid:
     return g
 
 
+def apply_overrides(p: Params, overrides: dict) -> Params:
+    names = {f[0] for f in Params._fields_}
+    for key, val in overrides.items():
+        key = "lambda_" if key in ("lam", "lambda") else key
+        if key not in names:
+            raise TypeError(f"unknown SCALP parameter {key!r}")
+        setattr(p, key, val)
+    return p
+
+
 def default_params(**overrides) -> Params:
     p = Params()
     check(lib().scalp_default_params(ctypes.byref(p)), "scalp_default_params")
-    for key, val in overrides.items():
-        setattr(p, "lambda_" if key == "lam" else key, val)
-    return p
+    return apply_overrides(p, overrides)
 
 
 def workspace_bytes(g: Grid) -> int:

@@ -16,7 +16,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libscalp.so")
-SOURCES = ["scalp_kernels.hip", "scalp_soft.hip", "scalp_metrics.hip", "scalp_abi.hip"]
+SOURCES = ["scalp_kernels.hip", "scalp_soft.hip", "scalp_metrics.hip", "scalp_maps.hip",
+           "scalp_abi.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

@@ -43,7 +43,14 @@ bool params_valid(const scalp_params_t* p) {
         return false;
     if (p->assign_mode != SCALP_ASSIGN_GRID3X3 && p->assign_mode != SCALP_ASSIGN_WINDOW)
         return false;
+    if (p->contour_source != SCALP_CONTOUR_INPUT && p->contour_source != SCALP_CONTOUR_GRADIENT)
+        return false;
     return true;
+}
+
+// The pointers a packing step reads are present.
+bool pack_inputs_ok(const scalp_params_t* p, const float* lab, const float* contour) {
+    return lab && (contour || p->contour_source == SCALP_CONTOUR_GRADIENT);
 }
 
 Tuning tuning_of(const scalp_params_t* p) {
@@ -51,6 +58,12 @@ Tuning tuning_of(const scalp_params_t* p) {
     t.wg = p->wg_size == 0 ? 1024 : p->wg_size;
     t.lds_pixels = p->lds_pixels > 0 ? p->lds_pixels : default_lds_pixels();
     return t;
+}
+
+// Assignment work items per cell: the largest cell is ceil(W / nx) x ceil(H / ny).
+int slices_of(const scalp_grid_t* g) {
+    const long long cw = (g->width + g->nx - 1) / g->nx, ch = (g->height + g->ny - 1) / g->ny;
+    return (int)std::max<long long>(1, (cw * ch + kSlicePixels - 1) / kSlicePixels);
 }
 
 Img img_of(const scalp_grid_t* g, const scalp_params_t* p, long long pix, int sp) {
@@ -64,7 +77,7 @@ Img img_of(const scalp_grid_t* g, const scalp_params_t* p, long long pix, int sp
     const double r = grid_r(g->width, g->height, g->k_requested);
     im.spw = (float)(((double)p->m * (double)p->m) / (r * r));          // Eq. (3)
     im.gamma = p->gamma < 0.0f ? (float)(2.0 * r) : p->gamma;           // Sec. III-A.3
-    im.pad = 0;
+    im.spl = slices_of(g);
     return im;
 }
 
@@ -121,6 +134,9 @@ int check_common(const scalp_grid_t* g, const scalp_params_t* p, void* ws, size_
 // Enqueue helpers (no validation).
 int enq_prepare(const scalp_grid_t* g, const scalp_params_t* p, const float* lab,
                 const float* contour, const Views& v, hipStream_t s) {
+    if (p->contour_source == SCALP_CONTOUR_GRADIENT)
+        return launch_prepare_gradient(g->width, g->height, lab, p->sigma, v.packed,
+                                       reinterpret_cast<unsigned long long*>(v.ctrl + kCtrlGradMax), s);
     return launch_prepare((long long)g->width * g->height, lab, contour, p->sigma, v.packed, s);
 }
 
@@ -216,6 +232,7 @@ int scalp_default_params(scalp_params_t* out) {
     out->lds_pixels = 0;
     out->wg_size = 0;
     out->assign_mode = SCALP_ASSIGN_GRID3X3;
+    out->contour_source = SCALP_CONTOUR_INPUT;
     return SCALP_OK;
 }
 
@@ -246,7 +263,7 @@ int scalp_prepare(const scalp_grid_t* g, const scalp_params_t* p, const float* l
                   const float* contour, void* ws, size_t ws_bytes, void* stream) {
     int rc = check_common(g, p, ws, ws_bytes);
     if (rc != SCALP_OK) return rc;
-    if (!lab || !contour) return SCALP_ERR_ARG;
+    if (!pack_inputs_ok(p, lab, contour)) return SCALP_ERR_ARG;
     library_init();
     const Views v = views_of(ws, layout_of((long long)g->width * g->height, g->num_sp));
     CHECK_HIP(enq_prepare(g, p, lab, contour, v, (hipStream_t)stream));
@@ -259,7 +276,7 @@ int scalp_init_grid(const scalp_grid_t* g, const scalp_params_t* p, const float*
     int rc = check_common(g, p, ws, ws_bytes);
     if (rc != SCALP_OK) return rc;
     if (!centers || !endpoints || !labels) return SCALP_ERR_ARG;
-    if (!p->reuse_prepared && (!lab || !contour)) return SCALP_ERR_ARG;
+    if (!p->reuse_prepared && !pack_inputs_ok(p, lab, contour)) return SCALP_ERR_ARG;
     library_init();
     const hipStream_t s = (hipStream_t)stream;
     const Layout L = layout_of((long long)g->width * g->height, g->num_sp);
@@ -276,7 +293,7 @@ int scalp_assign(const scalp_grid_t* g, const scalp_params_t* p, const float* la
     int rc = check_common(g, p, ws, ws_bytes);
     if (rc != SCALP_OK) return rc;
     if (!centers || !endpoints || !labels) return SCALP_ERR_ARG;
-    if (!p->reuse_prepared && (!lab || !contour)) return SCALP_ERR_ARG;
+    if (!p->reuse_prepared && !pack_inputs_ok(p, lab, contour)) return SCALP_ERR_ARG;
     library_init();
     const hipStream_t s = (hipStream_t)stream;
     const Views v = views_of(ws, layout_of((long long)g->width * g->height, g->num_sp));
@@ -351,7 +368,7 @@ int scalp_run(const scalp_grid_t* g, const scalp_params_t* p, const float* lab,
     int rc = check_common(g, p, ws, ws_bytes);
     if (rc != SCALP_OK) return rc;
     if (!centers || !endpoints || !labels || !counts) return SCALP_ERR_ARG;
-    if (!p->reuse_prepared && (!lab || !contour)) return SCALP_ERR_ARG;
+    if (!p->reuse_prepared && !pack_inputs_ok(p, lab, contour)) return SCALP_ERR_ARG;
     library_init();
     const hipStream_t s = (hipStream_t)stream;
     const Layout L = layout_of((long long)g->width * g->height, g->num_sp);
@@ -401,27 +418,30 @@ int scalp_graph_destroy(scalp_graph_handle h) {
 
 namespace {
 
-// Batched workspace: [packed][acc][ctrl][plist][imgs][cell_start]
+// Batched workspace: [packed][acc][ctrl][plist][imgs][cell_start][item_start]
 struct BatchLayout {
     Layout base;
-    size_t imgs, starts, total;
-    long long N, K;
+    size_t imgs, starts, items, total;
+    long long N, K, items_total;
 };
 
 bool batch_layout(const scalp_batch_desc_t* d, int n, BatchLayout* out) {
     if (!d || n < 1) return false;
-    long long N = 0, K = 0;
+    long long N = 0, K = 0, I = 0;
     for (int i = 0; i < n; ++i) {
         if (!grid_valid(&d[i].grid)) return false;
         if (d[i].pix_offset != N || d[i].sp_offset != K) return false;
         N += (long long)d[i].grid.width * d[i].grid.height;
         K += d[i].grid.num_sp;
-        if (N >= (1LL << 40) || K >= (1LL << 31)) return false;
+        I += (long long)d[i].grid.num_sp * slices_of(&d[i].grid);
+        if (N >= (1LL << 40) || K >= (1LL << 31) || I >= (1LL << 31)) return false;
     }
+    out->items_total = I;
     out->base = layout_of(N, K);
     out->imgs = out->base.total;
     out->starts = align_up(out->imgs + sizeof(Img) * (size_t)n);
-    out->total = align_up(out->starts + sizeof(int) * (size_t)(n + 1));
+    out->items = align_up(out->starts + sizeof(int) * (size_t)(n + 1));
+    out->total = align_up(out->items + sizeof(int) * (size_t)(n + 1));
     out->N = N;
     out->K = K;
     return true;
@@ -434,23 +454,40 @@ int enq_batched(const scalp_batch_desc_t* d, int n, const scalp_params_t* p, con
     char* b = static_cast<char*>(ws);
     Img* imgs = reinterpret_cast<Img*>(b + BL.imgs);
     int* starts = reinterpret_cast<int*>(b + BL.starts);
+    int* items = reinterpret_cast<int*>(b + BL.items);
     std::vector<Img> himg((size_t)n);
-    std::vector<int> hstart((size_t)n + 1);
+    std::vector<int> hstart((size_t)n + 1), hitem((size_t)n + 1);
+    long long total_items = 0;
     for (int i = 0; i < n; ++i) {
         himg[(size_t)i] = img_of(&d[i].grid, p, d[i].pix_offset, d[i].sp_offset);
         hstart[(size_t)i] = d[i].sp_offset;
+        hitem[(size_t)i] = (int)total_items;
+        total_items += (long long)d[i].grid.num_sp * himg[(size_t)i].spl;   // < 2^31: batch_layout
     }
     hstart[(size_t)n] = (int)BL.K;
+    hitem[(size_t)n] = (int)total_items;
     int e = launch_write_bytes(imgs, himg.data(), sizeof(Img) * (size_t)n, s);
     if (e == hipSuccess) e = launch_write_bytes(starts, hstart.data(), sizeof(int) * (size_t)(n + 1), s);
-    if (e == hipSuccess && !p->reuse_prepared) e = launch_prepare(BL.N, lab, contour, p->sigma, v.packed, s);
+    if (e == hipSuccess) e = launch_write_bytes(items, hitem.data(), sizeof(int) * (size_t)(n + 1), s);
+    if (e == hipSuccess && !p->reuse_prepared) {
+        if (p->contour_source == SCALP_CONTOUR_GRADIENT) {
+            // the prior is normalised per image: one max + pack per image
+            unsigned long long* mx = reinterpret_cast<unsigned long long*>(v.ctrl + kCtrlGradMax);
+            for (int i = 0; e == hipSuccess && i < n; ++i)
+                e = launch_prepare_gradient(d[i].grid.width, d[i].grid.height,
+                                            lab + 3 * d[i].pix_offset, p->sigma,
+                                            v.packed + d[i].pix_offset, mx, s);
+        } else {
+            e = launch_prepare(BL.N, lab, contour, p->sigma, v.packed, s);
+        }
+    }
     if (e == hipSuccess) e = launch_init_cells_batched(imgs, starts, n, (int)BL.K, v.packed, labels, v.acc, s);
     if (e == hipSuccess)
         e = launch_finalize_batched(imgs, starts, n, (int)BL.K, centers, endpoints, counts, v.acc,
                                     labels, v.ctrl, v.plist, false, s);
     const Tuning t = tuning_of(p);
     for (int it = 0; e == hipSuccess && it < p->iterations; ++it) {
-        e = launch_assign_persistent(imgs, starts, n, (int)BL.K, v.packed, centers, endpoints,
+        e = launch_assign_persistent(imgs, items, n, (int)total_items, v.packed, centers, endpoints,
                                      labels, v.acc, v.ctrl, p->lambda, t, grid, s);
         if (e == hipSuccess)
             e = launch_finalize_batched(imgs, starts, n, (int)BL.K, centers, endpoints, counts,
@@ -478,7 +515,7 @@ int scalp_run_batched(const scalp_batch_desc_t* descs, int32_t n, const scalp_pa
     if (!batch_layout(descs, n, &BL) || !params_valid(p)) return SCALP_ERR_ARG;
     if (p->assign_mode != SCALP_ASSIGN_GRID3X3) return SCALP_ERR_UNSUPPORTED;
     if (!centers || !endpoints || !labels || !counts) return SCALP_ERR_ARG;
-    if (!p->reuse_prepared && (!lab || !contour)) return SCALP_ERR_ARG;
+    if (!p->reuse_prepared && !pack_inputs_ok(p, lab, contour)) return SCALP_ERR_ARG;
     if (!ws || ws_bytes < BL.total) return SCALP_ERR_WORKSPACE;
     library_init();
     const int grid = persistent_grid(tuning_of(p));
@@ -496,7 +533,7 @@ int scalp_batched_graph_create(const scalp_batch_desc_t* descs, int32_t n, const
     if (!batch_layout(descs, n, &BL) || !params_valid(p)) return SCALP_ERR_ARG;
     if (p->assign_mode != SCALP_ASSIGN_GRID3X3) return SCALP_ERR_UNSUPPORTED;
     if (!centers || !endpoints || !labels || !counts || !out) return SCALP_ERR_ARG;
-    if (!p->reuse_prepared && (!lab || !contour)) return SCALP_ERR_ARG;
+    if (!p->reuse_prepared && !pack_inputs_ok(p, lab, contour)) return SCALP_ERR_ARG;
     if (!ws || ws_bytes < BL.total) return SCALP_ERR_WORKSPACE;
     library_init();
     // the occupancy query runs before the capture
@@ -580,8 +617,9 @@ int scalp_soft_forward(const scalp_grid_t* g, const scalp_params_t* p, float tem
                        int32_t batch, const float* lab, const float* contour, float* centers_t,
                        float* q_t, void* saved, void* ws, size_t ws_bytes, void* stream) {
     if (!soft_args_ok(g, p, temperature, batch)) return SCALP_ERR_ARG;
+    if (p->contour_source != SCALP_CONTOUR_INPUT) return SCALP_ERR_UNSUPPORTED;
     if (!centers_t || !q_t || !saved) return SCALP_ERR_ARG;
-    if (!p->reuse_prepared && (!lab || !contour)) return SCALP_ERR_ARG;
+    if (!p->reuse_prepared && !pack_inputs_ok(p, lab, contour)) return SCALP_ERR_ARG;
     const SoftWs W = soft_ws_layout(g, batch);
     if (!ws || ws_bytes < W.total) return SCALP_ERR_WORKSPACE;
     library_init();
@@ -619,6 +657,7 @@ int scalp_soft_backward(const scalp_grid_t* g, const scalp_params_t* p, float te
                         const float* grad_q, const float* grad_centers, float* grad_lab,
                         float* grad_contour, void* ws, size_t ws_bytes, void* stream) {
     if (!soft_args_ok(g, p, temperature, batch)) return SCALP_ERR_ARG;
+    if (p->contour_source != SCALP_CONTOUR_INPUT) return SCALP_ERR_UNSUPPORTED;
     if (!centers_t || !q_t || !saved || !grad_q || !grad_centers || !grad_lab || !grad_contour ||
         !contour)
         return SCALP_ERR_ARG;
@@ -688,6 +727,25 @@ int scalp_metrics(int32_t width, int32_t height, const int32_t* labels, int32_t 
         return SCALP_ERR_WORKSPACE;
     CHECK_HIP(launch_metrics(width, height, labels, num_sp, gt, num_regions, epsilon, out, ws,
                              (hipStream_t)stream));
+    return SCALP_OK;
+}
+
+// ------------------------------------------------------------------ maps
+
+int scalp_boundary_map(int32_t width, int32_t height, const int32_t* labels, int32_t n, float* out,
+                       void* stream) {
+    if (width < 1 || height < 1 || n < 1 || !labels || !out) return SCALP_ERR_ARG;
+    if ((long long)width * height >= (1LL << 31)) return SCALP_ERR_ARG;
+    CHECK_HIP(launch_boundary_frequency(width, height, n, labels, out, (hipStream_t)stream));
+    return SCALP_OK;
+}
+
+int scalp_contour_from_lab(int32_t width, int32_t height, const float* lab, float* out, void* ws,
+                           size_t ws_bytes, void* stream) {
+    if (width < 1 || height < 1 || !lab || !out) return SCALP_ERR_ARG;
+    if ((long long)width * height >= (1LL << 31)) return SCALP_ERR_ARG;
+    if (!ws || ws_bytes < 8) return SCALP_ERR_WORKSPACE;
+    CHECK_HIP(launch_contour_from_lab(width, height, lab, out, ws, (hipStream_t)stream));
     return SCALP_OK;
 }
 

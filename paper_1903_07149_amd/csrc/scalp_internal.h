@@ -21,6 +21,7 @@ constexpr int kAccStride = 8;
 enum Ctrl : int {
     kCtrlProjCount = 0,   // entries in the projection list
     kCtrlQueue = 1,       // persistent work-queue head
+    kCtrlGradMax = 2,     // words 2-3: FP64 bits of the largest gradient magnitude
     kCtrlWords = 64
 };
 
@@ -31,8 +32,13 @@ struct Img {
     int sp;           // first superpixel in the concatenated superpixel arrays
     float spw;        // m^2 / r^2 of Eq. (3)
     float gamma;      // gamma of Eq. (2)
-    int pad;
+    int spl;          // assignment work items per grid cell (slices of its pixels)
 };
+
+// Pixels of one assignment work item: cells larger than this are split into
+// several items, so that images with few, large superpixels still spread
+// over the whole chip.
+constexpr int kSlicePixels = 2048;
 
 struct Tuning {
     int wg;           // workgroup size of the assignment kernel (256 or 512)
@@ -73,7 +79,7 @@ int launch_project(const Img& im, const float* centres, const int* counts, const
 // Batched variants: imgs/cell_start/sp_start are device arrays in the workspace.
 int launch_init_cells_batched(const Img* imgs, const int* cell_start, int n_img, int total_cells,
                               const float4* packed, int* labels, long long* acc, hipStream_t s);
-int launch_assign_persistent(const Img* imgs, const int* cell_start, int n_img, int total_cells,
+int launch_assign_persistent(const Img* imgs, const int* item_start, int n_img, int total_items,
                              const float4* packed, const float* centres, const int* endpoints,
                              int* labels, long long* acc, int* ctrl, float lambda,
                              const Tuning& t, int grid, hipStream_t s);
@@ -112,6 +118,14 @@ int launch_soft_bwd_finish(const SoftGeom& g, const float4* gf, const float* gth
                            const float* contour, float sigma, float* glab, float* gcon,
                            hipStream_t st);
 int launch_copy_f32(const float* src, float* dst, long long n, hipStream_t st);
+
+// ---- per-pixel maps (scalp_maps.hip)
+int launch_boundary_frequency(int W, int H, int n, const int* labels, float* out, hipStream_t s);
+int launch_contour_from_lab(int W, int H, const float* lab, float* out, void* ws, hipStream_t s);
+// prepare with the contour prior computed from lab (same values as
+// launch_contour_from_lab followed by launch_prepare); mx: 8 bytes of scratch
+int launch_prepare_gradient(int W, int H, const float* lab, float sigma, float4* packed,
+                            unsigned long long* mx, hipStream_t s);
 
 // ---- quality metrics (scalp_metrics.hip)
 size_t metrics_workspace_bytes(long long N, int K, int R);

@@ -47,8 +47,16 @@ struct CellShared {
     unsigned long long bins[9][6];
 };
 
+// Strip (8-column band) of cell pixel t, in the order of cell_pixel.
+__device__ __forceinline__ int strip_of(int t, int cw, int ch) {
+    const int fullpx = (cw >> 3) * 8 * ch;
+    return t < fullpx ? t / (8 * ch) : (cw >> 3);
+}
+
+// Work item (cell, slice): pixels [t0, t1) of the cell in cell_pixel order,
+// slice boundaries on multiples of 64 so that every wave keeps an 8x8 block.
 template <int WG, bool ACCUM>
-__device__ __forceinline__ void process_cell(const Img& im, int cell,
+__device__ __forceinline__ void process_cell(const Img& im, int cell, int slice,
                                              const float4* __restrict__ packed,
                                              const float* __restrict__ centres,
                                              const int* __restrict__ endpoints,
@@ -61,6 +69,11 @@ __device__ __forceinline__ void process_cell(const Img& im, int cell,
     const int x0 = cell_lo(cj, W, nx), x1 = cell_lo(cj + 1, W, nx);
     const int y0 = cell_lo(ci, H, ny), y1 = cell_lo(ci + 1, H, ny);
     const float4* __restrict__ img = packed + im.pix;
+    const int cw = x1 - x0, ch = y1 - y0;
+    const int P = cw * ch;
+    const int spl = im.spl;
+    const int t0 = slice == 0 ? 0 : (int)(((long long)P * slice / spl) & ~63LL);
+    const int t1 = slice == spl - 1 ? P : (int)(((long long)P * (slice + 1) / spl) & ~63LL);
 
     if (tid < 9) {
         Cand c;
@@ -94,7 +107,12 @@ __device__ __forceinline__ void process_cell(const Img& im, int cell,
         // that keeps it within the budget.  Candidates left out walk their
         // paths from global memory instead.
         int rx0 = x0, rx1 = x1, ry0 = y0, ry1 = y1;
-        const bool fits = (long long)(x1 - x0) * (y1 - y0) <= cap;
+        if (spl > 1 && t1 > t0) {
+            // the 8-column strips the slice touches, over the cell's rows
+            rx0 = x0 + 8 * strip_of(t0, cw, ch);
+            rx1 = min(x1, x0 + 8 * strip_of(t1 - 1, cw, ch) + 8);
+        }
+        const bool fits = (long long)(rx1 - rx0) * (ry1 - ry0) <= cap;
         if (fits) {
             for (int j = 0; j < 9; ++j) {
                 if (sh.cand[j].k < 0) continue;
@@ -108,7 +126,7 @@ __device__ __forceinline__ void process_cell(const Img& im, int cell,
             }
             sh.rx0 = rx0; sh.ry0 = ry0; sh.rw = rx1 - rx0; sh.rh = ry1 - ry0;
         } else {
-            sh.rx0 = x0; sh.ry0 = y0; sh.rw = 0; sh.rh = 0;
+            sh.rx0 = rx0; sh.ry0 = ry0; sh.rw = 0; sh.rh = 0;
         }
     }
     __syncthreads();
@@ -121,15 +139,13 @@ __device__ __forceinline__ void process_cell(const Img& im, int cell,
     }
     __syncthreads();
 
-    const int cw = x1 - x0, ch = y1 - y0;
-    const int P = cw * ch;
     const int lane = tid & 63, wave = tid >> 6;
-    const int nchunks = (P + 63) >> 6;
+    const int nchunks = (t1 - t0 + 63) >> 6;
     const float oml = 1.0f - lambda;
     const float gamma = im.gamma, spw = im.spw;
     for (int chunk = wave; chunk < nchunks; chunk += WG / 64) {
-        const int t = chunk * 64 + lane;
-        if (t >= P) continue;
+        const int t = t0 + chunk * 64 + lane;
+        if (t >= t1) continue;
         int x, y;
         cell_pixel(t, cw, ch, x, y);
         x += x0;
@@ -205,14 +221,17 @@ __global__ __launch_bounds__(WG) void k_assign(Img im, const float4* __restrict_
     extern __shared__ float4 lds_dyn[];
     __shared__ CellShared sh;
     if (ACCUM && blockIdx.x == 0 && threadIdx.x == 0) ctrl[kCtrlProjCount] = 0;
-    const int cell = xcd_remap(blockIdx.x, gridDim.x);
-    process_cell<WG, ACCUM>(im, cell, packed, centres, endpoints, labels, acc, lambda, cap,
-                            lds_dyn, sh);
+    const int item = xcd_remap(blockIdx.x, gridDim.x);
+    const int cell = item / im.spl;
+    process_cell<WG, ACCUM>(im, cell, item - cell * im.spl, packed, centres, endpoints, labels,
+                            acc, lambda, cap, lds_dyn, sh);
 }
 
+// At most 64 VGPRs (8 waves per SIMD): two 1024-thread workgroups per CU.
 template <int WG>
-__global__ __launch_bounds__(WG) void k_assign_persistent(const Img* __restrict__ imgs,
-                                                          const int* __restrict__ cell_start,
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(8)))
+void k_assign_persistent(const Img* __restrict__ imgs,
+                                                          const int* __restrict__ item_start,
                                                           int n_img, int total,
                                                           const float4* __restrict__ packed,
                                                           const float* __restrict__ centres,
@@ -227,13 +246,15 @@ __global__ __launch_bounds__(WG) void k_assign_persistent(const Img* __restrict_
     for (;;) {
         if (threadIdx.x == 0) item = atomicAdd(&ctrl[kCtrlQueue], 1);
         __syncthreads();
-        const int it = item;
+        const int it = __builtin_amdgcn_readfirstlane(item);   // uniform: keep the item in SGPRs
         __syncthreads();
         if (it >= total) break;
-        const int i = find_image(cell_start, n_img, it);
+        const int i = find_image(item_start, n_img, it);
         const Img im = imgs[i];
-        process_cell<WG, true>(im, it - cell_start[i], packed, centres, endpoints, labels, acc,
-                               lambda, cap, lds_dyn, sh);
+        const int local = it - item_start[i];
+        const int cell = local / im.spl;
+        process_cell<WG, true>(im, cell, local - cell * im.spl, packed, centres, endpoints, labels,
+                               acc, lambda, cap, lds_dyn, sh);
     }
 }
 
@@ -720,7 +741,7 @@ static int launch_assign_t(const Img& im, const float4* packed, const float* cen
                            const int* endpoints, int* labels, long long* acc, int* ctrl,
                            float lambda, const Tuning& t, hipStream_t s) {
     const size_t bytes = dyn_lds(t);
-    hipLaunchKernelGGL((k_assign<WG, ACCUM>), dim3(im.nx * im.ny), dim3(WG), bytes, s, im, packed,
+    hipLaunchKernelGGL((k_assign<WG, ACCUM>), dim3(im.nx * im.ny * im.spl), dim3(WG), bytes, s, im, packed,
                        centres, endpoints, labels, acc, ctrl, lambda, t.lds_pixels);
     return hipGetLastError();
 }
@@ -745,27 +766,27 @@ int launch_assign(const Img& im, const float4* packed, const float* centres,
 }
 
 template <int WG>
-static int launch_persistent_t(const Img* imgs, const int* cell_start, int n_img, int total,
+static int launch_persistent_t(const Img* imgs, const int* item_start, int n_img, int total,
                                const float4* packed, const float* centres, const int* endpoints,
                                int* labels, long long* acc, int* ctrl, float lambda,
                                const Tuning& t, int grid, hipStream_t s) {
     hipLaunchKernelGGL(k_assign_persistent<WG>, dim3(grid), dim3(WG), dyn_lds(t), s, imgs,
-                       cell_start, n_img, total, packed, centres, endpoints, labels, acc, ctrl,
+                       item_start, n_img, total, packed, centres, endpoints, labels, acc, ctrl,
                        lambda, t.lds_pixels);
     return hipGetLastError();
 }
 
-int launch_assign_persistent(const Img* imgs, const int* cell_start, int n_img, int total_cells,
+int launch_assign_persistent(const Img* imgs, const int* item_start, int n_img, int total_items,
                              const float4* packed, const float* centres, const int* endpoints,
                              int* labels, long long* acc, int* ctrl, float lambda,
                              const Tuning& t, int grid, hipStream_t s) {
     if (t.wg == 1024)
-        return launch_persistent_t<1024>(imgs, cell_start, n_img, total_cells, packed, centres,
+        return launch_persistent_t<1024>(imgs, item_start, n_img, total_items, packed, centres,
                                          endpoints, labels, acc, ctrl, lambda, t, grid, s);
     if (t.wg == 512)
-        return launch_persistent_t<512>(imgs, cell_start, n_img, total_cells, packed, centres,
+        return launch_persistent_t<512>(imgs, item_start, n_img, total_items, packed, centres,
                                         endpoints, labels, acc, ctrl, lambda, t, grid, s);
-    return launch_persistent_t<256>(imgs, cell_start, n_img, total_cells, packed, centres,
+    return launch_persistent_t<256>(imgs, item_start, n_img, total_items, packed, centres,
                                     endpoints, labels, acc, ctrl, lambda, t, grid, s);
 }
 

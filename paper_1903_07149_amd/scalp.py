@@ -71,14 +71,12 @@ class Scalp:
         return self.grid.num_sp
 
     def _params(self, **over) -> Params:
-        p = Params.from_buffer_copy(self.params)
-        for key, val in over.items():
-            setattr(p, "lambda_" if key == "lam" else key, val)
-        return p
+        return L.apply_overrides(Params.from_buffer_copy(self.params), over)
 
     def _img(self, lab, contour):
         _need(lab, (self.H, self.W, 3), torch.float32, "lab")
-        _need(contour, (self.H, self.W), torch.float32, "contour")
+        if contour is not None:   # None: the library computes the prior (CONTOUR_GRADIENT)
+            _need(contour, (self.H, self.W), torch.float32, "contour")
 
     def _ws(self):
         return _p(self.workspace), ctypes.c_size_t(self.ws_bytes)
@@ -241,14 +239,13 @@ class ScalpBatch:
 
     def _check(self, lab, contour):
         _need(lab, (self.total_pixels, 3), torch.float32, "lab")
-        _need(contour, (self.total_pixels,), torch.float32, "contour")
+        if contour is not None:   # None: the library computes the prior (CONTOUR_GRADIENT)
+            _need(contour, (self.total_pixels,), torch.float32, "contour")
 
     def run(self, lab, contour, stream=None, out=None, **over):
         self._check(lab, contour)
         centers, endpoints, labels, counts = out if out is not None else self.new_state()
-        p = Params.from_buffer_copy(self.params)
-        for key, val in over.items():
-            setattr(p, "lambda_" if key == "lam" else key, val)
+        p = L.apply_overrides(Params.from_buffer_copy(self.params), over)
         check(L.lib().scalp_run_batched(self.descs, self.n, ctypes.byref(p), _p(lab), _p(contour),
                                         _p(centers), _p(endpoints), _p(labels), _p(counts),
                                         _p(self.workspace), ctypes.c_size_t(self.ws_bytes),
@@ -257,9 +254,7 @@ class ScalpBatch:
 
     def graph(self, lab, contour, centers, endpoints, labels, counts, **over) -> Graph:
         self._check(lab, contour)
-        p = Params.from_buffer_copy(self.params)
-        for key, val in over.items():
-            setattr(p, "lambda_" if key == "lam" else key, val)
+        p = L.apply_overrides(Params.from_buffer_copy(self.params), over)
         h = ctypes.c_void_p()
         check(L.lib().scalp_batched_graph_create(self.descs, self.n, ctypes.byref(p), _p(lab),
                                                  _p(contour), _p(centers), _p(endpoints),

@@ -24,6 +24,8 @@ def test_batched_equals_single_and_oracle(orc, tune):
     wls = _batch(7, 900, 30, 260, 300)
     wls.append(synth.Workload("one_px", 1, 1, 1, 10.0, 1, 1, 10))
     wls.append(synth.Workload("single_sp", 90, 40, 3, 10.0, 2, 1, 10))
+    # cells of 150x200 pixels: each is split into several work items
+    wls.append(synth.Workload("big_cells", 300, 200, 5, 10.0, 3, 2, 10))
     imgs = [synth.workload_image(w) for w in wls]
     b = ScalpBatch([(w.width, w.height, w.k) for w in wls], iterations=6, **tune)
     lab = dev(np.concatenate([i.lab.reshape(-1, 3) for i in imgs]))
