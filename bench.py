@@ -40,9 +40,12 @@ METRIC = "Mpixel-iter/s (assign+update) 1080p K=2000; batched and soft fwd+bwd M
 # packed FMA as 4 operations per lane slot).
 VALU_FP32_PEAK_TFLOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 HBM_PEAK_GBPS = 8000.0
-# LDS: 128 bytes per clock per CU (64 banks x 4 B is not assumed): 78.6 TB/s.
-LDS_PEAK_TBPS = 256 * 128 * 2.4e9 / 1e12
+# LDS: the conflict-free ds_read_b128 ceiling measured by peaks_probe,
+# 107.5 TB/s (175 B per CU-clock), is the figure the path's LDS rate is set
+# against (it is never the bound: the kernel issues 16 B per ~17 VALU ops).
+LDS_PEAK_TBPS = 107.5
 
+EXTENSIONS = ("batched", "soft", "window_form", "multiscale", "contour_prior", "quality")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "assign_hd_traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1903_07149_amd", "csrc", f)
                   for f in ("scalp_kernels.hip", "scalp_device.h")]
@@ -69,6 +72,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extensions", action="store_true")
+    ap.add_argument("--extensions", default=None,
+                    help="comma-separated subset of: batched, soft, window_form, "
+                         "multiscale, contour_prior, quality (default: all)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 512 MiB device copy (counter calibration)")
     ap.add_argument("--launch", default=None,
@@ -475,6 +481,11 @@ def main():
               "single-image paths shard by image across GPUs without communication, so "
               "per-GPU throughput is the figure", file=sys.stderr)
         sys.exit(2)
+    if args.extensions is not None:
+        unknown = set(args.extensions.split(",")) - set(EXTENSIONS)
+        if unknown:
+            print(f"unknown extensions: {sorted(unknown)}", file=sys.stderr)
+            sys.exit(2)
     import torch
     if not torch.cuda.is_available():
         print("bench.py needs a GPU (torch.cuda.is_available() is False)", file=sys.stderr)
@@ -491,18 +502,19 @@ def main():
         "graph_value": round(hard["graph_value"], 1),
     }
     if not args.no_extensions:
-        log("batched")
-        out["extensions"] = {"batched": bench_batched(torch, args, tuned)}
-        log("soft")
-        out["extensions"]["soft"] = bench_soft(torch, args)
-        log("window form")
-        out["extensions"]["window_form"] = bench_window(torch, args, img, tuned)
-        log("multi-scale")
-        out["extensions"]["multiscale_481x321"] = bench_multiscale(torch, args, tuned)
-        log("contour prior")
-        out["extensions"]["contour_prior"] = bench_contour(torch, args, img)
-        log("quality metrics")
-        out["extensions"]["quality_481x321"] = quality(torch, tuned)
+        runs = [("batched", lambda: bench_batched(torch, args, tuned)),
+                ("soft", lambda: bench_soft(torch, args)),
+                ("window_form", lambda: bench_window(torch, args, img, tuned)),
+                ("multiscale", lambda: bench_multiscale(torch, args, tuned)),
+                ("contour_prior", lambda: bench_contour(torch, args, img)),
+                ("quality", lambda: quality(torch, tuned))]
+        want = None if args.extensions is None else set(args.extensions.split(","))
+        names = {"multiscale": "multiscale_481x321", "quality": "quality_481x321"}
+        out["extensions"] = {}
+        for name, fn in runs:
+            if want is None or name in want:
+                log(name)
+                out["extensions"][names.get(name, name)] = fn()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(img, 2000, 10)

@@ -71,8 +71,11 @@ typedef struct {
     int32_t reuse_prepared;  /* 1: the workspace already holds this image's
                                 packed (l, a, b, w) from an earlier call with
                                 the same lab/contour/sigma; skip re-packing  */
-    int32_t lds_pixels;      /* tuning: LDS halo budget in pixels (16 B each),
-                                0..9728; 0 selects the default (4800)        */
+    int32_t lds_pixels;      /* tuning: LDS budget of the assignment in 16-byte
+                                units (per-candidate tables of 8-byte entries,
+                                two of this many; the window form's halo of
+                                16-byte texels), 0..9728; 0 selects the
+                                default (4800)                               */
     int32_t wg_size;         /* tuning: assignment workgroup size, 0 (default
                                 1024), 256, 512 or 1024                      */
     int32_t assign_mode;     /* SCALP_ASSIGN_GRID3X3 (default) or

@@ -19,7 +19,7 @@ import torch
 from .scalp import Scalp
 
 CANDIDATES = [dict(wg_size=w, lds_pixels=p) for w in (256, 512, 1024)
-              for p in (1, 1600, 2400, 3200, 4800)]
+              for p in (1, 2400, 3200, 3840, 4800)]
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_cache.json")
 
 

@@ -60,10 +60,13 @@ Tuning tuning_of(const scalp_params_t* p) {
     return t;
 }
 
-// Assignment work items per cell: the largest cell is ceil(W / nx) x ceil(H / ny).
-int slices_of(const scalp_grid_t* g) {
+// Assignment work items per cell for workgroups of wg lanes: the largest cell
+// is ceil(W / nx) x ceil(H / ny) pixels, in ceil(. / 64) chunks of 64, split
+// evenly so that no item has more than wg / 64 chunks.
+int slices_of(const scalp_grid_t* g, int wg) {
     const long long cw = (g->width + g->nx - 1) / g->nx, ch = (g->height + g->ny - 1) / g->ny;
-    return (int)std::max<long long>(1, (cw * ch + kSlicePixels - 1) / kSlicePixels);
+    const long long chunks = (cw * ch + 63) / 64, per = wg / 64;
+    return (int)std::max<long long>(1, (chunks + per - 1) / per);
 }
 
 Img img_of(const scalp_grid_t* g, const scalp_params_t* p, long long pix, int sp) {
@@ -77,7 +80,7 @@ Img img_of(const scalp_grid_t* g, const scalp_params_t* p, long long pix, int sp
     const double r = grid_r(g->width, g->height, g->k_requested);
     im.spw = (float)(((double)p->m * (double)p->m) / (r * r));          // Eq. (3)
     im.gamma = p->gamma < 0.0f ? (float)(2.0 * r) : p->gamma;           // Sec. III-A.3
-    im.spl = slices_of(g);
+    im.spl = slices_of(g, tuning_of(p).wg);
     return im;
 }
 
@@ -433,7 +436,7 @@ bool batch_layout(const scalp_batch_desc_t* d, int n, BatchLayout* out) {
         if (d[i].pix_offset != N || d[i].sp_offset != K) return false;
         N += (long long)d[i].grid.width * d[i].grid.height;
         K += d[i].grid.num_sp;
-        I += (long long)d[i].grid.num_sp * slices_of(&d[i].grid);
+        I += (long long)d[i].grid.num_sp * slices_of(&d[i].grid, kMinAssignWG);   // most items
         if (N >= (1LL << 40) || K >= (1LL << 31) || I >= (1LL << 31)) return false;
     }
     out->items_total = I;

@@ -121,6 +121,70 @@ __device__ __forceinline__ void walk_path_lds(const float4* lds, int idx, int rw
 #undef SCALP_ACC
 }
 
+// The walk over a per-candidate LDS table of (colour distance, w) pairs: the
+// colour distance of a texel to the candidate does not depend on the pixel
+// the path starts from, so it is computed once per texel (same FP32
+// operations, same order) and every path sample costs two adds.  Stepping is
+// walk_path_lds's: biased remainder, carry as the minor-axis step; the loop
+// takes four samples per trip with loads issued ahead of the adds.
+__device__ __forceinline__ void walk_table(const float2* tab, int idx, int tw, int dx, int dy,
+                                           float& sc, float& sw) {
+    const int adx = dx < 0 ? -dx : dx;
+    const int ady = dy < 0 ? -dy : dy;
+    const bool xmaj = adx >= ady;
+    const int n = xmaj ? adx : ady;
+    if (n < 2) return;
+    const unsigned am = (unsigned)(xmaj ? ady : adx);
+    const int sx = dx < 0 ? -8 : 8;
+    const int sy = dy < 0 ? -8 * tw : 8 * tw;
+    const int smaj = xmaj ? sx : sy;
+    const int sdiag = smaj + (xmaj ? sy : sx);
+    const unsigned inc = 2u * am;
+    const unsigned bias = 0u - 2u * (unsigned)n;
+    unsigned e = 0u - (unsigned)n;
+    const char* q = reinterpret_cast<const char*>(tab + idx);
+#define SCALP_STEP()                                              \
+    do {                                                          \
+        unsigned t_;                                              \
+        const bool c_ = __builtin_add_overflow(e, inc, &t_);      \
+        e = t_ + (c_ ? bias : 0u);                                \
+        q += c_ ? sdiag : smaj;                                   \
+    } while (0)
+#define SCALP_ACC(v)                                              \
+    do {                                                          \
+        sc = sc + (v).x;                                          \
+        sw = sw + (v).y;                                          \
+    } while (0)
+    SCALP_STEP();
+    float2 fa = *reinterpret_cast<const float2*>(q);
+    int left = n - 2;
+    while (left >= 4) {                 // four samples per trip: less loop control
+        SCALP_STEP();
+        const float2 fb = *reinterpret_cast<const float2*>(q);
+        SCALP_STEP();
+        const float2 fc = *reinterpret_cast<const float2*>(q);
+        SCALP_ACC(fa);
+        SCALP_STEP();
+        const float2 fd = *reinterpret_cast<const float2*>(q);
+        SCALP_ACC(fb);
+        SCALP_STEP();
+        fa = *reinterpret_cast<const float2*>(q);
+        SCALP_ACC(fc);
+        SCALP_ACC(fd);
+        left -= 4;
+    }
+    while (left > 0) {
+        SCALP_STEP();
+        const float2 fb = *reinterpret_cast<const float2*>(q);
+        SCALP_ACC(fa);
+        fa = fb;
+        --left;
+    }
+    SCALP_ACC(fa);
+#undef SCALP_STEP
+#undef SCALP_ACC
+}
+
 __device__ __forceinline__ int round_coord(float v, int hi) {
     int e = (int)floorf(v + 0.5f);
     e = e < 0 ? 0 : e;

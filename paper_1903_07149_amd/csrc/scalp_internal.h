@@ -32,13 +32,13 @@ struct Img {
     int sp;           // first superpixel in the concatenated superpixel arrays
     float spw;        // m^2 / r^2 of Eq. (3)
     float gamma;      // gamma of Eq. (2)
-    int spl;          // assignment work items per grid cell (slices of its pixels)
+    int spl;          // assignment work items per grid cell (at most WG pixels each)
 };
 
-// Pixels of one assignment work item: cells larger than this are split into
-// several items, so that images with few, large superpixels still spread
-// over the whole chip.
-constexpr int kSlicePixels = 2048;
+// An assignment work item has at most as many pixels as its workgroup has
+// lanes (one pixel per lane): cells larger than that are split into several
+// items, which also spreads images with few, large superpixels over the chip.
+constexpr int kMinAssignWG = 256;
 
 struct Tuning {
     int wg;           // workgroup size of the assignment kernel (256 or 512)
@@ -46,7 +46,10 @@ struct Tuning {
 };
 
 int default_lds_pixels();
-constexpr int kMaxLdsPixels = 9728;   // 152 KiB of the 160 KiB LDS of a gfx950 CU
+// LDS budget of the assignment kernels in 16-byte units (two 8-byte tables of
+// this many entries for the grid form; one table of twice as many for the
+// window form): 152 KiB of the 160 KiB of a gfx950 CU.
+constexpr int kMaxLdsPixels = 9728;
 
 // Raises the per-kernel dynamic LDS limit of the assignment kernels (once per
 // process, before any launch or capture).

@@ -38,12 +38,12 @@ struct Cand {
     float l, a, b, x, y;
     int cx, cy;       // path endpoint
     float dcc, wc;    // colour distance and w of the endpoint sample
-    int staged;       // 1: the endpoint (hence every path to it) is inside the LDS rectangle
+    int tx0, ty0, tw, th;   // its LDS table: origin, row pitch, rows; tw == 0: paths read global memory
 };
 
+// Per work item: the candidates and the update bins.
 struct CellShared {
     Cand cand[9];
-    int rx0, ry0, rw, rh;
     unsigned long long bins[9][6];
 };
 
@@ -54,7 +54,20 @@ __device__ __forceinline__ int strip_of(int t, int cw, int ch) {
 }
 
 // Work item (cell, slice): pixels [t0, t1) of the cell in cell_pixel order,
-// slice boundaries on multiples of 64 so that every wave keeps an 8x8 block.
+// one per lane.  The cell's ceil(P / 64) 64-pixel chunks are split evenly
+// over its spl slices (spl is chosen on the host so that no slice has more
+// than WG pixels), and every wave keeps an 8x8 block.
+//
+// Candidates are taken one at a time (ascending slot, hence ascending k).
+// For candidate j the workgroup first writes, for every texel q of the
+// rectangle spanned by the item's pixels and j's endpoint (every path to j
+// lies inside it), the pair (d_c(q, j), w_q) into an LDS table; lanes then
+// walk their paths over the table, two adds per sample.  Two tables
+// alternate, so one barrier per candidate separates writing a table from
+// reading it and reading it from overwriting it.  A candidate whose
+// rectangle exceeds the budget (cap entries) walks its paths from global
+// memory, computing d_c per sample.  All of these give the same FP32 values
+// in the same order as the plain definition.
 template <int WG, bool ACCUM>
 __device__ __forceinline__ void process_cell(const Img& im, int cell, int slice,
                                              const float4* __restrict__ packed,
@@ -62,7 +75,7 @@ __device__ __forceinline__ void process_cell(const Img& im, int cell, int slice,
                                              const int* __restrict__ endpoints,
                                              int* __restrict__ labels,
                                              long long* __restrict__ acc, float lambda, int cap,
-                                             float4* lds, CellShared& sh) {
+                                             float2* lds, CellShared& sh) {
     const int tid = threadIdx.x;
     const int W = im.W, H = im.H, nx = im.nx, ny = im.ny;
     const int ci = cell / nx, cj = cell - ci * nx;
@@ -72,13 +85,21 @@ __device__ __forceinline__ void process_cell(const Img& im, int cell, int slice,
     const int cw = x1 - x0, ch = y1 - y0;
     const int P = cw * ch;
     const int spl = im.spl;
-    const int t0 = slice == 0 ? 0 : (int)(((long long)P * slice / spl) & ~63LL);
-    const int t1 = slice == spl - 1 ? P : (int)(((long long)P * (slice + 1) / spl) & ~63LL);
+    const int chunks = (P + 63) >> 6;
+    const int t0 = 64 * (int)((long long)chunks * slice / spl);
+    const int t1 = min(P, 64 * (int)((long long)chunks * (slice + 1) / spl));
+    // columns of the item's pixels: the 8-column strips its range touches
+    int ix0 = x0, ix1 = x1;
+    if (spl > 1 && t1 > t0) {
+        ix0 = x0 + 8 * strip_of(t0, cw, ch);
+        ix1 = min(x1, x0 + 8 * strip_of(t1 - 1, cw, ch) + 8);
+    }
 
     if (tid < 9) {
         Cand c;
         const int ii = ci + tid / 3 - 1, jj = cj + tid % 3 - 1;
-        c.staged = 0;
+        c.tw = 0;
+        c.tx0 = c.ty0 = c.th = 0;
         if (ii >= 0 && ii < ny && jj >= 0 && jj < nx) {
             const int k = ii * nx + jj;
             const float* ck = centres + 5LL * (im.sp + k);
@@ -90,6 +111,14 @@ __device__ __forceinline__ void process_cell(const Img& im, int cell, int slice,
             const float4 fc = img[(long long)c.cy * W + c.cx];
             c.dcc = colour_dist(fc, c.l, c.a, c.b);
             c.wc = fc.w;
+            const int ax0 = min(ix0, c.cx), ax1 = max(ix1, c.cx + 1);
+            const int ay0 = min(y0, c.cy), ay1 = max(y1, c.cy + 1);
+            // row pitch = 8 (mod 16) entries: the 8 rows of a wave's 8x8
+            // block then start on 4 different quarters of the LDS banks
+            const int pitch = (ax1 - ax0) + ((24 - (ax1 - ax0) % 16) % 16);
+            if ((long long)pitch * (ay1 - ay0) <= cap) {
+                c.tx0 = ax0; c.ty0 = ay0; c.tw = pitch; c.th = ay1 - ay0;
+            }
         } else {
             c.k = -1;
             c.l = c.a = c.b = c.x = c.y = 0.0f;
@@ -102,83 +131,77 @@ __device__ __forceinline__ void process_cell(const Img& im, int cell, int slice,
         for (int t = tid; t < 54; t += WG) (&sh.bins[0][0])[t] = 0ULL;
     }
     __syncthreads();
-    if (tid == 0) {
-        // Greedy LDS rectangle: the cell, grown by each candidate endpoint
-        // that keeps it within the budget.  Candidates left out walk their
-        // paths from global memory instead.
-        int rx0 = x0, rx1 = x1, ry0 = y0, ry1 = y1;
-        if (spl > 1 && t1 > t0) {
-            // the 8-column strips the slice touches, over the cell's rows
-            rx0 = x0 + 8 * strip_of(t0, cw, ch);
-            rx1 = min(x1, x0 + 8 * strip_of(t1 - 1, cw, ch) + 8);
-        }
-        const bool fits = (long long)(rx1 - rx0) * (ry1 - ry0) <= cap;
-        if (fits) {
-            for (int j = 0; j < 9; ++j) {
-                if (sh.cand[j].k < 0) continue;
-                const int cx = sh.cand[j].cx, cy = sh.cand[j].cy;
-                const int ax0 = min(rx0, cx), ax1 = max(rx1, cx + 1);
-                const int ay0 = min(ry0, cy), ay1 = max(ry1, cy + 1);
-                if ((long long)(ax1 - ax0) * (ay1 - ay0) <= cap) {
-                    rx0 = ax0; rx1 = ax1; ry0 = ay0; ry1 = ay1;
-                    sh.cand[j].staged = 1;
-                }
-            }
-            sh.rx0 = rx0; sh.ry0 = ry0; sh.rw = rx1 - rx0; sh.rh = ry1 - ry0;
-        } else {
-            sh.rx0 = rx0; sh.ry0 = ry0; sh.rw = 0; sh.rh = 0;
-        }
-    }
-    __syncthreads();
-    const int rx0 = sh.rx0, ry0 = sh.ry0, rw = sh.rw;
-    const int area = rw * sh.rh;
-    for (int e = tid; e < area; e += WG) {
-        const int r = e / rw;
-        const int c = e - r * rw;
-        lds[e] = img[(long long)(ry0 + r) * W + rx0 + c];
-    }
-    __syncthreads();
 
-    const int lane = tid & 63, wave = tid >> 6;
-    const int nchunks = (t1 - t0 + 63) >> 6;
     const float oml = 1.0f - lambda;
     const float gamma = im.gamma, spw = im.spw;
-    for (int chunk = wave; chunk < nchunks; chunk += WG / 64) {
-        const int t = t0 + chunk * 64 + lane;
-        if (t >= t1) continue;
-        int x, y;
-        cell_pixel(t, cw, ch, x, y);
+    const bool mine = tid < t1 - t0;               // this lane's pixel exists
+    int x = 0, y = 0;
+    if (mine) {
+        cell_pixel(t0 + tid, cw, ch, x, y);
         x += x0;
         y += y0;
-        const int p = y * W + x;
-        const float4 fp = img[p];
-        const int lidx = (y - ry0) * rw + (x - rx0);
-        float best = INFINITY;
-        int bestj = -1;
+    }
+    float best = INFINITY;
+    int bestj = -1;
+    int buf = 0;
 #pragma unroll 1
-        for (int j = 0; j < 9; ++j) {
-            const int k = sh.cand[j].k;
-            if (k < 0) continue;
-            const float l = sh.cand[j].l, a = sh.cand[j].a, b = sh.cand[j].b;
-            const int dx = sh.cand[j].cx - x, dy = sh.cand[j].cy - y;
-            const float dcp = colour_dist(fp, l, a, b);
-            float sc = dcp;      // sample i = 0 is p itself
-            float sw = fp.w;
-            if (sh.cand[j].staged)
-                walk_path_lds(lds, lidx, rw, dx, dy, l, a, b, sc, sw);
-            else
+    for (int j = 0; j < 9; ++j) {
+        const int k = sh.cand[j].k;
+        if (k < 0) continue;                       // uniform
+        const float l = sh.cand[j].l, a = sh.cand[j].a, b = sh.cand[j].b;
+        const int cx = sh.cand[j].cx, cy = sh.cand[j].cy;
+        const int tw = sh.cand[j].tw, tx0 = sh.cand[j].tx0, ty0 = sh.cand[j].ty0;
+        float2* tab = lds + (buf ? cap : 0);
+        if (tw > 0) {                              // uniform
+            // entries past the rectangle's width pad the pitch; they are
+            // filled from clamped columns and never read by a path
+            const int area = tw * sh.cand[j].th;
+            // entry e = r * tw + c; lanes step by WG entries = (dr, dc)
+            const int dr = WG / tw, dc = WG - dr * tw;
+            int r = tid / tw, c = tid - r * tw;
+            const float4* row = img + (long long)(ty0 + r) * W;
+            for (int e = tid; e < area; e += WG) {
+                const float4 f = row[min(tx0 + c, W - 1)];
+                tab[e] = make_float2(colour_dist(f, l, a, b), f.w);
+                c += dc;
+                const bool wrap = c >= tw;
+                c -= wrap ? tw : 0;
+                row += (long long)(dr + (wrap ? 1 : 0)) * W;
+            }
+            __syncthreads();
+            buf ^= 1;
+        }
+        const float ccx = sh.cand[j].x, ccy = sh.cand[j].y;
+        const float dcc = sh.cand[j].dcc, wc = sh.cand[j].wc;
+        if (mine) {
+            const int dx = cx - x, dy = cy - y;
+            float dcp, sc, sw;
+            if (tw > 0) {
+                const int lidx = (y - ty0) * tw + (x - tx0);
+                const float2 e0 = tab[lidx];
+                dcp = e0.x;
+                sc = dcp;                          // sample i = 0 is p itself
+                sw = e0.y;
+                walk_table(tab, lidx, tw, dx, dy, sc, sw);
+            } else {
+                const int p = y * W + x;
+                const float4 fp = img[p];
+                dcp = colour_dist(fp, l, a, b);
+                sc = dcp;
+                sw = fp.w;
                 walk_path(img, p, 1, W, dx, dy, l, a, b, sc, sw);
+            }
             const int adx = dx < 0 ? -dx : dx, ady = dy < 0 ? -dy : dy;
             const int n = adx > ady ? adx : ady;
-            if (n > 0) {         // sample i = n is the endpoint
-                sc = sc + sh.cand[j].dcc;
-                sw = sw + sh.cand[j].wc;
+            if (n > 0) {                           // sample i = n is the endpoint
+                sc = sc + dcc;
+                sw = sw + wc;
             }
             const float np = (float)(n + 1);
             const float A = lambda * dcp + oml * (sc / np);      // Eq. (1)
             const float B = 1.0f + gamma * (sw / np);            // Eq. (2)
-            const float ex = (float)x - sh.cand[j].x;
-            const float ey = (float)y - sh.cand[j].y;
+            const float ex = (float)x - ccx;
+            const float ey = (float)y - ccy;
             const float ds = ex * ex + ey * ey;
             const float D = A * B + ds * spw;                    // Eq. (3)
             if (D < best) {
@@ -186,10 +209,15 @@ __device__ __forceinline__ void process_cell(const Img& im, int cell, int slice,
                 bestj = j;
             }
         }
-        if (bestj < 0) bestj = 4;   // only reachable with non-finite input
-        labels[im.pix + p] = sh.cand[bestj].k;
+    }
+
+    if (mine) {
+        const int p = y * W + x;
+        const int bj = bestj < 0 ? 4 : bestj;   // bestj < 0 only with non-finite input
+        labels[im.pix + p] = sh.cand[bj].k;
         if (ACCUM) {
-            unsigned long long* bin = sh.bins[bestj];
+            const float4 fp = img[p];
+            unsigned long long* bin = sh.bins[bj];
             atomicAdd(bin + 0, 1ULL);
             atomicAdd(bin + 1, (unsigned long long)x);
             atomicAdd(bin + 2, (unsigned long long)y);
@@ -218,13 +246,13 @@ __global__ __launch_bounds__(WG) void k_assign(Img im, const float4* __restrict_
                                                int* __restrict__ labels,
                                                long long* __restrict__ acc, int* ctrl,
                                                float lambda, int cap) {
-    extern __shared__ float4 lds_dyn[];
+    extern __shared__ float2 tab_dyn[];
     __shared__ CellShared sh;
     if (ACCUM && blockIdx.x == 0 && threadIdx.x == 0) ctrl[kCtrlProjCount] = 0;
     const int item = xcd_remap(blockIdx.x, gridDim.x);
     const int cell = item / im.spl;
     process_cell<WG, ACCUM>(im, cell, item - cell * im.spl, packed, centres, endpoints, labels,
-                            acc, lambda, cap, lds_dyn, sh);
+                            acc, lambda, cap, tab_dyn, sh);
 }
 
 // At most 64 VGPRs (8 waves per SIMD): two 1024-thread workgroups per CU.
@@ -239,7 +267,7 @@ void k_assign_persistent(const Img* __restrict__ imgs,
                                                           int* __restrict__ labels,
                                                           long long* __restrict__ acc, int* ctrl,
                                                           float lambda, int cap) {
-    extern __shared__ float4 lds_dyn[];
+    extern __shared__ float2 tab_dyn[];
     __shared__ CellShared sh;
     __shared__ int item;
     if (blockIdx.x == 0 && threadIdx.x == 0) ctrl[kCtrlProjCount] = 0;
@@ -254,7 +282,7 @@ void k_assign_persistent(const Img* __restrict__ imgs,
         const int local = it - item_start[i];
         const int cell = local / im.spl;
         process_cell<WG, true>(im, cell, local - cell * im.spl, packed, centres, endpoints, labels,
-                               acc, lambda, cap, lds_dyn, sh);
+                               acc, lambda, cap, tab_dyn, sh);
     }
 }
 
@@ -272,8 +300,7 @@ __global__ __launch_bounds__(WG) void k_assign_window(Img im, const float4* __re
                                                       const int* __restrict__ endpoints,
                                                       unsigned long long* __restrict__ keys,
                                                       int R, float lambda, int cap) {
-    extern __shared__ float4 lds_dyn[];
-    __shared__ int rect[4];
+    extern __shared__ float2 win_tab[];
     const int tid = threadIdx.x;
     const int k = xcd_remap(blockIdx.x, gridDim.x);
     const int W = im.W, H = im.H;
@@ -285,19 +312,20 @@ __global__ __launch_bounds__(WG) void k_assign_window(Img im, const float4* __re
     const int cy = min(max(endpoints[2LL * (im.sp + k) + 1], 0), H - 1);
     const int x0 = max(wx - R, 0), x1 = min(wx + R, W - 1) + 1;
     const int y0 = max(wy - R, 0), y1 = min(wy + R, H - 1) + 1;
-    // the paths of the window end at (cx, cy): stage bbox(window, endpoint)
+    // the paths of the window end at (cx, cy): over bbox(window, endpoint)
+    // the table holds (d_c(q, k), w_q), two 8-byte entries per 16-byte unit
     const int rx0 = min(x0, cx), rx1 = max(x1, cx + 1);
     const int ry0 = min(y0, cy), ry1 = max(y1, cy + 1);
-    const bool staged = (long long)(rx1 - rx0) * (ry1 - ry0) <= cap;
+    const bool staged = (long long)(rx1 - rx0) * (ry1 - ry0) <= 2LL * cap;
     const int rw = rx1 - rx0;
     if (staged) {
         const int area = rw * (ry1 - ry0);
         for (int e = tid; e < area; e += WG) {
             const int r = e / rw;
-            lds_dyn[e] = img[(long long)(ry0 + r) * W + rx0 + (e - r * rw)];
+            const float4 f = img[(long long)(ry0 + r) * W + rx0 + (e - r * rw)];
+            win_tab[e] = make_float2(colour_dist(f, l, a, b), f.w);
         }
     }
-    (void)rect;
     __syncthreads();
     const float4 fc = img[(long long)cy * W + cx];
     const float dcc = colour_dist(fc, l, a, b), wc = fc.w;
@@ -317,7 +345,7 @@ __global__ __launch_bounds__(WG) void k_assign_window(Img im, const float4* __re
         const float dcp = colour_dist(fp, l, a, b);
         float sc = dcp, sw = fp.w;
         if (staged)
-            walk_path_lds(lds_dyn, (y - ry0) * rw + (x - rx0), rw, dx, dy, l, a, b, sc, sw);
+            walk_table(win_tab, (y - ry0) * rw + (x - rx0), rw, dx, dy, sc, sw);
         else
             walk_path(img, p, 1, W, dx, dy, l, a, b, sc, sw);
         const int adx = dx < 0 ? -dx : dx, ady = dy < 0 ? -dy : dy;
@@ -674,6 +702,8 @@ void allow_lds(K kernel, size_t bytes) {
 
 }  // namespace
 
+// 4800 x 16 B of tables (75 KiB) fit twice in 160 KiB: two 1024-thread
+// workgroups per CU.
 int default_lds_pixels() { return 4800; }
 
 int launch_write_bytes(void* dst, const void* src, size_t n, hipStream_t s) {

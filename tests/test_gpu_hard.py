@@ -34,7 +34,7 @@ def _image(W, H, seed, regions=None):
 # one superpixel per pixel, and cells too large for the LDS halo.
 SMALL = [(97, 61, 30), (256, 200, 100), (481, 321, 250), (37, 5, 7), (1, 1, 1), (1, 50, 5),
          (50, 1, 5), (64, 64, 4096), (300, 200, 2), (129, 77, 1)]
-# tuning variants: default (1024 threads, 4800-texel halo); halo too small for
+# tuning variants: default (1024 threads, 4800-unit LDS tables); tables too small for
 # most endpoints; budget below one cell (every path from global memory);
 # 256- and 512-thread workgroups
 TUNINGS = [dict(), dict(lds_pixels=900), dict(lds_pixels=1), dict(wg_size=256),

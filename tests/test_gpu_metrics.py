@@ -10,7 +10,7 @@ from gpu_util import dev, host, needs_gpu, say, torch
 pytestmark = [pytest.mark.gpu, needs_gpu]
 
 
-@pytest.mark.parametrize("eps", [2.0, 1.0, 3.5])
+@pytest.mark.parametrize("eps", [2.0, 1.0, 3.5, 5.0])
 @pytest.mark.parametrize("H,W,K,R,seed", [(37, 53, 9, 5, 1), (128, 96, 40, 12, 2), (1, 70, 4, 3, 3),
                                           (64, 1, 2, 2, 4)])
 def test_metrics_match_definitions(H, W, K, R, seed, eps):
@@ -27,6 +27,17 @@ def test_metrics_match_definitions(H, W, K, R, seed, eps):
     assert abs(got["co"] - ref["co"]) <= 1e-12 * max(1.0, ref["co"])
     assert got["gt_boundary"] == int(M.boundary(gt).sum())
     assert got["sp_boundary"] == int(M.boundary(sp).sum())
+
+
+def test_boundary_recall_at_the_tolerance():
+    """Offsets at exactly epsilon do not count (the oracle's closed-form case)."""
+    from paper_1903_07149_amd.metrics import metrics
+    g = np.zeros((30, 30), np.int32)
+    g[10, 10] = 1
+    s = np.zeros_like(g)
+    s[14, 14] = 1
+    got = metrics(dev(s), dev(g), num_sp=2, num_regions=2, epsilon=5.0)
+    assert got["br"] == 2 / 5 == M.boundary_recall(s, g, 5.0)
 
 
 def test_metrics_of_a_run_and_ablation():

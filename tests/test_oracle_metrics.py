@@ -46,6 +46,41 @@ def test_boundary_recall_tolerance(shift, expected):
     assert M.boundary_recall(s, g, eps=2.0) == expected
 
 
+@pytest.mark.parametrize("eps", [1.0, 2.0, 3.5, 5.0])
+def test_boundary_recall_brute_force_blocky(eps):
+    """Sparse boundaries (blocky maps) so that the tolerance decides: for
+    eps = 5 the offsets (3, 4) lie exactly at distance eps and do not count."""
+    rng = np.random.default_rng(int(eps * 10))
+    H, W = 30, 33
+    for _ in range(3):
+        g = np.kron(rng.integers(0, 4, (H // 6 + 1, W // 6 + 1)), np.ones((6, 6), np.int64))[:H, :W]
+        s = np.kron(rng.integers(0, 5, (H // 5 + 1, W // 5 + 1)), np.ones((5, 5), np.int64))[:H, :W]
+        s = np.roll(s, (2, 3), axis=(0, 1))
+        bg, bs = M.boundary(g), M.boundary(s)
+        qs = np.argwhere(bs)
+        hits = 0
+        for y, x in np.argwhere(bg):
+            d2 = (qs[:, 0] - y) ** 2 + (qs[:, 1] - x) ** 2
+            hits += bool((d2 < eps * eps).any())
+        got = M.boundary_recall(s, g, eps)
+        assert math.isclose(got, hits / bg.sum())
+        assert 0.0 < got < 1.0 or eps >= 3.5
+
+
+def test_boundary_recall_at_the_tolerance():
+    """Two one-pixel islands, ground truth at (10, 10) and superpixel at
+    (14, 14): each boundary is the island and its 4 neighbours.  With eps = 5
+    the ground-truth pixels (11, 10) and (10, 11) are at distance sqrt(20)
+    from (13, 14) / (14, 13); (10, 10) is at exactly 5 (offsets (3, 4) and
+    (4, 3)) and does not count; (9, 10) and (10, 9) are farther.  BR = 2/5."""
+    g = np.zeros((30, 30), np.int64)
+    g[10, 10] = 1
+    s = np.zeros_like(g)
+    s[14, 14] = 1
+    assert M.boundary_recall(s, g, eps=5.0) == 2 / 5
+    assert M.boundary_recall(s, g, eps=5.0 + 1e-9) == 3 / 5
+
+
 def test_boundary_recall_brute_force():
     rng = np.random.default_rng(3)
     for _ in range(5):

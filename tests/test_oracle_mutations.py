@@ -45,9 +45,6 @@ MUTATIONS = {
 # Pin files that are expected to catch each family of mistakes (all files
 # are run for a mutation not listed here).
 WHERE = {
-    "window_off_by_one": (H, "for (int x = wx - R; x <= wx + R; x++) {",
-                          "for (int x = wx - R; x < wx + R; x++) {"),
-    "window_ties_to_last": (H, "                if (D < d[p]) {", "                if (D <= d[p]) {"),
     "soft_bwd_drop_lambda": ["tests/test_oracle_soft.py"],
     "soft_bwd_drop_gamma": ["tests/test_oracle_soft.py"],
     "soft_bwd_softmax_sign": ["tests/test_oracle_soft.py"],
@@ -78,3 +75,54 @@ def test_mutation_is_caught(name, tmp_path):
                        timeout=600)
     assert r.returncode == 1 and " failed" in r.stdout, (
         f"planted mistake '{name}' survived the pins:\n{r.stdout[-2000:]}")
+
+
+# Mistakes planted in the numpy parts of the oracle (quality metrics and
+# per-pixel maps), with the pin file expected to catch each.
+PM = "metrics.py"
+PP = "maps.py"
+PY_MUTATIONS = {
+    "br_radius_inclusive": (PM, "if dx * dx + dy * dy >= eps * eps:", "if dx * dx + dy * dy > eps * eps:"),
+    "br_square_window": (PM, "if dx * dx + dy * dy >= eps * eps:", "if False:"),
+    "asa_sum_not_max": (PM, "t.max(axis=1).sum()", "t.sum(axis=1).max()"),
+    "ue_counts_every_region": (PM, "((size - t) * (t > 0)).sum()", "(size - t).sum()"),
+    "co_no_border_edges": (PM, "edges += np.bincount(L[0, :], minlength=K) + np.bincount(L[-1, :], minlength=K)",
+                           "pass"),
+    "boundary_no_vertical": (PP, "d = M[1:, :] != M[:-1, :]     # vertical neighbours differ",
+                             "d = np.zeros_like(M[1:, :], bool)"),
+    "frequency_last_map_only": (PP, "count += b", "count = b.astype(np.int64)"),
+    "gradient_no_half": (PP, "gx = 0.5 * (right - left)", "gx = (right - left)"),
+    "gradient_wraps_border": (PP, "right = f[:, np.minimum(xs + 1, W - 1), :]",
+                              "right = f[:, (xs + 1) % W, :]"),
+    "contour_not_normalised": (PP, "return (g / m).astype(np.float32)", "return g.astype(np.float32)"),
+}
+PY_WHERE = {PM: ["tests/test_oracle_metrics.py"], PP: ["tests/test_oracle_maps.py"]}
+
+
+@pytest.mark.parametrize("name", sorted(PY_MUTATIONS))
+def test_python_mutation_is_caught(name, tmp_path):
+    fname, old, new = PY_MUTATIONS[name]
+    work = tmp_path / "oracle"
+    shutil.copytree(ORACLE, work, ignore=shutil.ignore_patterns("*.so", "__pycache__"))
+    src = (work / fname).read_text()
+    assert src.count(old) == 1, f"mutation site for {name} not found exactly once"
+    (work / fname).write_text(src.replace(old, new))
+    env = dict(os.environ, SCALP_ORACLE_COPY_ROOT=str(tmp_path))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        *PY_WHERE[fname]], cwd=ROOT, env=env, capture_output=True, text=True,
+                       timeout=600)
+    assert r.returncode == 1 and " failed" in r.stdout, (
+        f"planted mistake '{name}' survived the pins:\n{r.stdout[-2000:]}")
+
+
+def test_python_copy_is_the_one_tested(tmp_path):
+    """The harness really swaps the package: an unmodified copy passes and a
+    copy whose module raises on import fails."""
+    work = tmp_path / "oracle"
+    shutil.copytree(ORACLE, work, ignore=shutil.ignore_patterns("*.so", "__pycache__"))
+    (work / PP).write_text((work / PP).read_text() + "\nraise ImportError('planted')\n")
+    env = dict(os.environ, SCALP_ORACLE_COPY_ROOT=str(tmp_path))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        "tests/test_oracle_maps.py"], cwd=ROOT, env=env, capture_output=True, text=True,
+                       timeout=600)
+    assert r.returncode != 0 and "planted" in r.stdout + r.stderr
