@@ -8,9 +8,11 @@
 // membership); the rounding is piecewise constant, so it carries no gradient.
 //
 // Forward, per iteration:
-//   k_soft_assign  workgroup per (image, cell): LDS-staged halo, per-lane path
-//                  walks as in the hard kernel, softmax over the 9 slots;
-//                  writes Q and the factors A (Eq. (1)) and B (Eq. (2)).
+//   k_soft_assign  workgroup per (image, cell): per-candidate LDS tables of
+//                  (colour distance, w) and per-lane path walks as in the
+//                  hard kernel; writes D and the factors A (Eq. (1)) and
+//                  B (Eq. (2)).
+//   k_soft_softmax FP64 softmax of -D/T over the 9 slots, written as Q.
 //   k_soft_update  workgroup per (image, superpixel): gathers Q over the 3x3
 //                  cell block in a fixed order (FP64 partial sums, tree
 //                  reduction): deterministic, no atomics.
@@ -45,6 +47,9 @@ struct SoftImg {
 // A superpixel whose soft mass is below a millionth of a pixel counts as
 // empty and keeps its centre (as an empty one does in the hard update).
 constexpr double kZMin = 1e-6;
+
+// Softmax weight below which a slot's path terms are left out of the backward.
+constexpr float kQMin = 0x1p-24f;
 
 struct SoftCand {
     int k;
@@ -141,12 +146,19 @@ __global__ __launch_bounds__(WG) void k_soft_init(SoftImg s, const float4* __res
     if (tid < 5) theta0[(5LL * b) * s.K + 5LL * k + tid] = (float)(red[tid][0] / red[5][0]);
 }
 
+// One workgroup per (image, cell).  As in the hard assignment, candidates are
+// taken one at a time: the workgroup writes a table of (d_c(q, k), w_q) over
+// the rectangle spanned by the cell and the candidate's endpoint (two tables
+// alternate, one barrier per candidate), and every lane walks its pixels'
+// paths over it, two adds per sample; a rectangle beyond the budget walks
+// from global memory.  Same FP32 operations, same order.
 template <int WG>
 __global__ __launch_bounds__(WG) void k_soft_assign(SoftImg s, const float4* __restrict__ packed,
                                                     const float* __restrict__ theta_prev,
                                                     float* __restrict__ q, float* __restrict__ fa,
                                                     float* __restrict__ fb, int cap) {
     extern __shared__ float4 lds_dyn[];
+    float2* tabs = reinterpret_cast<float2*>(lds_dyn);          // two tables of cap entries
     __shared__ SoftShared sh;
     const int item = xcd_remap(blockIdx.x, gridDim.x);
     const int b = item / s.K, cell = item - b * s.K;
@@ -158,58 +170,84 @@ __global__ __launch_bounds__(WG) void k_soft_assign(SoftImg s, const float4* __r
     const float4* __restrict__ img = packed + (long long)b * s.N;
     load_candidates(s, ci, cj, theta_prev + 5LL * s.K * b, img, sh);
     __syncthreads();
-    plan_rect(x0, x1, y0, y1, cap, sh);
-    __syncthreads();
-    const int rx0 = sh.rx0, ry0 = sh.ry0, rw = sh.rw;
-    const int area = rw * sh.rh;
-    for (int e = tid; e < area; e += WG) {
-        const int r = e / rw;
-        lds_dyn[e] = img[(long long)(ry0 + r) * W + rx0 + (e - r * rw)];
-    }
-    __syncthreads();
     const int cw = x1 - x0, ch = y1 - y0, P = cw * ch;
     const int lane = tid & 63, wave = tid >> 6;
     const float lambda = s.lambda, oml = 1.0f - lambda;
     const long long base = 9LL * s.N * b;
-    for (int chunk = wave; chunk * 64 < P; chunk += WG / 64) {
-        const int t = chunk * 64 + lane;
-        if (t >= P) continue;
-        int x, y;
-        cell_pixel(t, cw, ch, x, y);
-        x += x0;
-        y += y0;
-        const int p = y * W + x;
-        const float4 fp = img[p];
-        const int lidx = (y - ry0) * rw + (x - rx0);
-        // D of each slot goes to the Q buffer (k_soft_softmax turns it into
-        // Q); A and B go straight to the saved factors.
+    int buf = 0;
 #pragma unroll 1
-        for (int j = 0; j < 9; ++j) {
-            const long long o = base + (long long)j * s.N + p;
-            if (sh.cand[j].k < 0) {
+    for (int j = 0; j < 9; ++j) {
+        const int k = sh.cand[j].k;
+        if (k < 0) {                                            // uniform
+            for (int chunk = wave; chunk * 64 < P; chunk += WG / 64) {
+                const int t = chunk * 64 + lane;
+                if (t >= P) continue;
+                int x, y;
+                cell_pixel(t, cw, ch, x, y);
+                const long long o = base + (long long)j * s.N + (long long)(y + y0) * W + x + x0;
                 fa[o] = 0.0f;
                 fb[o] = 0.0f;
-                continue;
             }
-            const float l = sh.cand[j].l, a = sh.cand[j].a, bb = sh.cand[j].b;
-            const int dx = sh.cand[j].cx - x, dy = sh.cand[j].cy - y;
-            const float dcp = colour_dist(fp, l, a, bb);
-            float sc = dcp, sw = fp.w;
-            if (sh.cand[j].staged)
-                walk_path_lds(lds_dyn, lidx, rw, dx, dy, l, a, bb, sc, sw);
-            else
+            continue;
+        }
+        const float l = sh.cand[j].l, a = sh.cand[j].a, bb = sh.cand[j].b;
+        const int cx = sh.cand[j].cx, cy = sh.cand[j].cy;
+        const int tx0 = min(x0, cx), ty0 = min(y0, cy);
+        const int rwid = max(x1, cx + 1) - tx0, th = max(y1, cy + 1) - ty0;
+        const int tw = rwid + (24 - rwid % 16) % 16;            // pitch: 8 (mod 16) entries
+        const bool staged = (long long)tw * th <= cap;
+        float2* tab = tabs + (buf ? cap : 0);
+        if (staged) {                                           // uniform
+            const int area = tw * th;
+            for (int e = tid; e < area; e += WG) {
+                const int r = e / tw;
+                const int c = e - r * tw;
+                const float4 f = img[(long long)(ty0 + r) * W + min(tx0 + c, W - 1)];
+                tab[e] = make_float2(colour_dist(f, l, a, bb), f.w);
+            }
+            __syncthreads();
+            buf ^= 1;
+        }
+        const float dcc = sh.cand[j].dcc, wc = sh.cand[j].wc;
+        const float ccx = sh.cand[j].x, ccy = sh.cand[j].y;
+        for (int chunk = wave; chunk * 64 < P; chunk += WG / 64) {
+            const int t = chunk * 64 + lane;
+            if (t >= P) continue;
+            int x, y;
+            cell_pixel(t, cw, ch, x, y);
+            x += x0;
+            y += y0;
+            const int p = y * W + x;
+            const int dx = cx - x, dy = cy - y;
+            float dcp, sc, sw;
+            if (staged) {
+                const int lidx = (y - ty0) * tw + (x - tx0);
+                const float2 e0 = tab[lidx];
+                dcp = e0.x;
+                sc = dcp;
+                sw = e0.y;
+                walk_table(tab, lidx, tw, dx, dy, sc, sw);
+            } else {
+                const float4 fp = img[p];
+                dcp = colour_dist(fp, l, a, bb);
+                sc = dcp;
+                sw = fp.w;
                 walk_path(img, p, 1, W, dx, dy, l, a, bb, sc, sw);
+            }
             const int adx = dx < 0 ? -dx : dx, ady = dy < 0 ? -dy : dy;
             const int n = adx > ady ? adx : ady;
             if (n > 0) {
-                sc = sc + sh.cand[j].dcc;
-                sw = sw + sh.cand[j].wc;
+                sc = sc + dcc;
+                sw = sw + wc;
             }
             const float np = (float)(n + 1);
             const float A = lambda * dcp + oml * (sc / np);
             const float Bw = 1.0f + s.gamma * (sw / np);
-            const float ex = (float)x - sh.cand[j].x, ey = (float)y - sh.cand[j].y;
+            const float ex = (float)x - ccx, ey = (float)y - ccy;
             const float D = A * Bw + (ex * ex + ey * ey) * s.spw;
+            // D goes to the Q buffer (k_soft_softmax turns it into Q); A and B
+            // go straight to the saved factors
+            const long long o = base + (long long)j * s.N + p;
             q[o] = D;
             fa[o] = A;
             fb[o] = Bw;
@@ -310,7 +348,7 @@ __global__ __launch_bounds__(WG) void k_soft_update(SoftImg s, const float* __re
 // ------------------------------------------------------------------ backward
 
 // Soft-update backward (theta_t = sum Q feat / Z) and softmax backward:
-// gd[j] = dL/dD_pj.  gf += dL/df_p through the update.
+// gd[j] = dL/dD_pj (0 where Q_pj < kQMin).  gf += dL/df_p through the update.
 __global__ void k_soft_bwd_update(SoftImg s, int first, const float* __restrict__ q,
                                   const double* __restrict__ z, const float* __restrict__ theta,
                                   const float4* __restrict__ packed,
@@ -350,8 +388,12 @@ __global__ void k_soft_bwd_update(SoftImg s, int first, const float* __restrict_
             }
             dot += Q[j] * G[j];
         }
+        // A slot's whole path contribution is proportional to Q_pj; below
+        // FP32's unit roundoff (2^-24) it is dropped, and the path pass skips
+        // the slot (at low T most pixels have one slot above it).
 #pragma unroll
-        for (int j = 0; j < 9; ++j) gd[qb + (long long)j * s.N] = -s.inv_t * Q[j] * (G[j] - dot);
+        for (int j = 0; j < 9; ++j)
+            gd[qb + (long long)j * s.N] = Q[j] < kQMin ? 0.0f : -s.inv_t * Q[j] * (G[j] - dot);
         float4 o = gf[i];
         o.x += gfl;
         o.y += gfa;
@@ -380,8 +422,12 @@ __global__ __launch_bounds__(WG) void k_soft_bwd_path(SoftImg s, const float4* _
                                                       float* __restrict__ gth_prev, int cap) {
     extern __shared__ float4 lds_dyn[];
     __shared__ SoftShared sh;
-    float4* acc = lds_dyn;                                     // [cap] dL/d(l,a,b,w)
-    float* alpha = reinterpret_cast<float*>(lds_dyn + cap);    // [cap]
+    // five planar float tiles of cap texels: dL/dl, dL/da, dL/db, dL/dw, alpha
+    float* accx = reinterpret_cast<float*>(lds_dyn);
+    float* accy = accx + cap;
+    float* accz = accy + cap;
+    float* accw = accz + cap;
+    float* alpha = accw + cap;
     const int item = xcd_remap(blockIdx.x, gridDim.x);
     const int b = item / s.K, cell = item - b * s.K;
     const int tid = threadIdx.x;
@@ -399,7 +445,10 @@ __global__ __launch_bounds__(WG) void k_soft_bwd_path(SoftImg s, const float4* _
     const int rx0 = sh.rx0, ry0 = sh.ry0, rw = sh.rw;
     const int area = rw * sh.rh;
     for (int e = tid; e < area; e += WG) {
-        acc[e] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        accx[e] = 0.0f;
+        accy[e] = 0.0f;
+        accz[e] = 0.0f;
+        accw[e] = 0.0f;
         alpha[e] = 0.0f;
     }
     __syncthreads();
@@ -411,79 +460,96 @@ __global__ __launch_bounds__(WG) void k_soft_bwd_path(SoftImg s, const float4* _
         const SoftCand c = sh.cand[j];
         if (c.k < 0) continue;                                  // uniform
         float gk[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+        // every path to this slot ends on its endpoint: that sample is
+        // reduced over the wave and added once (staged case)
+        const int lic = (c.cy - ry0) * rw + (c.cx - rx0);
         for (int chunk = wave; chunk * 64 < P; chunk += WG / 64) {
             const int t = chunk * 64 + lane;
-            if (t >= P) continue;
-            int x, y;
-            cell_pixel(t, cw, ch, x, y);
-            x += x0;
-            y += y0;
-            const int p = y * W + x;
-            const long long o = base + (long long)j * s.N + p;
-            const float g = gd[o];
-            if (g == 0.0f) continue;
-            const float A = fa[o], Bw = fb[o];
-            const int dx = c.cx - x, dy = c.cy - y;
-            const int adx = dx < 0 ? -dx : dx, ady = dy < 0 ? -dy : dy;
-            const int n = adx > ady ? adx : ady;
-            const float inv_np = 1.0f / (float)(n + 1);
-            const float cf = 2.0f * g * Bw * oml * inv_np;      // per path sample, times (f_q - f_k)
-            const float cw_ = g * A * s.gamma * inv_np;         // per path sample: dL/dw_q
-            const float4 fp = img[p];
-            const float lf = 2.0f * g * Bw * lambda;            // lambda term of p
-            const float dl = fp.x - c.l, da = fp.y - c.a, db = fp.z - c.b;
-            gk[0] -= lf * dl;
-            gk[1] -= lf * da;
-            gk[2] -= lf * db;
-            gk[3] -= 2.0f * g * s.spw * ((float)x - c.x);
-            gk[4] -= 2.0f * g * s.spw * ((float)y - c.y);
-            // the path, samples i = 0 .. n (p itself included)
-            const bool xmaj = adx >= ady;
-            const int am = xmaj ? ady : adx;
-            const int two_n = 2 * n, inc = 2 * am;
-            int rem = n;
-            if (c.staged) {
-                const int stx = dx < 0 ? -1 : 1, sty = dy < 0 ? -rw : rw;
-                const int smaj = xmaj ? stx : sty;
-                const int sdiag = smaj + (xmaj ? sty : stx);
-                int li = (y - ry0) * rw + (x - rx0);
-                atomicAdd(&acc[li].x, lf * dl);
-                atomicAdd(&acc[li].y, lf * da);
-                atomicAdd(&acc[li].z, lf * db);
-                for (int i = 0; i <= n; ++i) {
-                    if (i > 0) {
-                        rem += inc;
-                        const bool st = rem >= two_n;
-                        rem -= st ? two_n : 0;
-                        li += st ? sdiag : smaj;
+            float cf_end = 0.0f, cw_end = 0.0f;
+            int x = 0, y = 0, p = 0;
+            float g = 0.0f;
+            long long o = 0;
+            if (t < P) {
+                cell_pixel(t, cw, ch, x, y);
+                x += x0;
+                y += y0;
+                p = y * W + x;
+                o = base + (long long)j * s.N + p;
+                g = gd[o];
+            }
+            if (g != 0.0f) {
+                const float A = fa[o], Bw = fb[o];
+                const int dx = c.cx - x, dy = c.cy - y;
+                const int adx = dx < 0 ? -dx : dx, ady = dy < 0 ? -dy : dy;
+                const int n = adx > ady ? adx : ady;
+                const float inv_np = 1.0f / (float)(n + 1);
+                const float cf = 2.0f * g * Bw * oml * inv_np;      // per path sample, times (f_q - f_k)
+                const float cw_ = g * A * s.gamma * inv_np;         // per path sample: dL/dw_q
+                const float4 fp = img[p];
+                const float lf = 2.0f * g * Bw * lambda;            // lambda term of p
+                const float dl = fp.x - c.l, da = fp.y - c.a, db = fp.z - c.b;
+                gk[0] -= lf * dl;
+                gk[1] -= lf * da;
+                gk[2] -= lf * db;
+                gk[3] -= 2.0f * g * s.spw * ((float)x - c.x);
+                gk[4] -= 2.0f * g * s.spw * ((float)y - c.y);
+                // the path, samples i = 0 .. n (p itself included)
+                const bool xmaj = adx >= ady;
+                const int am = xmaj ? ady : adx;
+                const int two_n = 2 * n, inc = 2 * am;
+                int rem = n;
+                if (c.staged) {
+                    const int stx = dx < 0 ? -1 : 1, sty = dy < 0 ? -rw : rw;
+                    const int smaj = xmaj ? stx : sty;
+                    const int sdiag = smaj + (xmaj ? sty : stx);
+                    int li = (y - ry0) * rw + (x - rx0);
+                    atomicAdd(&accx[li], lf * dl);
+                    atomicAdd(&accy[li], lf * da);
+                    atomicAdd(&accz[li], lf * db);
+                    for (int i = 0; i < n; ++i) {                   // samples 0 .. n-1
+                        if (i > 0) {
+                            rem += inc;
+                            const bool st = rem >= two_n;
+                            rem -= st ? two_n : 0;
+                            li += st ? sdiag : smaj;
+                        }
+                        atomicAdd(&alpha[li], cf);
+                        atomicAdd(&accw[li], cw_);
                     }
-                    atomicAdd(&alpha[li], cf);
-                    atomicAdd(&acc[li].w, cw_);
+                    cf_end = cf;                                    // sample n: the endpoint
+                    cw_end = cw_;
+                } else {
+                    const int stx = dx < 0 ? -1 : 1, sty = dy < 0 ? -W : W;
+                    const int smaj = xmaj ? stx : sty;
+                    const int sdiag = smaj + (xmaj ? sty : stx);
+                    int gi = p;
+                    unsafeAtomicAdd(&gimg[gi].x, lf * dl);
+                    unsafeAtomicAdd(&gimg[gi].y, lf * da);
+                    unsafeAtomicAdd(&gimg[gi].z, lf * db);
+                    for (int i = 0; i <= n; ++i) {
+                        if (i > 0) {
+                            rem += inc;
+                            const bool st = rem >= two_n;
+                            rem -= st ? two_n : 0;
+                            gi += st ? sdiag : smaj;
+                        }
+                        const float4 fq = img[gi];
+                        const float el = fq.x - c.l, ea = fq.y - c.a, eb = fq.z - c.b;
+                        unsafeAtomicAdd(&gimg[gi].x, cf * el);
+                        unsafeAtomicAdd(&gimg[gi].y, cf * ea);
+                        unsafeAtomicAdd(&gimg[gi].z, cf * eb);
+                        unsafeAtomicAdd(&gimg[gi].w, cw_);
+                        gk[0] -= cf * el;
+                        gk[1] -= cf * ea;
+                        gk[2] -= cf * eb;
+                    }
                 }
-            } else {
-                const int stx = dx < 0 ? -1 : 1, sty = dy < 0 ? -W : W;
-                const int smaj = xmaj ? stx : sty;
-                const int sdiag = smaj + (xmaj ? sty : stx);
-                int gi = p;
-                unsafeAtomicAdd(&gimg[gi].x, lf * dl);
-                unsafeAtomicAdd(&gimg[gi].y, lf * da);
-                unsafeAtomicAdd(&gimg[gi].z, lf * db);
-                for (int i = 0; i <= n; ++i) {
-                    if (i > 0) {
-                        rem += inc;
-                        const bool st = rem >= two_n;
-                        rem -= st ? two_n : 0;
-                        gi += st ? sdiag : smaj;
-                    }
-                    const float4 fq = img[gi];
-                    const float el = fq.x - c.l, ea = fq.y - c.a, eb = fq.z - c.b;
-                    unsafeAtomicAdd(&gimg[gi].x, cf * el);
-                    unsafeAtomicAdd(&gimg[gi].y, cf * ea);
-                    unsafeAtomicAdd(&gimg[gi].z, cf * eb);
-                    unsafeAtomicAdd(&gimg[gi].w, cw_);
-                    gk[0] -= cf * el;
-                    gk[1] -= cf * ea;
-                    gk[2] -= cf * eb;
+            }
+            if (c.staged) {                                     // uniform
+                const float se = wave_sum(cf_end), sw_ = wave_sum(cw_end);
+                if (lane == 0) {
+                    if (se != 0.0f) atomicAdd(&alpha[lic], se);
+                    if (sw_ != 0.0f) atomicAdd(&accw[lic], sw_);
                 }
             }
         }
@@ -503,11 +569,9 @@ __global__ __launch_bounds__(WG) void k_soft_bwd_path(SoftImg s, const float4* _
                     const float4 fq = img[(long long)y * W + x];
                     const float el = al * (fq.x - c.l), ea = al * (fq.y - c.a),
                                 eb = al * (fq.z - c.b);
-                    float4 v = acc[li];
-                    v.x += el;
-                    v.y += ea;
-                    v.z += eb;
-                    acc[li] = v;
+                    accx[li] += el;
+                    accy[li] += ea;
+                    accz[li] += eb;
                     gk[0] -= el;
                     gk[1] -= ea;
                     gk[2] -= eb;
@@ -523,14 +587,14 @@ __global__ __launch_bounds__(WG) void k_soft_bwd_path(SoftImg s, const float4* _
     }
     // flush the workgroup's tiles
     for (int e = tid; e < area; e += WG) {
-        const float4 v = acc[e];
-        if (v.x != 0.0f || v.y != 0.0f || v.z != 0.0f || v.w != 0.0f) {
+        const float vx = accx[e], vy = accy[e], vz = accz[e], vw = accw[e];
+        if (vx != 0.0f || vy != 0.0f || vz != 0.0f || vw != 0.0f) {
             const int r = e / rw;
             float4* d = &gimg[(long long)(ry0 + r) * W + rx0 + (e - r * rw)];
-            unsafeAtomicAdd(&d->x, v.x);
-            unsafeAtomicAdd(&d->y, v.y);
-            unsafeAtomicAdd(&d->z, v.z);
-            unsafeAtomicAdd(&d->w, v.w);
+            unsafeAtomicAdd(&d->x, vx);
+            unsafeAtomicAdd(&d->y, vy);
+            unsafeAtomicAdd(&d->z, vz);
+            unsafeAtomicAdd(&d->w, vw);
         }
     }
     if (tid < 45) {
