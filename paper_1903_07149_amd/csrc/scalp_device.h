@@ -59,74 +59,20 @@ __device__ __forceinline__ void walk_path(const float4* __restrict__ base, int i
     }
 }
 
-// The same walk over the LDS halo.  The remainder is kept biased by -2n in
-// 32-bit unsigned arithmetic, so the minor-axis step is exactly the carry of
-// "remainder + 2|d_minor|" (one add with carry-out, two selects, two adds
-// per sample).  The loop is unrolled by two with the texel of the next
-// sample loaded before the current one is accumulated, so each LDS load has
-// a sample's worth of work to hide behind.
-__device__ __forceinline__ void walk_path_lds(const float4* lds, int idx, int rw, int dx, int dy,
-                                              float l, float a, float b, float& sc, float& sw) {
-    const int adx = dx < 0 ? -dx : dx;
-    const int ady = dy < 0 ? -dy : dy;
-    const bool xmaj = adx >= ady;
-    const int n = xmaj ? adx : ady;
-    if (n < 2) return;
-    const unsigned am = (unsigned)(xmaj ? ady : adx);
-    const int sx = dx < 0 ? -16 : 16;
-    const int sy = dy < 0 ? -16 * rw : 16 * rw;
-    const int smaj = xmaj ? sx : sy;
-    const int sdiag = smaj + (xmaj ? sy : sx);
-    const unsigned inc = 2u * am;
-    const unsigned bias = 0u - 2u * (unsigned)n;          // 2^32 - 2n
-    unsigned e = 0u - (unsigned)n;                        // remainder n, biased
-    const char* q = reinterpret_cast<const char*>(lds + idx);
-#define SCALP_STEP()                                              \
-    do {                                                          \
-        unsigned t_;                                              \
-        const bool c_ = __builtin_add_overflow(e, inc, &t_);      \
-        e = t_ + (c_ ? bias : 0u);                                \
-        q += c_ ? sdiag : smaj;                                   \
-    } while (0)
-#define SCALP_ACC(f)                                              \
-    do {                                                          \
-        const float dl_ = (f).x - l;                              \
-        const float da_ = (f).y - a;                              \
-        const float db_ = (f).z - b;                              \
-        const float dc_ = (dl_ * dl_ + da_ * da_) + db_ * db_;    \
-        sc = sc + dc_;                                            \
-        sw = sw + (f).w;                                          \
-    } while (0)
-    SCALP_STEP();
-    float4 fa = *reinterpret_cast<const float4*>(q);      // sample 1
-    int left = n - 2;                                      // samples 2 .. n-1 still to load
-    while (left >= 2) {
-        SCALP_STEP();
-        const float4 fb = *reinterpret_cast<const float4*>(q);
-        SCALP_ACC(fa);
-        SCALP_STEP();
-        fa = *reinterpret_cast<const float4*>(q);
-        SCALP_ACC(fb);
-        left -= 2;
-    }
-    if (left == 1) {
-        SCALP_STEP();
-        const float4 fb = *reinterpret_cast<const float4*>(q);
-        SCALP_ACC(fa);
-        SCALP_ACC(fb);
-    } else {
-        SCALP_ACC(fa);
-    }
-#undef SCALP_STEP
-#undef SCALP_ACC
-}
-
 // The walk over a per-candidate LDS table of (colour distance, w) pairs: the
 // colour distance of a texel to the candidate does not depend on the pixel
 // the path starts from, so it is computed once per texel (same FP32
-// operations, same order) and every path sample costs two adds.  Stepping is
-// walk_path_lds's: biased remainder, carry as the minor-axis step; the loop
-// takes four samples per trip with loads issued ahead of the adds.
+// operations, same order) and every path sample costs two adds.
+//
+// Stepping: the minor-axis offset after i major steps, floor(i s + 1/2) with
+// s = |d_minor| / n, is the number of carries out of a 32-bit accumulator
+// that starts at 2^31 and adds F = ceil(2^32 s) per step (2^32 - 1 when
+// s = 1).  The accumulated excess i (F - 2^32 s) < i stays below the gap
+// 2^32 / (2n) between i s + 1/2 and the next integer whenever 2 n^2 < 2^32,
+// i.e. n < 46340 (tables never exceed 2 x 9728 entries, so every path over a
+// table qualifies), and an exact tie is never undershot since F rounds up.
+// One add with carry-out, one select and one address add per sample; four
+// samples per loop trip with the loads issued ahead of the adds.
 __device__ __forceinline__ void walk_table(const float2* tab, int idx, int tw, int dx, int dy,
                                            float& sc, float& sw) {
     const int adx = dx < 0 ? -dx : dx;
@@ -134,20 +80,18 @@ __device__ __forceinline__ void walk_table(const float2* tab, int idx, int tw, i
     const bool xmaj = adx >= ady;
     const int n = xmaj ? adx : ady;
     if (n < 2) return;
-    const unsigned am = (unsigned)(xmaj ? ady : adx);
+    const int am = xmaj ? ady : adx;
+    const unsigned F = am == n ? 0xffffffffu
+                               : (unsigned)ceil((double)am * 4294967296.0 / (double)n);
     const int sx = dx < 0 ? -8 : 8;
     const int sy = dy < 0 ? -8 * tw : 8 * tw;
     const int smaj = xmaj ? sx : sy;
     const int sdiag = smaj + (xmaj ? sy : sx);
-    const unsigned inc = 2u * am;
-    const unsigned bias = 0u - 2u * (unsigned)n;
-    unsigned e = 0u - (unsigned)n;
+    unsigned acc = 0x80000000u;
     const char* q = reinterpret_cast<const char*>(tab + idx);
 #define SCALP_STEP()                                              \
     do {                                                          \
-        unsigned t_;                                              \
-        const bool c_ = __builtin_add_overflow(e, inc, &t_);      \
-        e = t_ + (c_ ? bias : 0u);                                \
+        const bool c_ = __builtin_add_overflow(acc, F, &acc);     \
         q += c_ ? sdiag : smaj;                                   \
     } while (0)
 #define SCALP_ACC(v)                                              \
@@ -158,7 +102,7 @@ __device__ __forceinline__ void walk_table(const float2* tab, int idx, int tw, i
     SCALP_STEP();
     float2 fa = *reinterpret_cast<const float2*>(q);
     int left = n - 2;
-    while (left >= 4) {                 // four samples per trip: less loop control
+    while (left >= 4) {
         SCALP_STEP();
         const float2 fb = *reinterpret_cast<const float2*>(q);
         SCALP_STEP();
