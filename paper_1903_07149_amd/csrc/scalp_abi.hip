@@ -81,6 +81,8 @@ Img img_of(const scalp_grid_t* g, const scalp_params_t* p, long long pix, int sp
     im.spw = (float)(((double)p->m * (double)p->m) / (r * r));          // Eq. (3)
     im.gamma = p->gamma < 0.0f ? (float)(2.0 * r) : p->gamma;           // Sec. III-A.3
     im.spl = slices_of(g, tuning_of(p).wg);
+    im.rad = (int)std::floor(r + 0.5);
+    im.pad = 0;
     return im;
 }
 

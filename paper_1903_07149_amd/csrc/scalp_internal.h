@@ -33,6 +33,8 @@ struct Img {
     float spw;        // m^2 / r^2 of Eq. (3)
     float gamma;      // gamma of Eq. (2)
     int spl;          // assignment work items per grid cell (at most WG pixels each)
+    int rad;          // R = r rounded to whole pixels (the window form's half-width)
+    int pad;
 };
 
 // An assignment work item has at most as many pixels as its workgroup has

@@ -592,22 +592,16 @@ __device__ __forceinline__ unsigned long long proj_key(int x, int y, int W, floa
     return ((unsigned long long)__float_as_uint(d) << 32) | (unsigned)(y * W + x);
 }
 
+// Nearest member of cluster k (key of proj_key) and the number of members
+// inside [X0, X1) x [Y0, Y1), reduced over the workgroup; four independent
+// label loads in flight per thread per round.
 template <int WG>
-__device__ void project_one(const Img& im, int k, const float* __restrict__ centres,
-                            const int* __restrict__ counts, const int* __restrict__ labels,
-                            int* __restrict__ endpoints) {
+__device__ void scan_region(const int* __restrict__ lb, int W, int k, int X0, int X1, int Y0,
+                            int Y1, float xk, float yk, unsigned long long& best, int& found) {
     const int tid = threadIdx.x;
-    const int W = im.W, H = im.H;
-    const int* lb = labels + im.pix;
-    const float xk = centres[5LL * (im.sp + k) + 3];
-    const float yk = centres[5LL * (im.sp + k) + 4];
-    const int ci = k / im.nx, cj = k - ci * im.nx;
-    const int X0 = cell_lo(max(cj - 1, 0), W, im.nx), X1 = cell_lo(min(cj + 2, im.nx), W, im.nx);
-    const int Y0 = cell_lo(max(ci - 1, 0), H, im.ny), Y1 = cell_lo(min(ci + 2, im.ny), H, im.ny);
     const int bw = X1 - X0, area = bw * (Y1 - Y0);
-    unsigned long long best = ~0ULL;
-    int found = 0;
-    // four independent label loads in flight per thread per round
+    best = ~0ULL;
+    found = 0;
     for (int e0 = tid; e0 < area; e0 += 4 * WG) {
         int lbl[4], xs[4], ys[4];
 #pragma unroll
@@ -628,20 +622,37 @@ __device__ void project_one(const Img& im, int k, const float* __restrict__ cent
         }
     }
     block_min_sum<WG>(best, found);
-    if (found < counts[im.sp + k]) {
-        // members outside the 3x3 cell block (labels not produced by the
-        // assignment): scan the whole image
-        best = ~0ULL;
-        found = 0;
-        for (long long p = tid; p < (long long)W * H; p += WG) {
-            if (lb[p] == k) {
-                const unsigned long long key = proj_key((int)(p % W), (int)(p / W), W, xk, yk);
-                best = key < best ? key : best;
-            }
-        }
-        block_min_sum<WG>(best, found);
+}
+
+// Eq. (4) for one queued cluster: the argmin over all its members, found by
+// scanning regions of growing size until every member (counts) was seen:
+// the 3x3 cell block around its grid cell (where the grid form's labels
+// lie), then the square of half-width 2R + 2 around its rounded barycenter
+// (the window form: members lie within R of the previous barycenter, which
+// lies within R of the new one), then the whole image (any labels).
+template <int WG>
+__device__ void project_one(const Img& im, int k, const float* __restrict__ centres,
+                            const int* __restrict__ counts, const int* __restrict__ labels,
+                            int* __restrict__ endpoints) {
+    const int W = im.W, H = im.H;
+    const int* lb = labels + im.pix;
+    const float xk = centres[5LL * (im.sp + k) + 3];
+    const float yk = centres[5LL * (im.sp + k) + 4];
+    const int ci = k / im.nx, cj = k - ci * im.nx;
+    const int count = counts[im.sp + k];
+    unsigned long long best;
+    int found;
+    scan_region<WG>(lb, W, k, cell_lo(max(cj - 1, 0), W, im.nx), cell_lo(min(cj + 2, im.nx), W, im.nx),
+                    cell_lo(max(ci - 1, 0), H, im.ny), cell_lo(min(ci + 2, im.ny), H, im.ny), xk, yk,
+                    best, found);
+    if (found < count) {                           // uniform: reduced over the workgroup
+        const int h = 2 * im.rad + 2;
+        const int cx = round_coord(xk, W - 1), cy = round_coord(yk, H - 1);
+        scan_region<WG>(lb, W, k, max(cx - h, 0), min(cx + h + 1, W), max(cy - h, 0),
+                        min(cy + h + 1, H), xk, yk, best, found);
+        if (found < count) scan_region<WG>(lb, W, k, 0, W, 0, H, xk, yk, best, found);
     }
-    if (tid == 0 && best != ~0ULL) {
+    if (threadIdx.x == 0 && best != ~0ULL) {
         const unsigned idx = (unsigned)(best & 0xffffffffULL);
         endpoints[2LL * (im.sp + k)] = (int)(idx % (unsigned)W);
         endpoints[2LL * (im.sp + k) + 1] = (int)(idx / (unsigned)W);
