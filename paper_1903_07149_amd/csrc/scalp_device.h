@@ -59,6 +59,21 @@ __device__ __forceinline__ void walk_path(const float4* __restrict__ base, int i
     }
 }
 
+// Increment of the carry-counting line stepper below for minor extent am and
+// major extent n (0 <= am <= n).  Any F with 0 <= F - 2^32 am/n < 2^32/(2 n^2)
+// steps exactly (see walk_table).  For n < 1023 a reciprocal good to one ulp
+// gives 2^32 am/n within 769, and adding 1025 lands in (256, 1794]: inside
+// the window for every n up to 1094.  Longer paths take the correctly
+// rounded double quotient, rounded up.
+__device__ __forceinline__ unsigned step_increment(int am, int n) {
+    if (am == n) return 0xffffffffu;
+    if (n < 1023) {
+        const float sf = (float)am * __builtin_amdgcn_rcpf((float)n);
+        return (unsigned)(sf * 4294967296.0f) + 1025u;
+    }
+    return (unsigned)ceil((double)am * 4294967296.0 / (double)n);
+}
+
 // The walk over a per-candidate LDS table of (colour distance, w) pairs: the
 // colour distance of a texel to the candidate does not depend on the pixel
 // the path starts from, so it is computed once per texel (same FP32
@@ -81,8 +96,7 @@ __device__ __forceinline__ void walk_table(const float2* tab, int idx, int tw, i
     const int n = xmaj ? adx : ady;
     if (n < 2) return;
     const int am = xmaj ? ady : adx;
-    const unsigned F = am == n ? 0xffffffffu
-                               : (unsigned)ceil((double)am * 4294967296.0 / (double)n);
+    const unsigned F = step_increment(am, n);
     const int sx = dx < 0 ? -8 : 8;
     const int sy = dy < 0 ? -8 * tw : 8 * tw;
     const int smaj = xmaj ? sx : sy;
@@ -127,6 +141,36 @@ __device__ __forceinline__ void walk_table(const float2* tab, int idx, int tw, i
     SCALP_ACC(fa);
 #undef SCALP_STEP
 #undef SCALP_ACC
+}
+
+// Correctly rounded FP64 reciprocals 1/1 .. 1/1024, built at compile time.
+struct RecipTable {
+    double v[1025];
+    constexpr RecipTable() : v() {
+        for (int i = 1; i <= 1024; ++i) v[i] = 1.0 / (double)i;
+    }
+};
+namespace {
+__constant__ const RecipTable kRecip = RecipTable();
+}
+
+// a / np and b / np in IEEE FP32 (np = n + 1) for the two averages of
+// Eqs. (1)-(2).  For np <= 1024 and a, b zero or at least 2^-100, the FP32
+// rounding of the FP64 product a * RN(1/np) is the IEEE quotient: a float
+// divided by an integer np is never a rounding midpoint of FP32 and stays at
+// least 2^-35 (relative) away from one for np <= 1024, while the product's
+// error is below 2^-52.  Other operands take the IEEE division itself.
+__device__ __forceinline__ void div_path_len(float a, float b, int n, float& qa, float& qb) {
+    const bool fast = n < 1024 && !(a > 0.0f && a < 0x1p-100f) && !(b > 0.0f && b < 0x1p-100f);
+    if (fast) {
+        const double inv = kRecip.v[n + 1];
+        qa = (float)((double)a * inv);
+        qb = (float)((double)b * inv);
+    } else {
+        const float np = (float)(n + 1);
+        qa = a / np;
+        qb = b / np;
+    }
 }
 
 __device__ __forceinline__ int round_coord(float v, int hi) {

@@ -197,9 +197,10 @@ __device__ __forceinline__ void process_cell(const Img& im, int cell, int slice,
                 sc = sc + dcc;
                 sw = sw + wc;
             }
-            const float np = (float)(n + 1);
-            const float A = lambda * dcp + oml * (sc / np);      // Eq. (1)
-            const float B = 1.0f + gamma * (sw / np);            // Eq. (2)
+            float qc, qw;                          // sc / |P|, sw / |P|
+            div_path_len(sc, sw, n, qc, qw);
+            const float A = lambda * dcp + oml * qc;             // Eq. (1)
+            const float B = 1.0f + gamma * qw;                   // Eq. (2)
             const float ex = (float)x - ccx;
             const float ey = (float)y - ccy;
             const float ds = ex * ex + ey * ey;
@@ -354,9 +355,10 @@ __global__ __launch_bounds__(WG) void k_assign_window(Img im, const float4* __re
             sc = sc + dcc;
             sw = sw + wc;
         }
-        const float np = (float)(n + 1);
-        const float A = lambda * dcp + oml * (sc / np);
-        const float B = 1.0f + im.gamma * (sw / np);
+        float qc, qw;
+        div_path_len(sc, sw, n, qc, qw);
+        const float A = lambda * dcp + oml * qc;
+        const float B = 1.0f + im.gamma * qw;
         const float ex = (float)x - xk, ey = (float)y - yk;
         const float D = A * B + (ex * ex + ey * ey) * im.spw;
         const unsigned long long key = ((unsigned long long)__float_as_uint(D) << 32) | (unsigned)k;

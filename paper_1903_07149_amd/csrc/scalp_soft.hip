@@ -240,9 +240,10 @@ __global__ __launch_bounds__(WG) void k_soft_assign(SoftImg s, const float4* __r
                 sc = sc + dcc;
                 sw = sw + wc;
             }
-            const float np = (float)(n + 1);
-            const float A = lambda * dcp + oml * (sc / np);
-            const float Bw = 1.0f + s.gamma * (sw / np);
+            float qc, qw;
+            div_path_len(sc, sw, n, qc, qw);
+            const float A = lambda * dcp + oml * qc;
+            const float Bw = 1.0f + s.gamma * qw;
             const float ex = (float)x - ccx, ey = (float)y - ccy;
             const float D = A * Bw + (ex * ex + ey * ey) * s.spw;
             // D goes to the Q buffer (k_soft_softmax turns it into Q); A and B
