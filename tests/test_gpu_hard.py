@@ -87,6 +87,38 @@ def test_assign_bit_exact(orc, W, H, k, tune):
     assert (lbl == ol).all(), f"{int((lbl != ol).sum())} labels differ"
 
 
+@pytest.mark.parametrize("W,H,k,tune", [(2100, 1000, 1, {}), (3000, 3, 2, {"lds_pixels": 9728}),
+                                         (2, 2600, 1, {})])
+def test_assign_long_paths(orc, W, H, k, tune):
+    """One 2100x1000 cell: paths of up to ~1050 samples, walked from global
+    memory, whose averages over more than 1024 samples take the IEEE
+    divisions; thin images: many short cells, tables of extreme aspect."""
+    img = _image(W, H, 8, regions=6)
+    g = orc.grid(W, H, k)
+    c, e = perturbed_state(orc, g, img.lab, seed=W + H, jitter=2.0)
+    s = _scalp(W, H, k, **tune)
+    say("assign long paths", W, H, k, tune)
+    lbl = host(s.assign(dev(img.lab), dev(img.contour), dev(c), dev(e)))
+    ol, _, _ = orc.assign(g, img.lab, orc.wmap(img.contour), c, e)
+    assert (lbl == ol).all(), f"{int((lbl != ol).sum())} labels differ"
+
+
+@pytest.mark.parametrize("scale", [1e-21, 1e-17])
+def test_assign_tiny_colour_sums(orc, scale):
+    """Lab values so small that the path colour sums fall below 2^-100 (down
+    to the subnormal range): those averages take the IEEE division."""
+    W, H, k = 97, 61, 30
+    img = _image(W, H, 9)
+    lab = (img.lab * np.float32(scale)).astype(np.float32)
+    g = orc.grid(W, H, k)
+    c, e = perturbed_state(orc, g, lab, seed=3, jitter=3.0, colour=10.0 * scale)
+    s = _scalp(W, H, k)
+    say("assign tiny", scale)
+    lbl = host(s.assign(dev(lab), dev(img.contour), dev(c), dev(e)))
+    ol, _, _ = orc.assign(g, lab, orc.wmap(img.contour), c, e)
+    assert (lbl == ol).all(), f"{int((lbl != ol).sum())} labels differ"
+
+
 @pytest.mark.parametrize("lam,gamma", [(1.0, 0.0), (0.0, 0.0), (0.3, 7.0)])
 def test_assign_parameters(orc, lam, gamma):
     W, H, k = 200, 150, 60
