@@ -73,8 +73,8 @@ typedef struct {
                                 the same lab/contour/sigma; skip re-packing  */
     int32_t lds_pixels;      /* tuning: LDS budget of the assignment in 16-byte
                                 units (per-candidate tables of 8-byte entries,
-                                two of this many; the window form's halo of
-                                16-byte texels), 0..9728; 0 selects the
+                                two of this many; one table of twice as many
+                                for the window form), 0..9728; 0 selects the
                                 default (4800)                               */
     int32_t wg_size;         /* tuning: assignment workgroup size, 0 (default
                                 1024), 256, 512 or 1024                      */
@@ -239,22 +239,29 @@ int scalp_batched_graph_create(const scalp_batch_desc_t* descs, int32_t n_images
  * B images of the same size.  Q_pj = softmax_j(-D_pj / T) over the 3x3
  * candidate slots j = (di+1)*3 + (dj+1) (slots outside the grid get 0), D of
  * Eqs. (1)-(3) with paths to floor(X_k + 0.5) (no projection); soft update
- * f_k = sum Q f_p / sum Q, X_k = sum Q X_p / sum Q (sum Q = 0: keep);
- * Theta_0 = cell means.  FP32 throughout.
+ * f_k = sum Q f_p / sum Q, X_k = sum Q X_p / sum Q (a superpixel whose
+ * sum Q is below 1e-6 keeps its centre); Theta_0 = cell means.  D is
+ * evaluated in FP32 exactly as in the hard path; the softmax and the update
+ * sums run in FP64; Q and Theta are stored as FP32.  Slot-major layouts:
  *   centers_t : float32 [iters+1][B][K'][5]   (output; Theta_0 .. Theta_T)
- *   q_t       : float32 [iters][B][H][W][9]   (output)
+ *   q_t       : float32 [iters][B][9][H][W]   (output)
  *   saved     : scalp_soft_saved_bytes() bytes (output of forward, input of
- *               backward): per-iteration distance factors and sum Q.
+ *               backward): per-iteration factors A, B of Eqs. (1)-(2) and
+ *               the FP64 masses sum Q.
+ * lab: float32 [B][H][W][3]; contour: float32 [B][H][W].  The soft entry
+ * points support only SCALP_ASSIGN_GRID3X3 and SCALP_CONTOUR_INPUT.
  */
 size_t scalp_soft_saved_bytes(const scalp_grid_t* g, int32_t batch, int32_t iterations);
 size_t scalp_soft_workspace_bytes(const scalp_grid_t* g, int32_t batch);
 int scalp_soft_forward(const scalp_grid_t* g, const scalp_params_t* p, float temperature,
                        int32_t batch, const float* lab, const float* contour, float* centers_t,
                        float* q_t, void* saved, void* workspace, size_t workspace_bytes, void* stream);
-/* Gradient of L given dL/dQ_T (grad_q: [B][H][W][9]) and dL/dTheta_T
+/* Gradient of L given dL/dQ_T (grad_q: [B][9][H][W]) and dL/dTheta_T
  * (grad_centers: [B][K'][5]) with respect to lab (grad_lab: [B][H][W][3],
  * output) and contour (grad_contour: [B][H][W], output).  Path samples are
- * recomputed, not stored.  FP32 with float atomics: not bit-reproducible. */
+ * recomputed, not stored; slots whose Q is below 2^-24 contribute no path
+ * terms (each is proportional to Q).  FP32 with float atomics: not
+ * bit-reproducible. */
 int scalp_soft_backward(const scalp_grid_t* g, const scalp_params_t* p, float temperature,
                         int32_t batch, const float* lab, const float* contour,
                         const float* centers_t, const float* q_t, const void* saved,

@@ -1,9 +1,10 @@
 """Autotuner for the assignment kernel's launch shape.
 
 Two knobs change speed but never results (every configuration is checked
-bit-exact against the oracle by the GPU tests): the workgroup size (waves
-sharing one grid cell's LDS halo) and the LDS halo budget in texels (which
-bounds how many candidate endpoints a cell can stage, and how many
+bit-exact against the oracle by the GPU tests): the workgroup size (lanes
+of one work item, one pixel each, sharing its LDS tables) and the LDS budget
+in 16-byte units (the size of the two per-candidate tables, which bounds
+which candidates walk over LDS rather than global memory, and how many
 workgroups fit on a CU).  The tuner times one fused assignment pass
 (`scalp_assign_accumulate`) per configuration with HIP events on the
 workload's own image and superpixel state, and caches the winner in a JSON

@@ -26,9 +26,11 @@ __device__ __forceinline__ long long to_fixed(float v) {
 
 // Accumulates the samples i = 1 .. n-1 of the path from the pixel at linear
 // index `idx` toward (dx, dy): on major-axis step i the minor offset is
-// floor((2 i |d_minor| + n) / (2 n)), kept incrementally as a remainder.
-// stepx / stepy are the index strides of one pixel in x / y.  (Global-memory
-// variant, used when a candidate's endpoint lies outside the LDS halo.)
+// floor((2 i |d_minor| + n) / (2 n)), kept incrementally as a remainder
+// (exact for any n).  stepx / stepy are the index strides of one pixel in
+// x / y.  Global-memory variant, used when a candidate's path rectangle
+// exceeds the LDS tables: up to three texel loads in flight, accumulated in
+// path order.
 __device__ __forceinline__ void walk_path(const float4* __restrict__ base, int idx, int stepx,
                                           int stepy, int dx, int dy, float l, float a, float b,
                                           float& sc, float& sw) {
@@ -36,6 +38,7 @@ __device__ __forceinline__ void walk_path(const float4* __restrict__ base, int i
     const int ady = dy < 0 ? -dy : dy;
     const bool xmaj = adx >= ady;
     const int n = xmaj ? adx : ady;
+    if (n < 2) return;
     const int am = xmaj ? ady : adx;
     const int sx = dx < 0 ? -stepx : stepx;
     const int sy = dy < 0 ? -stepy : stepy;
@@ -44,19 +47,44 @@ __device__ __forceinline__ void walk_path(const float4* __restrict__ base, int i
     const int two_n = 2 * n;
     const int inc = 2 * am;
     int rem = n;
-    for (int i = 1; i < n; ++i) {
-        rem += inc;
-        const bool step = rem >= two_n;
-        rem -= step ? two_n : 0;
-        idx += step ? sdiag : smaj;
-        const float4 f = base[idx];
-        const float dl = f.x - l;
-        const float da = f.y - a;
-        const float db = f.z - b;
-        const float dc = (dl * dl + da * da) + db * db;
-        sc = sc + dc;
-        sw = sw + f.w;
+#define SCALP_GSTEP()                                             \
+    do {                                                          \
+        rem += inc;                                               \
+        const bool st_ = rem >= two_n;                            \
+        rem -= st_ ? two_n : 0;                                   \
+        idx += st_ ? sdiag : smaj;                                \
+    } while (0)
+#define SCALP_GACC(f)                                             \
+    do {                                                          \
+        const float dl_ = (f).x - l;                              \
+        const float da_ = (f).y - a;                              \
+        const float db_ = (f).z - b;                              \
+        const float dc_ = (dl_ * dl_ + da_ * da_) + db_ * db_;    \
+        sc = sc + dc_;                                            \
+        sw = sw + (f).w;                                          \
+    } while (0)
+    SCALP_GSTEP();
+    float4 fa = base[idx];
+    int left = n - 2;
+    while (left >= 2) {
+        SCALP_GSTEP();
+        const float4 fb = base[idx];
+        SCALP_GSTEP();
+        const float4 fc = base[idx];
+        SCALP_GACC(fa);
+        SCALP_GACC(fb);
+        fa = fc;
+        left -= 2;
     }
+    if (left == 1) {
+        SCALP_GSTEP();
+        const float4 fb = base[idx];
+        SCALP_GACC(fa);
+        fa = fb;
+    }
+    SCALP_GACC(fa);
+#undef SCALP_GSTEP
+#undef SCALP_GACC
 }
 
 // Increment of the carry-counting line stepper below for minor extent am and
@@ -181,7 +209,7 @@ __device__ __forceinline__ int round_coord(float v, int hi) {
 
 // Workgroup index -> work item.  Workgroups are dispatched round-robin over
 // the 8 XCDs; give each XCD a contiguous run of items so that neighbouring
-// cells, which stage overlapping halos, share an L2.
+// cells, which read overlapping table rectangles, share an L2.
 __device__ __forceinline__ int xcd_remap(int b, int G) {
     const int q = G >> 3, rem = G & 7;
     const int x = b & 7, slot = b >> 3;

@@ -43,8 +43,8 @@ struct Img {
 constexpr int kMinAssignWG = 256;
 
 struct Tuning {
-    int wg;           // workgroup size of the assignment kernel (256 or 512)
-    int lds_pixels;   // LDS halo budget in pixels
+    int wg;           // workgroup size of the assignment kernel (256, 512 or 1024)
+    int lds_pixels;   // LDS table budget in 16-byte units
 };
 
 int default_lds_pixels();

@@ -91,3 +91,53 @@ def test_batch_descriptors_must_be_concatenated():
     d[1].pix_offset = 1201
     assert lib.scalp_batch_workspace_bytes(d, 2) == 0
     assert lib.scalp_batch_workspace_bytes(d, 0) == 0
+
+
+def test_mode_parameters_are_validated_on_host():
+    lib = L.lib()
+    g = L.make_grid(64, 48, 12)
+    fake = ctypes.c_void_p(0x1000)          # never dereferenced: validation fails first
+    ws = L.workspace_bytes(g)
+    args = lambda pr: (ctypes.byref(g), ctypes.byref(pr), fake, fake, fake, fake, fake, fake, ws,
+                       None)
+    for field, val in [("assign_mode", 2), ("assign_mode", -1), ("contour_source", 2),
+                       ("contour_source", -1)]:
+        pp = L.default_params(**{field: val})
+        assert lib.scalp_assign(*args(pp)) == L.SCALP_ERR_ARG, (field, val)
+    # a computed contour prior makes the contour pointer optional, a given one does not
+    p = L.default_params()
+    assert lib.scalp_prepare(ctypes.byref(g), ctypes.byref(p), fake, None, fake, ws,
+                             None) == L.SCALP_ERR_ARG
+    # the soft entry points support neither the window form nor a computed prior
+    sw = lib.scalp_soft_workspace_bytes(ctypes.byref(g), 1)
+    for over, code in [(dict(assign_mode=L.ASSIGN_WINDOW), L.SCALP_ERR_ARG),
+                       (dict(contour_source=L.CONTOUR_GRADIENT), L.SCALP_ERR_UNSUPPORTED)]:
+        pp = L.default_params(**over)
+        assert lib.scalp_soft_forward(ctypes.byref(g), ctypes.byref(pp), ctypes.c_float(0.5), 1,
+                                      fake, fake, fake, fake, fake, fake, sw, None) == code, over
+    with pytest.raises(TypeError):
+        L.default_params(not_a_parameter=1)
+
+
+def test_metrics_and_maps_validate_on_host():
+    lib = L.lib()
+    fake = ctypes.c_void_p(0x1000)
+    out = ctypes.c_void_p(0x2000)
+    assert lib.scalp_metrics_workspace_bytes(10, 10, 4, 3) > 0
+    assert lib.scalp_metrics_workspace_bytes(0, 10, 4, 3) == 0
+    assert lib.scalp_metrics_workspace_bytes(10, 10, 0, 3) == 0
+    ws = lib.scalp_metrics_workspace_bytes(10, 10, 4, 3)
+    f = ctypes.c_float
+    assert lib.scalp_metrics(10, 10, fake, 4, fake, 3, f(2.0), out, fake, ws - 1,
+                             None) == L.SCALP_ERR_WORKSPACE
+    for eps in (0.0, -1.0, float("nan"), 100.0):
+        assert lib.scalp_metrics(10, 10, fake, 4, fake, 3, f(eps), out, fake, ws,
+                                 None) == L.SCALP_ERR_ARG, eps
+    assert lib.scalp_metrics(10, 10, None, 4, fake, 3, f(2.0), out, fake, ws,
+                             None) == L.SCALP_ERR_ARG
+    assert lib.scalp_boundary_map(0, 5, fake, 2, out, None) == L.SCALP_ERR_ARG
+    assert lib.scalp_boundary_map(5, 5, fake, 0, out, None) == L.SCALP_ERR_ARG
+    assert lib.scalp_boundary_map(5, 5, None, 2, out, None) == L.SCALP_ERR_ARG
+    assert lib.scalp_contour_from_lab(5, 5, fake, out, fake, 4, None) == L.SCALP_ERR_WORKSPACE
+    assert lib.scalp_contour_from_lab(5, 0, fake, out, fake, 8, None) == L.SCALP_ERR_ARG
+    assert lib.scalp_contour_from_lab(5, 5, None, out, fake, 8, None) == L.SCALP_ERR_ARG

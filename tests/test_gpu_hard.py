@@ -31,7 +31,7 @@ def _image(W, H, seed, regions=None):
 
 
 # (W, H, k): several tiles and ragged cells, thin and degenerate shapes,
-# one superpixel per pixel, and cells too large for the LDS halo.
+# one superpixel per pixel, and cells too large for the LDS tables.
 SMALL = [(97, 61, 30), (256, 200, 100), (481, 321, 250), (37, 5, 7), (1, 1, 1), (1, 50, 5),
          (50, 1, 5), (64, 64, 4096), (300, 200, 2), (129, 77, 1)]
 # tuning variants: default (1024 threads, 4800-unit LDS tables); tables too small for

@@ -132,7 +132,7 @@ def test_autograd_function_and_lds_fallback(orc):
     glab_o, gcon_o = orc.soft_backward(lab, con, k, gq.transpose(0, 2, 3, 1), gth,
                                        iterations=iters, T=T, d32=True)
     results = []
-    for lds in (0, 1, 300):                       # default; no LDS halo; partial halo
+    for lds in (0, 1, 300):                       # default; no LDS tables; partial
         eng = _engine(W, H, k, B, T, iters, lds_pixels=lds)
         L = dev(lab).requires_grad_(True)
         C = dev(con).requires_grad_(True)
