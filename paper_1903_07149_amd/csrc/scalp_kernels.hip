@@ -465,18 +465,28 @@ struct LabSource {
     }
 };
 
+// Integer sums of the update for labels that need not be grid neighbours
+// (window form, caller-supplied labels).  One workgroup per grid cell
+// accumulates into a small LDS table keyed by label (open addressing, key
+// claimed with a compare-and-swap); a label that finds no free slot goes
+// straight to the global sums.  The sums are integers, so the result does
+// not depend on the order of the atomics.
+constexpr int kAccSlots = 32;
+
 template <int WG>
 __global__ __launch_bounds__(WG) void k_accumulate(Img im, LabSource src,
                                                    const int* __restrict__ labels,
                                                    long long* __restrict__ acc) {
-    __shared__ unsigned long long bins[9][6];
+    __shared__ int keys[kAccSlots];
+    __shared__ unsigned long long bins[kAccSlots][6];
     const int tid = threadIdx.x;
     const int cell = blockIdx.x;
     const int ci = cell / im.nx, cj = cell - ci * im.nx;
     const int x0 = cell_lo(cj, im.W, im.nx), x1 = cell_lo(cj + 1, im.W, im.nx);
     const int y0 = cell_lo(ci, im.H, im.ny), y1 = cell_lo(ci + 1, im.H, im.ny);
     const int K = im.nx * im.ny;
-    for (int t = tid; t < 54; t += WG) (&bins[0][0])[t] = 0ULL;
+    for (int t = tid; t < kAccSlots * 6; t += WG) (&bins[0][0])[t] = 0ULL;
+    for (int t = tid; t < kAccSlots; t += WG) keys[t] = -1;
     __syncthreads();
     const int cw = x1 - x0, P = cw * (y1 - y0);
     for (int t = tid; t < P; t += WG) {
@@ -486,27 +496,34 @@ __global__ __launch_bounds__(WG) void k_accumulate(Img im, LabSource src,
         const int k = labels[p];
         if (k < 0 || k >= K) continue;
         const float3 f = src(p);
-        unsigned long long v[6] = {1ULL, (unsigned long long)x, (unsigned long long)y,
-                                   (unsigned long long)to_fixed(f.x),
-                                   (unsigned long long)to_fixed(f.y),
-                                   (unsigned long long)to_fixed(f.z)};
-        const int ki = k / im.nx, kj = k - ki * im.nx;
-        const int di = ki - ci + 1, dj = kj - cj + 1;
-        if (di >= 0 && di < 3 && dj >= 0 && dj < 3) {
-            unsigned long long* bin = bins[di * 3 + dj];
-            for (int q = 0; q < 6; ++q) atomicAdd(bin + q, v[q]);
+        const unsigned long long v[6] = {1ULL, (unsigned long long)x, (unsigned long long)y,
+                                         (unsigned long long)to_fixed(f.x),
+                                         (unsigned long long)to_fixed(f.y),
+                                         (unsigned long long)to_fixed(f.z)};
+        int slot = -1;
+        for (int probe = 0, h = k & (kAccSlots - 1); probe < kAccSlots;
+             ++probe, h = (h + 1) & (kAccSlots - 1)) {
+            const int cur = keys[h];
+            if (cur == k) { slot = h; break; }
+            if (cur == -1) {
+                const int old = atomicCAS(&keys[h], -1, k);
+                if (old == -1 || old == k) { slot = h; break; }
+            }
+        }
+        if (slot >= 0) {
+            for (int q = 0; q < 6; ++q) atomicAdd(&bins[slot][q], v[q]);
         } else {
             for (int q = 0; q < 6; ++q)
-                atomicAdd((unsigned long long*)(acc + kAccStride * (long long)k + q), v[q]);
+                atomicAdd((unsigned long long*)(acc + kAccStride * (long long)(im.sp + k) + q), v[q]);
         }
     }
     __syncthreads();
-    if (tid < 54) {
-        const int j = tid / 6, q = tid - 6 * (tid / 6);
-        const int ii = ci + j / 3 - 1, jj = cj + j % 3 - 1;
-        if (ii >= 0 && ii < im.ny && jj >= 0 && jj < im.nx && bins[j][0] != 0ULL)
-            atomicAdd((unsigned long long*)(acc + kAccStride * (long long)(ii * im.nx + jj) + q),
-                      bins[j][q]);
+    for (int t = tid; t < kAccSlots * 6; t += WG) {
+        const int slot = t / 6, q = t - 6 * (t / 6);
+        const int k = keys[slot];
+        if (k >= 0 && bins[slot][0] != 0ULL)
+            atomicAdd((unsigned long long*)(acc + kAccStride * (long long)(im.sp + k) + q),
+                      bins[slot][q]);
     }
 }
 
