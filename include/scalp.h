@@ -248,8 +248,9 @@ int scalp_batched_graph_create(const scalp_batch_desc_t* descs, int32_t n_images
  *   saved     : scalp_soft_saved_bytes() bytes (output of forward, input of
  *               backward): per-iteration factors A, B of Eqs. (1)-(2) and
  *               the FP64 masses sum Q.
- * lab: float32 [B][H][W][3]; contour: float32 [B][H][W].  The soft entry
- * points support only SCALP_ASSIGN_GRID3X3 and SCALP_CONTOUR_INPUT.
+ * lab: float32 [B][H][W][3]; contour: float32 [B][H][W]; 1 <= B <= 65535.
+ * The soft entry points support only SCALP_ASSIGN_GRID3X3 and
+ * SCALP_CONTOUR_INPUT.
  */
 size_t scalp_soft_saved_bytes(const scalp_grid_t* g, int32_t batch, int32_t iterations);
 size_t scalp_soft_workspace_bytes(const scalp_grid_t* g, int32_t batch);

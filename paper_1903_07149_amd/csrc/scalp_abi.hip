@@ -593,7 +593,7 @@ bool soft_args_ok(const scalp_grid_t* g, const scalp_params_t* p, float temperat
     if (!grid_valid(g) || !params_valid(p)) return false;
     if (p->assign_mode != SCALP_ASSIGN_GRID3X3) return false;   // soft slots are the 3x3 cells
     if (!(temperature > 0.0f) || !std::isfinite(temperature)) return false;
-    if (batch < 1 || p->iterations < 1) return false;
+    if (batch < 1 || batch > 65535 || p->iterations < 1) return false;
     const long long N = (long long)g->width * g->height;
     return (long long)batch * N < (1LL << 40);
 }
@@ -687,7 +687,7 @@ int scalp_soft_backward(const scalp_grid_t* g, const scalp_params_t* p, float te
     const float* fa = reinterpret_cast<const float*>(sb + S.a);
     const float* fb = reinterpret_cast<const float*>(sb + S.bf);
     const double* z = reinterpret_cast<const double*>(sb + S.z);
-    const int cap = soft_cap_bytes(p) / 20;
+    const int cap = soft_cap_bytes(p) / 16;   // four gradient floats per texel
     if (!p->reuse_prepared) CHECK_HIP(launch_prepare(B * N, lab, contour, p->sigma, packed, s));
     CHECK_HIP(launch_clear(reinterpret_cast<long long*>(gf), B * N * 2, s));
     CHECK_HIP(launch_copy_f32(grad_centers, gth[0], B * K * 5, s));

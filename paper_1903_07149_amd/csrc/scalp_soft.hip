@@ -19,15 +19,12 @@
 // Backward, per iteration in reverse:
 //   k_soft_bwd_update  thread per pixel: soft-update and softmax backward,
 //                      giving dL/dD for the 9 slots.
-//   k_soft_bwd_path    workgroup per (image, cell), one pass per candidate
-//                      slot: every lane re-walks its path (samples are
-//                      recomputed, never stored) and scatters
-//                      alpha_q += dL/dD * B (1-lambda) 2/|P|  and
-//                      dL/dw_q += dL/dD * A gamma/|P|  into LDS tiles; a
-//                      fold then turns alpha into dL/df_q = alpha_q (f_q - f_k)
-//                      and into the candidate's centre gradient.  The tiles
-//                      leave the workgroup as float atomics (not
-//                      bit-reproducible).
+//   k_soft_bwd_path    workgroup per (image, cell), one pass: every lane
+//                      re-walks the paths of its pixel's slots with a nonzero
+//                      dL/dD (samples are recomputed, never stored) and
+//                      scatters dL/df_q and dL/dw_q into LDS tiles and the
+//                      candidate's centre gradient into LDS bins; both leave
+//                      the workgroup as float atomics (not bit-reproducible).
 #include <algorithm>
 
 #include "scalp_device.h"
@@ -256,18 +253,22 @@ __global__ __launch_bounds__(WG) void k_soft_assign(SoftImg s, const float4* __r
     }
 }
 
+// Per-pixel soft kernels run a 3D grid: image in z, rows strided over y,
+// 256-column segments in x (no per-pixel division to recover coordinates).
+#define SOFT_FOR_PIXELS(s)                                                   \
+    const int b = blockIdx.z;                                                \
+    const int x = blockIdx.x * 256 + threadIdx.x;                            \
+    for (int y = blockIdx.y; y < (s).H; y += gridDim.y)                      \
+        if (x < (s).W)
+
 // Q_pj = softmax_j(-D_pj / T) in FP64 over the slots inside the grid, rounded
 // once to FP32 (the FP32 distances differ by far more than FP32's exponent
 // range allows at small T).  In place over the D values.  A separate kernel
 // so that the FP64 exponentials do not raise the register count of the path
 // walk.
-__global__ void k_soft_softmax(SoftImg s, float* __restrict__ q) {
-    const long long total = (long long)s.B * s.N;
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
-         i += (long long)gridDim.x * blockDim.x) {
-        const int b = (int)(i / s.N);
-        const long long p = i - (long long)b * s.N;
-        const int y = (int)(p / s.W), x = (int)(p - (long long)y * s.W);
+__global__ __launch_bounds__(256) void k_soft_softmax(SoftImg s, float* __restrict__ q) {
+    SOFT_FOR_PIXELS(s) {
+        const long long p = (long long)y * s.W + x;
         const int ci = (int)(((long long)y * s.ny) / s.H), cj = (int)(((long long)x * s.nx) / s.W);
         const long long base = 9LL * s.N * b + p;
         float D[9];
@@ -350,17 +351,18 @@ __global__ __launch_bounds__(WG) void k_soft_update(SoftImg s, const float* __re
 
 // Soft-update backward (theta_t = sum Q feat / Z) and softmax backward:
 // gd[j] = dL/dD_pj (0 where Q_pj < kQMin).  gf += dL/df_p through the update.
-__global__ void k_soft_bwd_update(SoftImg s, int first, const float* __restrict__ q,
-                                  const double* __restrict__ z, const float* __restrict__ theta,
-                                  const float4* __restrict__ packed,
-                                  const float* __restrict__ gth, const float* __restrict__ gq_in,
-                                  float* __restrict__ gd, float4* __restrict__ gf) {
-    const long long total = (long long)s.B * s.N;
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
-         i += (long long)gridDim.x * blockDim.x) {
-        const int b = (int)(i / s.N);
-        const long long p = i - (long long)b * s.N;
-        const int y = (int)(p / s.W), x = (int)(p - (long long)y * s.W);
+__global__ __launch_bounds__(256) void k_soft_bwd_update(SoftImg s, int first,
+                                                         const float* __restrict__ q,
+                                                         const double* __restrict__ z,
+                                                         const float* __restrict__ theta,
+                                                         const float4* __restrict__ packed,
+                                                         const float* __restrict__ gth,
+                                                         const float* __restrict__ gq_in,
+                                                         float* __restrict__ gd,
+                                                         float4* __restrict__ gf) {
+    SOFT_FOR_PIXELS(s) {
+        const long long p = (long long)y * s.W + x;
+        const long long i = (long long)b * s.N + p;
         const int ci = (int)(((long long)y * s.ny) / s.H), cj = (int)(((long long)x * s.nx) / s.W);
         const float4 f = packed[i];
         const float feat[5] = {f.x, f.y, f.z, (float)x, (float)y};
@@ -413,6 +415,18 @@ __global__ void k_soft_bwd_pass(SoftImg s, const double* __restrict__ z,
         gth_prev[i] = z[i / 5] >= kZMin ? 0.0f : gth[i];
 }
 
+// One workgroup per (image, cell), one pass: each lane loads its pixel's nine
+// dL/dD values and re-walks the path of every slot whose value is not zero
+// (at low T about one per pixel), scattering per sample
+//   dL/df_q += cf (f_q - f_k)   with cf = dL/dD * B (1 - lambda) 2 / |P|
+//   dL/dw_q += dL/dD * A gamma / |P|
+// into LDS tiles over the rectangle of the cell and its candidates'
+// endpoints (texel colours come through the cache); the candidate's centre gradient
+// takes the opposite colour terms and the spatial and lambda terms.  The
+// endpoint sample, shared by every path to a slot, is reduced over the wave
+// and added once.  Tiles leave the workgroup as float atomics (not
+// bit-reproducible).  Candidates whose endpoint lies outside the rectangle
+// scatter straight to global memory.
 template <int WG>
 __global__ __launch_bounds__(WG) void k_soft_bwd_path(SoftImg s, const float4* __restrict__ packed,
                                                       const float* __restrict__ theta_prev,
@@ -423,12 +437,11 @@ __global__ __launch_bounds__(WG) void k_soft_bwd_path(SoftImg s, const float4* _
                                                       float* __restrict__ gth_prev, int cap) {
     extern __shared__ float4 lds_dyn[];
     __shared__ SoftShared sh;
-    // five planar float tiles of cap texels: dL/dl, dL/da, dL/db, dL/dw, alpha
+    // four planar float tiles of cap texels: dL/dl, dL/da, dL/db, dL/dw
     float* accx = reinterpret_cast<float*>(lds_dyn);
     float* accy = accx + cap;
     float* accz = accy + cap;
     float* accw = accz + cap;
-    float* alpha = accw + cap;
     const int item = xcd_remap(blockIdx.x, gridDim.x);
     const int b = item / s.K, cell = item - b * s.K;
     const int tid = threadIdx.x;
@@ -450,51 +463,53 @@ __global__ __launch_bounds__(WG) void k_soft_bwd_path(SoftImg s, const float4* _
         accy[e] = 0.0f;
         accz[e] = 0.0f;
         accw[e] = 0.0f;
-        alpha[e] = 0.0f;
     }
     __syncthreads();
     const int cw = x1 - x0, ch = y1 - y0, P = cw * ch;
     const int lane = tid & 63, wave = tid >> 6;
     const float lambda = s.lambda, oml = 1.0f - lambda;
     const long long base = 9LL * s.N * b;
-    for (int j = 0; j < 9; ++j) {
-        const SoftCand c = sh.cand[j];
-        if (c.k < 0) continue;                                  // uniform
-        float gk[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-        // every path to this slot ends on its endpoint: that sample is
-        // reduced over the wave and added once (staged case)
-        const int lic = (c.cy - ry0) * rw + (c.cx - rx0);
-        for (int chunk = wave; chunk * 64 < P; chunk += WG / 64) {
-            const int t = chunk * 64 + lane;
+    for (int chunk = wave; chunk * 64 < P; chunk += WG / 64) {
+        const int t = chunk * 64 + lane;
+        const bool valid = t < P;
+        int x = 0, y = 0;
+        if (valid) {
+            cell_pixel(t, cw, ch, x, y);
+            x += x0;
+            y += y0;
+        }
+        const int p = y * W + x;
+        float g[9];
+#pragma unroll
+        for (int j = 0; j < 9; ++j)
+            g[j] = valid && sh.cand[j].k >= 0 ? gd[base + (long long)j * s.N + p] : 0.0f;
+#pragma unroll 1
+        for (int j = 0; j < 9; ++j) {                           // uniform
+            const SoftCand c = sh.cand[j];
+            if (c.k < 0) continue;
+            const float gj = g[j];
+            // no lane of this wave has the slot: skip its walks and reductions
+            if (__ballot(gj != 0.0f) == 0ULL) continue;
+            float gk[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
             float cf_end = 0.0f, cw_end = 0.0f;
-            int x = 0, y = 0, p = 0;
-            float g = 0.0f;
-            long long o = 0;
-            if (t < P) {
-                cell_pixel(t, cw, ch, x, y);
-                x += x0;
-                y += y0;
-                p = y * W + x;
-                o = base + (long long)j * s.N + p;
-                g = gd[o];
-            }
-            if (g != 0.0f) {
+            if (gj != 0.0f) {
+                const long long o = base + (long long)j * s.N + p;
                 const float A = fa[o], Bw = fb[o];
                 const int dx = c.cx - x, dy = c.cy - y;
                 const int adx = dx < 0 ? -dx : dx, ady = dy < 0 ? -dy : dy;
                 const int n = adx > ady ? adx : ady;
                 const float inv_np = 1.0f / (float)(n + 1);
-                const float cf = 2.0f * g * Bw * oml * inv_np;      // per path sample, times (f_q - f_k)
-                const float cw_ = g * A * s.gamma * inv_np;         // per path sample: dL/dw_q
+                const float cf = 2.0f * gj * Bw * oml * inv_np;  // per sample, times (f_q - f_k)
+                const float cw_ = gj * A * s.gamma * inv_np;     // per sample: dL/dw_q
+                const float lf = 2.0f * gj * Bw * lambda;        // lambda term of p
                 const float4 fp = img[p];
-                const float lf = 2.0f * g * Bw * lambda;            // lambda term of p
                 const float dl = fp.x - c.l, da = fp.y - c.a, db = fp.z - c.b;
                 gk[0] -= lf * dl;
                 gk[1] -= lf * da;
                 gk[2] -= lf * db;
-                gk[3] -= 2.0f * g * s.spw * ((float)x - c.x);
-                gk[4] -= 2.0f * g * s.spw * ((float)y - c.y);
-                // the path, samples i = 0 .. n (p itself included)
+                gk[3] -= 2.0f * gj * s.spw * ((float)x - c.x);
+                gk[4] -= 2.0f * gj * s.spw * ((float)y - c.y);
+                // samples i = 0 .. n-1 (p itself first); i = n is the endpoint
                 const bool xmaj = adx >= ady;
                 const int am = xmaj ? ady : adx;
                 const int two_n = 2 * n, inc = 2 * am;
@@ -503,21 +518,34 @@ __global__ __launch_bounds__(WG) void k_soft_bwd_path(SoftImg s, const float4* _
                     const int stx = dx < 0 ? -1 : 1, sty = dy < 0 ? -rw : rw;
                     const int smaj = xmaj ? stx : sty;
                     const int sdiag = smaj + (xmaj ? sty : stx);
+                    const int gty = dy < 0 ? -W : W;                // the same steps in the image
+                    const int gmaj = xmaj ? stx : gty;
+                    const int gdiag = gmaj + (xmaj ? gty : stx);
                     int li = (y - ry0) * rw + (x - rx0);
+                    int gi = p;
                     atomicAdd(&accx[li], lf * dl);
                     atomicAdd(&accy[li], lf * da);
                     atomicAdd(&accz[li], lf * db);
-                    for (int i = 0; i < n; ++i) {                   // samples 0 .. n-1
+                    for (int i = 0; i < n; ++i) {
                         if (i > 0) {
                             rem += inc;
                             const bool st = rem >= two_n;
                             rem -= st ? two_n : 0;
                             li += st ? sdiag : smaj;
+                            gi += st ? gdiag : gmaj;
                         }
-                        atomicAdd(&alpha[li], cf);
+                        const float4 fq = img[gi];
+                        const float el = cf * (fq.x - c.l), ea = cf * (fq.y - c.a),
+                                    eb = cf * (fq.z - c.b);
+                        atomicAdd(&accx[li], el);
+                        atomicAdd(&accy[li], ea);
+                        atomicAdd(&accz[li], eb);
                         atomicAdd(&accw[li], cw_);
+                        gk[0] -= el;
+                        gk[1] -= ea;
+                        gk[2] -= eb;
                     }
-                    cf_end = cf;                                    // sample n: the endpoint
+                    cf_end = cf;
                     cw_end = cw_;
                 } else {
                     const int stx = dx < 0 ? -1 : 1, sty = dy < 0 ? -W : W;
@@ -535,57 +563,51 @@ __global__ __launch_bounds__(WG) void k_soft_bwd_path(SoftImg s, const float4* _
                             gi += st ? sdiag : smaj;
                         }
                         const float4 fq = img[gi];
-                        const float el = fq.x - c.l, ea = fq.y - c.a, eb = fq.z - c.b;
-                        unsafeAtomicAdd(&gimg[gi].x, cf * el);
-                        unsafeAtomicAdd(&gimg[gi].y, cf * ea);
-                        unsafeAtomicAdd(&gimg[gi].z, cf * eb);
+                        const float el = cf * (fq.x - c.l), ea = cf * (fq.y - c.a),
+                                    eb = cf * (fq.z - c.b);
+                        unsafeAtomicAdd(&gimg[gi].x, el);
+                        unsafeAtomicAdd(&gimg[gi].y, ea);
+                        unsafeAtomicAdd(&gimg[gi].z, eb);
                         unsafeAtomicAdd(&gimg[gi].w, cw_);
-                        gk[0] -= cf * el;
-                        gk[1] -= cf * ea;
-                        gk[2] -= cf * eb;
+                        gk[0] -= el;
+                        gk[1] -= ea;
+                        gk[2] -= eb;
                     }
                 }
             }
-            if (c.staged) {                                     // uniform
-                const float se = wave_sum(cf_end), sw_ = wave_sum(cw_end);
-                if (lane == 0) {
-                    if (se != 0.0f) atomicAdd(&alpha[lic], se);
-                    if (sw_ != 0.0f) atomicAdd(&accw[lic], sw_);
-                }
+            // one butterfly for the seven wave sums: each step issues seven
+            // independent shuffles
+            float red[7] = {gk[0], gk[1], gk[2], gk[3], gk[4], cf_end, cw_end};
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+                for (int v = 0; v < 7; ++v) red[v] += __shfl_xor(red[v], o, 64);
             }
-        }
-        __syncthreads();
-        if (c.staged) {
-            // fold: dL/df_q += alpha_q (f_q - f_k); the candidate's colour
-            // gradient takes the opposite sum.  Clears alpha for the next slot.
-            const int fx0 = max(min(x0, c.cx), rx0), fx1 = min(max(x1, c.cx + 1), rx0 + rw);
-            const int fy0 = max(min(y0, c.cy), ry0), fy1 = min(max(y1, c.cy + 1), ry0 + sh.rh);
-            const int fw = fx1 - fx0, fa_ = fw * (fy1 - fy0);
-            for (int e = tid; e < fa_; e += WG) {
-                const int r = e / fw;
-                const int x = fx0 + (e - r * fw), y = fy0 + r;
-                const int li = (y - ry0) * rw + (x - rx0);
-                const float al = alpha[li];
-                if (al != 0.0f) {
-                    const float4 fq = img[(long long)y * W + x];
-                    const float el = al * (fq.x - c.l), ea = al * (fq.y - c.a),
-                                eb = al * (fq.z - c.b);
-                    accx[li] += el;
-                    accy[li] += ea;
-                    accz[li] += eb;
+#pragma unroll
+            for (int v = 0; v < 5; ++v) gk[v] = red[v];
+            if (c.staged) {                                     // uniform
+                // the endpoint: (sum cf) (f_c - f_k) and sum dL/dw
+                const float se = red[5], swe = red[6];
+                if (lane == 0 && (se != 0.0f || swe != 0.0f)) {
+                    const int lic = (c.cy - ry0) * rw + (c.cx - rx0);
+                    const float4 fc = img[(long long)c.cy * W + c.cx];
+                    const float el = se * (fc.x - c.l), ea = se * (fc.y - c.a),
+                                eb = se * (fc.z - c.b);
+                    atomicAdd(&accx[lic], el);
+                    atomicAdd(&accy[lic], ea);
+                    atomicAdd(&accz[lic], eb);
+                    atomicAdd(&accw[lic], swe);
                     gk[0] -= el;
                     gk[1] -= ea;
                     gk[2] -= eb;
-                    alpha[li] = 0.0f;
                 }
             }
+            if (lane == 0)
+                for (int v = 0; v < 5; ++v)
+                    if (gk[v] != 0.0f) atomicAdd(&sh.bins[j][v], gk[v]);
         }
-        for (int v = 0; v < 5; ++v) {
-            const float sv = wave_sum(gk[v]);
-            if (lane == 0 && sv != 0.0f) atomicAdd(&sh.bins[j][v], sv);
-        }
-        __syncthreads();
     }
+    __syncthreads();
     // flush the workgroup's tiles
     for (int e = tid; e < area; e += WG) {
         const float vx = accx[e], vy = accy[e], vz = accz[e], vw = accw[e];
@@ -608,17 +630,15 @@ __global__ __launch_bounds__(WG) void k_soft_bwd_path(SoftImg s, const float4* _
 
 // Theta_0 = cell means: dL/df_p += dL/dTheta_0 / |cell|; then the outputs:
 // dL/dlab = dL/df and dL/dC = dL/dw * 2C/sigma^2 exp(-C^2/sigma^2).
-__global__ void k_soft_bwd_finish(SoftImg s, const float4* __restrict__ gf,
-                                  const float* __restrict__ gth0,
-                                  const float* __restrict__ contour, float sigma,
-                                  float* __restrict__ glab, float* __restrict__ gcon) {
-    const long long total = (long long)s.B * s.N;
+__global__ __launch_bounds__(256) void k_soft_bwd_finish(SoftImg s, const float4* __restrict__ gf,
+                                                         const float* __restrict__ gth0,
+                                                         const float* __restrict__ contour,
+                                                         float sigma, float* __restrict__ glab,
+                                                         float* __restrict__ gcon) {
     const double s2 = (double)sigma * (double)sigma;
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
-         i += (long long)gridDim.x * blockDim.x) {
-        const int b = (int)(i / s.N);
-        const long long p = i - (long long)b * s.N;
-        const int y = (int)(p / s.W), x = (int)(p - (long long)y * s.W);
+    SOFT_FOR_PIXELS(s) {
+        const long long p = (long long)y * s.W + x;
+        const long long i = (long long)b * s.N + p;
         const int ci = (int)(((long long)y * s.ny) / s.H), cj = (int)(((long long)x * s.nx) / s.W);
         const int cnt = (cell_lo(cj + 1, s.W, s.nx) - cell_lo(cj, s.W, s.nx)) *
                         (cell_lo(ci + 1, s.H, s.ny) - cell_lo(ci, s.H, s.ny));
@@ -639,6 +659,7 @@ __global__ void k_copy_f32(const float* __restrict__ src, float* __restrict__ ds
 }
 
 constexpr int kSoftWG = 256;
+constexpr int kSoftBwdWG = 512;
 
 unsigned grid_for(long long n) {
     return (unsigned)std::max<long long>(1, std::min<long long>((n + 255) / 256, 65536));
@@ -652,6 +673,13 @@ SoftGeom soft_geom(int W, int H, int nx, int ny, int B, float spw, float gamma, 
     g.W = W; g.H = H; g.nx = nx; g.ny = ny; g.B = B; g.wg = wg;
     g.spw = spw; g.gamma = gamma; g.lambda = lambda; g.temperature = temperature;
     return g;
+}
+
+// Grid of the per-pixel soft kernels: about 4096 blocks over all images.
+static dim3 pixel_grid(const SoftImg& s) {
+    const int bx = (s.W + 255) / 256;
+    const int by = std::max(1, std::min(s.H, 4096 / std::max(1, bx * s.B)));
+    return dim3((unsigned)bx, (unsigned)std::min(by, 65535), (unsigned)s.B);
 }
 
 static SoftImg to_img(const SoftGeom& g) {
@@ -668,9 +696,7 @@ void lift_soft_lds_limits() {
     for (const void* k : {reinterpret_cast<const void*>(k_soft_assign<256>),
                           reinterpret_cast<const void*>(k_soft_assign<512>),
                           reinterpret_cast<const void*>(k_soft_assign<1024>),
-                          reinterpret_cast<const void*>(k_soft_bwd_path<256>),
-                          reinterpret_cast<const void*>(k_soft_bwd_path<512>),
-                          reinterpret_cast<const void*>(k_soft_bwd_path<1024>)}) {
+                          reinterpret_cast<const void*>(k_soft_bwd_path<kSoftBwdWG>)}) {
         static_cast<void>(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                               (int)cap));
         static_cast<void>(hipGetLastError());
@@ -700,7 +726,7 @@ int launch_soft_assign(const SoftGeom& g, const float4* packed, const float* the
     else if (g.wg == 512) e = soft_assign_t<512>(s, packed, theta_prev, q, fa, fb, cap, st);
     else e = soft_assign_t<256>(s, packed, theta_prev, q, fa, fb, cap, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_soft_softmax, dim3(grid_for(s.B * s.N)), dim3(256), 0, st, s, q);
+    hipLaunchKernelGGL(k_soft_softmax, pixel_grid(s), dim3(256), 0, st, s, q);
     return hipGetLastError();
 }
 
@@ -716,7 +742,7 @@ int launch_soft_bwd_update(const SoftGeom& g, int first, const float* q, const d
                            const float* theta, const float4* packed, const float* gth,
                            const float* gq_in, float* gd, float4* gf, hipStream_t st) {
     const SoftImg s = to_img(g);
-    hipLaunchKernelGGL(k_soft_bwd_update, dim3(grid_for(s.B * s.N)), dim3(256), 0, st, s, first, q,
+    hipLaunchKernelGGL(k_soft_bwd_update, pixel_grid(s), dim3(256), 0, st, s, first, q,
                        z, theta, packed, gth, gq_in, gd, gf);
     return hipGetLastError();
 }
@@ -734,7 +760,7 @@ static int soft_bwd_path_t(const SoftImg& s, const float4* packed, const float* 
                            const float* fa, const float* fb, const float* gd, float4* gf,
                            float* gth_prev, int cap, hipStream_t st) {
     hipLaunchKernelGGL(k_soft_bwd_path<WG>, dim3(s.B * s.K), dim3(WG),
-                       (size_t)cap * (sizeof(float4) + sizeof(float)), st, s, packed, theta_prev,
+                       (size_t)cap * 4 * sizeof(float), st, s, packed, theta_prev,
                        fa, fb, gd, gf, gth_prev, cap);
     return hipGetLastError();
 }
@@ -742,19 +768,17 @@ static int soft_bwd_path_t(const SoftImg& s, const float4* packed, const float* 
 int launch_soft_bwd_path(const SoftGeom& g, const float4* packed, const float* theta_prev,
                          const float* fa, const float* fb, const float* gd, float4* gf,
                          float* gth_prev, int cap, hipStream_t st) {
-    const SoftImg s = to_img(g);
-    if (g.wg == 1024)
-        return soft_bwd_path_t<1024>(s, packed, theta_prev, fa, fb, gd, gf, gth_prev, cap, st);
-    if (g.wg == 512)
-        return soft_bwd_path_t<512>(s, packed, theta_prev, fa, fb, gd, gf, gth_prev, cap, st);
-    return soft_bwd_path_t<256>(s, packed, theta_prev, fa, fb, gd, gf, gth_prev, cap, st);
+    // one shape for the backward pass whatever the assignment's (measured
+    // fastest on 16 x 512x512, k = 400: 512 lanes)
+    return soft_bwd_path_t<kSoftBwdWG>(to_img(g), packed, theta_prev, fa, fb, gd, gf, gth_prev,
+                                       cap, st);
 }
 
 int launch_soft_bwd_finish(const SoftGeom& g, const float4* gf, const float* gth0,
                            const float* contour, float sigma, float* glab, float* gcon,
                            hipStream_t st) {
     const SoftImg s = to_img(g);
-    hipLaunchKernelGGL(k_soft_bwd_finish, dim3(grid_for(s.B * s.N)), dim3(256), 0, st, s, gf, gth0,
+    hipLaunchKernelGGL(k_soft_bwd_finish, pixel_grid(s), dim3(256), 0, st, s, gf, gth0,
                        contour, sigma, glab, gcon);
     return hipGetLastError();
 }

@@ -115,6 +115,10 @@ def test_mode_parameters_are_validated_on_host():
         pp = L.default_params(**over)
         assert lib.scalp_soft_forward(ctypes.byref(g), ctypes.byref(pp), ctypes.c_float(0.5), 1,
                                       fake, fake, fake, fake, fake, fake, sw, None) == code, over
+    p = L.default_params()
+    for batch in (0, 65536):
+        assert lib.scalp_soft_forward(ctypes.byref(g), ctypes.byref(p), ctypes.c_float(0.5), batch,
+                                      fake, fake, fake, fake, fake, fake, sw, None) == L.SCALP_ERR_ARG
     with pytest.raises(TypeError):
         L.default_params(not_a_parameter=1)
 
