@@ -171,6 +171,24 @@ def test_update_arbitrary_labels(orc):
     assert (cnt == ocnt).all() and (nc == oc).all() and (ne == oe).all()
 
 
+def test_update_many_labels_per_cell(orc):
+    """Random labels over 64 superpixels on a 64x64 image: each 8x8 cell holds
+    more distinct labels than the update's per-cell LDS table (32 slots), so
+    the overflow goes to the global sums; results stay exact."""
+    W, H, k = 64, 64, 64
+    img = _image(W, H, 10)
+    g = orc.grid(W, H, k)
+    rng = np.random.default_rng(11)
+    labels = rng.integers(0, g.num_sp, (H, W)).astype(np.int32)
+    c, e, _ = orc.init_grid(g, img.lab, mode=orc.MEAN_FIXED)
+    s = _scalp(W, H, k)
+    say("update many labels per cell")
+    nc, ne, cnt = (host(t) for t in s.update(dev(img.lab), dev(labels), dev(c), dev(e)))
+    oc, ocnt = orc.update(g, img.lab, labels, c, mode=orc.MEAN_FIXED)
+    oe, _ = orc.project(g, labels, oc, ocnt, e)
+    assert (cnt == ocnt).all() and (nc == oc).all() and (ne == oe).all()
+
+
 def _compare_runs(orc, img, k, iters, **kw):
     H, W = img.contour.shape
     s = _scalp(W, H, k, **kw)
