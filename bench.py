@@ -223,7 +223,8 @@ def cpu_baseline(img, k, iters):
         orc.run(img.lab, img.contour, k, iterations=iters)
         reps += 1
         el = time.perf_counter() - t0
-        if el >= 10.0 or reps >= 3:
+        # a bounded sample: at least 10 s of CPU work, at most 12 full runs
+        if el >= 10.0 or reps >= 12:
             break
     return {"value": round(W * H * iters * reps / el / 1e6, 3), "unit": "Mpixel-iter/s",
             "cores": threads, "kind": "oracle",
