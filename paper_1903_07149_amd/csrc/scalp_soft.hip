@@ -323,12 +323,17 @@ __global__ __launch_bounds__(WG) void k_soft_update(SoftImg s, const float* __re
     const int bw = X1 - X0, area = bw * (Y1 - Y0);
     const float4* img = packed + (long long)b * s.N;
     const float* qb = q + 9LL * s.N * b;
+    // the block's inner cell boundaries: a pixel's cell row is ci - 1 + (y >= yb1)
+    // + (y >= yb2), likewise for columns
+    const int yb1 = cell_lo(ci, s.H, s.ny), yb2 = cell_lo(ci + 1, s.H, s.ny);
+    const int xb1 = cell_lo(cj, s.W, s.nx), xb2 = cell_lo(cj + 1, s.W, s.nx);
     double acc[6] = {0, 0, 0, 0, 0, 0};
     for (int e = tid; e < area; e += WG) {
         const int r = e / bw;
         const int x = X0 + (e - r * bw), y = Y0 + r;
-        const int cip = (int)(((long long)y * s.ny) / s.H), cjp = (int)(((long long)x * s.nx) / s.W);
-        const int j = (ci - cip + 1) * 3 + (cj - cjp + 1);
+        const int di = (y >= yb1 ? 1 : 0) + (y >= yb2 ? 1 : 0);
+        const int dj = (x >= xb1 ? 1 : 0) + (x >= xb2 ? 1 : 0);
+        const int j = (2 - di) * 3 + (2 - dj);      // the pixel's slot that points at k
         const long long p = (long long)y * s.W + x;
         const double Q = qb[(long long)j * s.N + p];
         const float4 f = img[p];
