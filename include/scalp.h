@@ -261,7 +261,9 @@ int scalp_soft_forward(const scalp_grid_t* g, const scalp_params_t* p, float tem
  * (grad_centers: [B][K'][5]) with respect to lab (grad_lab: [B][H][W][3],
  * output) and contour (grad_contour: [B][H][W], output).  Path samples are
  * recomputed, not stored; slots whose Q is below 2^-24 contribute no path
- * terms (each is proportional to Q).  FP32 with float atomics: not
+ * terms (each is proportional to Q).  contour is always required (dw/dC
+ * needs it); lab may be null when reuse_prepared is set and the workspace
+ * holds the packed image of the forward call.  FP32 with float atomics: not
  * bit-reproducible. */
 int scalp_soft_backward(const scalp_grid_t* g, const scalp_params_t* p, float temperature,
                         int32_t batch, const float* lab, const float* contour,
@@ -278,7 +280,8 @@ int scalp_soft_backward(const scalp_grid_t* g, const scalp_params_t* p, float te
  * ground-truth partition `gt` (int32 [H][W], values in [0, num_regions)).
  * A pixel is a boundary pixel when a 4-neighbour inside the image has
  * another label; BR counts ground-truth boundary pixels with a superpixel
- * boundary pixel at Euclidean distance < epsilon (the paper uses 2);
+ * boundary pixel at Euclidean distance < epsilon (the paper uses 2;
+ * 0 < epsilon <= 64, else SCALP_ERR_ARG);
  * perimeters count 4-connected pixel edges, the image border included.
  * Pixels whose label or region is out of range are left out of the overlap
  * table and the perimeters.  out: device double[6] = {BR, ASA, UE, CO,
