@@ -115,7 +115,11 @@ __device__ __forceinline__ unsigned step_increment(int am, int n) {
 // i.e. n < 46340 (tables never exceed 2 x 9728 entries, so every path over a
 // table qualifies), and an exact tie is never undershot since F rounds up.
 // One add with carry-out, one select and one address add per sample; four
-// samples per loop trip with the loads issued ahead of the adds.
+// samples per loop trip with the loads issued ahead of the adds.  The trip
+// counter is decremented with a borrow-out that is itself the exit test, and
+// the accumulator passes through an empty asm statement once per trip so
+// that the compiler keeps the chain of adds instead of re-deriving acc from
+// a separate induction variable (one instruction less per trip each).
 __device__ __forceinline__ void walk_table(const float2* tab, int idx, int tw, int dx, int dy,
                                            float& sc, float& sw) {
     const int adx = dx < 0 ? -dx : dx;
@@ -136,38 +140,53 @@ __device__ __forceinline__ void walk_table(const float2* tab, int idx, int tw, i
         const bool c_ = __builtin_add_overflow(acc, F, &acc);     \
         q += c_ ? sdiag : smaj;                                   \
     } while (0)
+#define SCALP_LOAD() (*reinterpret_cast<const float2*>(q))
 #define SCALP_ACC(v)                                              \
     do {                                                          \
         sc = sc + (v).x;                                          \
         sw = sw + (v).y;                                          \
     } while (0)
+    // samples 1 .. n-1 (sample 0 and the endpoint are added by the caller)
     SCALP_STEP();
-    float2 fa = *reinterpret_cast<const float2*>(q);
-    int left = n - 2;
-    while (left >= 4) {
+    float2 fa = SCALP_LOAD();
+    unsigned trips = (unsigned)(n - 2) >> 2;
+    while (!__builtin_sub_overflow(trips, 1u, &trips)) {
         SCALP_STEP();
-        const float2 fb = *reinterpret_cast<const float2*>(q);
+        const float2 fb = SCALP_LOAD();
         SCALP_STEP();
-        const float2 fc = *reinterpret_cast<const float2*>(q);
+        const float2 fc = SCALP_LOAD();
         SCALP_ACC(fa);
         SCALP_STEP();
-        const float2 fd = *reinterpret_cast<const float2*>(q);
+        const float2 fd = SCALP_LOAD();
         SCALP_ACC(fb);
         SCALP_STEP();
-        fa = *reinterpret_cast<const float2*>(q);
+        fa = SCALP_LOAD();
         SCALP_ACC(fc);
         SCALP_ACC(fd);
-        left -= 4;
+        asm volatile("" : "+v"(acc));
     }
-    while (left > 0) {
+    const int rem = (n - 2) & 3;
+    if (rem > 0) {
         SCALP_STEP();
-        const float2 fb = *reinterpret_cast<const float2*>(q);
+        const float2 fb = SCALP_LOAD();
         SCALP_ACC(fa);
         fa = fb;
-        --left;
+    }
+    if (rem > 1) {
+        SCALP_STEP();
+        const float2 fb = SCALP_LOAD();
+        SCALP_ACC(fa);
+        fa = fb;
+    }
+    if (rem > 2) {
+        SCALP_STEP();
+        const float2 fb = SCALP_LOAD();
+        SCALP_ACC(fa);
+        fa = fb;
     }
     SCALP_ACC(fa);
 #undef SCALP_STEP
+#undef SCALP_LOAD
 #undef SCALP_ACC
 }
 
@@ -182,16 +201,22 @@ namespace {
 __constant__ const RecipTable kRecip = RecipTable();
 }
 
+// RN(1 / (n + 1)) for a path of n steps (np = n + 1 samples), clamped to the
+// table; callers fetch it before walking the path so that the load's latency
+// hides behind the walk.
+__device__ __forceinline__ double path_recip(int n) { return kRecip.v[(n < 1023 ? n : 1023) + 1]; }
+
 // a / np and b / np in IEEE FP32 (np = n + 1) for the two averages of
-// Eqs. (1)-(2).  For np <= 1024 and a, b zero or at least 2^-100, the FP32
-// rounding of the FP64 product a * RN(1/np) is the IEEE quotient: a float
-// divided by an integer np is never a rounding midpoint of FP32 and stays at
-// least 2^-35 (relative) away from one for np <= 1024, while the product's
-// error is below 2^-52.  Other operands take the IEEE division itself.
-__device__ __forceinline__ void div_path_len(float a, float b, int n, float& qa, float& qb) {
+// Eqs. (1)-(2); inv = path_recip(n).  For np <= 1024 and a, b zero or at
+// least 2^-100, the FP32 rounding of the FP64 product a * RN(1/np) is the
+// IEEE quotient: a float divided by an integer np is never a rounding
+// midpoint of FP32 and stays at least 2^-35 (relative) away from one for
+// np <= 1024, while the product's error is below 2^-52.  Other operands take
+// the IEEE division itself.
+__device__ __forceinline__ void div_path_len(float a, float b, int n, double inv, float& qa,
+                                             float& qb) {
     const bool fast = n < 1024 && !(a > 0.0f && a < 0x1p-100f) && !(b > 0.0f && b < 0x1p-100f);
     if (fast) {
-        const double inv = kRecip.v[n + 1];
         qa = (float)((double)a * inv);
         qb = (float)((double)b * inv);
     } else {

@@ -41,10 +41,17 @@ struct Cand {
     int tx0, ty0, tw, th;   // its LDS table: origin, row pitch, rows; tw == 0: paths read global memory
 };
 
-// Per work item: the candidates and the update bins.
+// Copies of the update bins: the lanes of a wave mostly pick the same
+// candidate, and 64-bit LDS atomics on one word serialise, so lane t adds to
+// copy (t ^ (t >> 3)) mod kBinCopies: every row and every column of the
+// wave's 8x8 pixel block spreads over all copies, and at most 8 lanes of a
+// wave share one word.
+constexpr int kBinCopies = 8;
+
+// Per work item: the candidates and the update bins, [slot * 6 + sum][copy].
 struct CellShared {
     Cand cand[9];
-    unsigned long long bins[9][6];
+    unsigned long long bins[9 * 6][kBinCopies];
 };
 
 // Strip (8-column band) of cell pixel t, in the order of cell_pixel.
@@ -128,7 +135,7 @@ __device__ __forceinline__ void process_cell(const Img& im, int cell, int slice,
         sh.cand[tid] = c;
     }
     if (ACCUM) {
-        for (int t = tid; t < 54; t += WG) (&sh.bins[0][0])[t] = 0ULL;
+        for (int t = tid; t < 54 * kBinCopies; t += WG) (&sh.bins[0][0])[t] = 0ULL;
     }
     __syncthreads();
 
@@ -175,6 +182,9 @@ __device__ __forceinline__ void process_cell(const Img& im, int cell, int slice,
         const float dcc = sh.cand[j].dcc, wc = sh.cand[j].wc;
         if (mine) {
             const int dx = cx - x, dy = cy - y;
+            const int adx = dx < 0 ? -dx : dx, ady = dy < 0 ? -dy : dy;
+            const int n = adx > ady ? adx : ady;
+            const double inv = path_recip(n);
             float dcp, sc, sw;
             if (tw > 0) {
                 const int lidx = (y - ty0) * tw + (x - tx0);
@@ -191,14 +201,12 @@ __device__ __forceinline__ void process_cell(const Img& im, int cell, int slice,
                 sw = fp.w;
                 walk_path(img, p, 1, W, dx, dy, l, a, b, sc, sw);
             }
-            const int adx = dx < 0 ? -dx : dx, ady = dy < 0 ? -dy : dy;
-            const int n = adx > ady ? adx : ady;
             if (n > 0) {                           // sample i = n is the endpoint
                 sc = sc + dcc;
                 sw = sw + wc;
             }
             float qc, qw;                          // sc / |P|, sw / |P|
-            div_path_len(sc, sw, n, qc, qw);
+            div_path_len(sc, sw, n, inv, qc, qw);
             const float A = lambda * dcp + oml * qc;             // Eq. (1)
             const float B = 1.0f + gamma * qw;                   // Eq. (2)
             const float ex = (float)x - ccx;
@@ -218,23 +226,30 @@ __device__ __forceinline__ void process_cell(const Img& im, int cell, int slice,
         labels[im.pix + p] = sh.cand[bj].k;
         if (ACCUM) {
             const float4 fp = img[p];
-            unsigned long long* bin = sh.bins[bj];
-            atomicAdd(bin + 0, 1ULL);
-            atomicAdd(bin + 1, (unsigned long long)x);
-            atomicAdd(bin + 2, (unsigned long long)y);
-            atomicAdd(bin + 3, (unsigned long long)to_fixed(fp.x));
-            atomicAdd(bin + 4, (unsigned long long)to_fixed(fp.y));
-            atomicAdd(bin + 5, (unsigned long long)to_fixed(fp.z));
+            const int cp = (tid ^ (tid >> 3)) & (kBinCopies - 1);
+            unsigned long long(*bin)[kBinCopies] = sh.bins + 6 * bj;
+            atomicAdd(&bin[0][cp], 1ULL);
+            atomicAdd(&bin[1][cp], (unsigned long long)x);
+            atomicAdd(&bin[2][cp], (unsigned long long)y);
+            atomicAdd(&bin[3][cp], (unsigned long long)to_fixed(fp.x));
+            atomicAdd(&bin[4][cp], (unsigned long long)to_fixed(fp.y));
+            atomicAdd(&bin[5][cp], (unsigned long long)to_fixed(fp.z));
         }
     }
     if (ACCUM) {
         __syncthreads();
         if (tid < 54) {
-            const int j = tid / 6, v = tid - 6 * (tid / 6);
+            const int j = tid / 6;
             const int k = sh.cand[j].k;
-            if (k >= 0 && sh.bins[j][0] != 0ULL)
-                atomicAdd((unsigned long long*)(acc + kAccStride * (long long)(im.sp + k) + v),
-                          sh.bins[j][v]);
+            unsigned long long n = 0, v = 0;
+            for (int c = 0; c < kBinCopies; ++c) {
+                n += sh.bins[6 * j][c];
+                v += sh.bins[tid][c];
+            }
+            if (k >= 0 && n != 0ULL)
+                atomicAdd((unsigned long long*)(acc + kAccStride * (long long)(im.sp + k) +
+                                                (tid - 6 * j)),
+                          v);
         }
     }
     __syncthreads();   // shared state is reused by the next cell of a persistent workgroup
@@ -343,20 +358,21 @@ __global__ __launch_bounds__(WG) void k_assign_window(Img im, const float4* __re
         const int p = y * W + x;
         const float4 fp = img[p];
         const int dx = cx - x, dy = cy - y;
+        const int adx = dx < 0 ? -dx : dx, ady = dy < 0 ? -dy : dy;
+        const int n = adx > ady ? adx : ady;
+        const double inv = path_recip(n);
         const float dcp = colour_dist(fp, l, a, b);
         float sc = dcp, sw = fp.w;
         if (staged)
             walk_table(win_tab, (y - ry0) * rw + (x - rx0), rw, dx, dy, sc, sw);
         else
             walk_path(img, p, 1, W, dx, dy, l, a, b, sc, sw);
-        const int adx = dx < 0 ? -dx : dx, ady = dy < 0 ? -dy : dy;
-        const int n = adx > ady ? adx : ady;
         if (n > 0) {
             sc = sc + dcc;
             sw = sw + wc;
         }
         float qc, qw;
-        div_path_len(sc, sw, n, qc, qw);
+        div_path_len(sc, sw, n, inv, qc, qw);
         const float A = lambda * dcp + oml * qc;
         const float B = 1.0f + im.gamma * qw;
         const float ex = (float)x - xk, ey = (float)y - yk;

@@ -216,6 +216,9 @@ __global__ __launch_bounds__(WG) void k_soft_assign(SoftImg s, const float4* __r
             y += y0;
             const int p = y * W + x;
             const int dx = cx - x, dy = cy - y;
+            const int adx = dx < 0 ? -dx : dx, ady = dy < 0 ? -dy : dy;
+            const int n = adx > ady ? adx : ady;
+            const double inv = path_recip(n);
             float dcp, sc, sw;
             if (staged) {
                 const int lidx = (y - ty0) * tw + (x - tx0);
@@ -231,14 +234,12 @@ __global__ __launch_bounds__(WG) void k_soft_assign(SoftImg s, const float4* __r
                 sw = fp.w;
                 walk_path(img, p, 1, W, dx, dy, l, a, bb, sc, sw);
             }
-            const int adx = dx < 0 ? -dx : dx, ady = dy < 0 ? -dy : dy;
-            const int n = adx > ady ? adx : ady;
             if (n > 0) {
                 sc = sc + dcc;
                 sw = sw + wc;
             }
             float qc, qw;
-            div_path_len(sc, sw, n, qc, qw);
+            div_path_len(sc, sw, n, inv, qc, qw);
             const float A = lambda * dcp + oml * qc;
             const float Bw = 1.0f + s.gamma * qw;
             const float ex = (float)x - ccx, ey = (float)y - ccy;
