@@ -595,7 +595,11 @@ bool soft_args_ok(const scalp_grid_t* g, const scalp_params_t* p, float temperat
     if (!(temperature > 0.0f) || !std::isfinite(temperature)) return false;
     if (batch < 1 || batch > 65535 || p->iterations < 1) return false;
     const long long N = (long long)g->width * g->height;
-    return (long long)batch * N < (1LL << 40);
+    if ((long long)batch * N >= (1LL << 40)) return false;
+    // one workgroup per (image, cell, slice) must fit a 32-bit grid
+    const long long items = (long long)batch * g->num_sp *
+                            soft_slices(g->width, g->height, g->nx, g->ny, kMinAssignWG);
+    return items <= 0x7fffffffLL;
 }
 
 int soft_cap_bytes(const scalp_params_t* p) {

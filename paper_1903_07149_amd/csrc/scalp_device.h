@@ -102,6 +102,41 @@ __device__ __forceinline__ unsigned step_increment(int am, int n) {
     return (unsigned)ceil((double)am * 4294967296.0 / (double)n);
 }
 
+// Fills an LDS table with (d_c(q), w_q) for the texels of a rectangle of
+// the packed image: entry e = r * tw + c holds texel (min(tx0 + c, W - 1),
+// ty0 + r), for e < area (entries past the rectangle's width only pad the
+// row pitch and are never read by a path).  Lanes step by WG entries, i.e.
+// by (WG / tw rows, WG mod tw columns), with no division per entry, and
+// take two entries per trip with both loads issued before either is used.
+template <int WG>
+__device__ __forceinline__ void fill_table(float2* tab, const float4* __restrict__ img, int W,
+                                           int tx0, int ty0, int tw, int area, float l, float a,
+                                           float b) {
+    const int tid = threadIdx.x;
+    const int dr = WG / tw, dc = WG - dr * tw;
+    int r = tid / tw, c = tid - r * tw;
+    const float4* row = img + (long long)(ty0 + r) * W;
+    int e = tid;
+    for (; e + WG < area; e += 2 * WG) {
+        const float4 f0 = row[min(tx0 + c, W - 1)];
+        c += dc;
+        bool wrap = c >= tw;
+        c -= wrap ? tw : 0;
+        row += (long long)(dr + (wrap ? 1 : 0)) * W;
+        const float4 f1 = row[min(tx0 + c, W - 1)];
+        c += dc;
+        wrap = c >= tw;
+        c -= wrap ? tw : 0;
+        row += (long long)(dr + (wrap ? 1 : 0)) * W;
+        tab[e] = make_float2(colour_dist(f0, l, a, b), f0.w);
+        tab[e + WG] = make_float2(colour_dist(f1, l, a, b), f1.w);
+    }
+    if (e < area) {
+        const float4 f = row[min(tx0 + c, W - 1)];
+        tab[e] = make_float2(colour_dist(f, l, a, b), f.w);
+    }
+}
+
 // The walk over a per-candidate LDS table of (colour distance, w) pairs: the
 // colour distance of a texel to the candidate does not depend on the pixel
 // the path starts from, so it is computed once per texel (same FP32
@@ -271,6 +306,35 @@ __device__ __forceinline__ void cell_pixel(int t, int cw, int ch, int& x, int& y
     }
     y = (s & 1) ? (ch - 1 - row) : row;
     x = col;
+}
+
+// Strip (8-column band) of cell pixel t, in the order of cell_pixel.
+__device__ __forceinline__ int strip_of(int t, int cw, int ch) {
+    const int fullpx = (cw >> 3) * 8 * ch;
+    return t < fullpx ? t / (8 * ch) : (cw >> 3);
+}
+
+// x of lane i - CTRL's shift, 0 where that lane is outside the row or the
+// row is not in ROW_MASK (DPP: gfx9 row_shr / row_bcast controls).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_or_zero(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xf,
+                                                      false));
+}
+
+// Sum over the 64 lanes of a wave in six DPP steps (no LDS traffic): row
+// prefix sums by shifts of 1, 2, 4 and 8 lanes, then the last lane of each
+// row is broadcast into the next row (row_bcast:15) and lane 31 into rows 2
+// and 3 (row_bcast:31).  Only lane 63 holds the total.  All lanes must be
+// active.
+__device__ __forceinline__ float wave_sum_last(float v) {
+    v += dpp_or_zero<0x111, 0xf>(v);
+    v += dpp_or_zero<0x112, 0xf>(v);
+    v += dpp_or_zero<0x114, 0xf>(v);
+    v += dpp_or_zero<0x118, 0xf>(v);
+    v += dpp_or_zero<0x142, 0xa>(v);
+    v += dpp_or_zero<0x143, 0xc>(v);
+    return v;
 }
 
 __device__ __forceinline__ float wave_sum(float v) {

@@ -106,6 +106,9 @@ struct SoftGeom {
 SoftGeom soft_geom(int W, int H, int nx, int ny, int B, float spw, float gamma, float lambda,
                    float temperature, int wg);
 void lift_soft_lds_limits();
+// Work items per cell of the soft assignment at workgroup size wg: a cell
+// is cut into slices of whole 64-pixel chunks, at most wg pixels each.
+int soft_slices(int W, int H, int nx, int ny, int wg);
 int launch_soft_init(const SoftGeom& g, const float4* packed, float* theta0, hipStream_t st);
 int launch_soft_assign(const SoftGeom& g, const float4* packed, const float* theta_prev, float* q,
                        float* fa, float* fb, int cap, hipStream_t st);

@@ -54,12 +54,6 @@ struct CellShared {
     unsigned long long bins[9 * 6][kBinCopies];
 };
 
-// Strip (8-column band) of cell pixel t, in the order of cell_pixel.
-__device__ __forceinline__ int strip_of(int t, int cw, int ch) {
-    const int fullpx = (cw >> 3) * 8 * ch;
-    return t < fullpx ? t / (8 * ch) : (cw >> 3);
-}
-
 // Work item (cell, slice): pixels [t0, t1) of the cell in cell_pixel order,
 // one per lane.  The cell's ceil(P / 64) 64-pixel chunks are split evenly
 // over its spl slices (spl is chosen on the host so that no slice has more
@@ -160,21 +154,7 @@ __device__ __forceinline__ void process_cell(const Img& im, int cell, int slice,
         const int tw = sh.cand[j].tw, tx0 = sh.cand[j].tx0, ty0 = sh.cand[j].ty0;
         float2* tab = lds + (buf ? cap : 0);
         if (tw > 0) {                              // uniform
-            // entries past the rectangle's width pad the pitch; they are
-            // filled from clamped columns and never read by a path
-            const int area = tw * sh.cand[j].th;
-            // entry e = r * tw + c; lanes step by WG entries = (dr, dc)
-            const int dr = WG / tw, dc = WG - dr * tw;
-            int r = tid / tw, c = tid - r * tw;
-            const float4* row = img + (long long)(ty0 + r) * W;
-            for (int e = tid; e < area; e += WG) {
-                const float4 f = row[min(tx0 + c, W - 1)];
-                tab[e] = make_float2(colour_dist(f, l, a, b), f.w);
-                c += dc;
-                const bool wrap = c >= tw;
-                c -= wrap ? tw : 0;
-                row += (long long)(dr + (wrap ? 1 : 0)) * W;
-            }
+            fill_table<WG>(tab, img, W, tx0, ty0, tw, tw * sh.cand[j].th, l, a, b);
             __syncthreads();
             buf ^= 1;
         }
@@ -335,12 +315,7 @@ __global__ __launch_bounds__(WG) void k_assign_window(Img im, const float4* __re
     const bool staged = (long long)(rx1 - rx0) * (ry1 - ry0) <= 2LL * cap;
     const int rw = rx1 - rx0;
     if (staged) {
-        const int area = rw * (ry1 - ry0);
-        for (int e = tid; e < area; e += WG) {
-            const int r = e / rw;
-            const float4 f = img[(long long)(ry0 + r) * W + rx0 + (e - r * rw)];
-            win_tab[e] = make_float2(colour_dist(f, l, a, b), f.w);
-        }
+        fill_table<WG>(win_tab, img, W, rx0, ry0, rw, rw * (ry1 - ry0), l, a, b);
     }
     __syncthreads();
     const float4 fc = img[(long long)cy * W + cx];
@@ -494,15 +469,18 @@ __global__ __launch_bounds__(WG) void k_accumulate(Img im, LabSource src,
                                                    const int* __restrict__ labels,
                                                    long long* __restrict__ acc) {
     __shared__ int keys[kAccSlots];
-    __shared__ unsigned long long bins[kAccSlots][6];
+    // [slot * 6 + sum][copy]: the lanes of a wave mostly carry one label, so
+    // each adds to copy (t ^ t >> 3) mod kBinCopies (see CellShared)
+    __shared__ unsigned long long bins[kAccSlots * 6][kBinCopies];
     const int tid = threadIdx.x;
     const int cell = blockIdx.x;
     const int ci = cell / im.nx, cj = cell - ci * im.nx;
     const int x0 = cell_lo(cj, im.W, im.nx), x1 = cell_lo(cj + 1, im.W, im.nx);
     const int y0 = cell_lo(ci, im.H, im.ny), y1 = cell_lo(ci + 1, im.H, im.ny);
     const int K = im.nx * im.ny;
-    for (int t = tid; t < kAccSlots * 6; t += WG) (&bins[0][0])[t] = 0ULL;
+    for (int t = tid; t < kAccSlots * 6 * kBinCopies; t += WG) (&bins[0][0])[t] = 0ULL;
     for (int t = tid; t < kAccSlots; t += WG) keys[t] = -1;
+    const int cp = (tid ^ (tid >> 3)) & (kBinCopies - 1);
     __syncthreads();
     const int cw = x1 - x0, P = cw * (y1 - y0);
     for (int t = tid; t < P; t += WG) {
@@ -527,7 +505,7 @@ __global__ __launch_bounds__(WG) void k_accumulate(Img im, LabSource src,
             }
         }
         if (slot >= 0) {
-            for (int q = 0; q < 6; ++q) atomicAdd(&bins[slot][q], v[q]);
+            for (int q = 0; q < 6; ++q) atomicAdd(&bins[slot * 6 + q][cp], v[q]);
         } else {
             for (int q = 0; q < 6; ++q)
                 atomicAdd((unsigned long long*)(acc + kAccStride * (long long)(im.sp + k) + q), v[q]);
@@ -537,9 +515,13 @@ __global__ __launch_bounds__(WG) void k_accumulate(Img im, LabSource src,
     for (int t = tid; t < kAccSlots * 6; t += WG) {
         const int slot = t / 6, q = t - 6 * (t / 6);
         const int k = keys[slot];
-        if (k >= 0 && bins[slot][0] != 0ULL)
-            atomicAdd((unsigned long long*)(acc + kAccStride * (long long)(im.sp + k) + q),
-                      bins[slot][q]);
+        unsigned long long n = 0, v = 0;
+        for (int c = 0; c < kBinCopies; ++c) {
+            n += bins[slot * 6][c];
+            v += bins[t][c];
+        }
+        if (k >= 0 && n != 0ULL)
+            atomicAdd((unsigned long long*)(acc + kAccStride * (long long)(im.sp + k) + q), v);
     }
 }
 

@@ -36,6 +36,7 @@ using namespace dev;
 
 struct SoftImg {
     int W, H, nx, ny, K, B;
+    int spl;    // work items (slices) per cell of the path kernels
     long long N;
     float spw, gamma, lambda, inv_t;
     double temp;
@@ -143,12 +144,14 @@ __global__ __launch_bounds__(WG) void k_soft_init(SoftImg s, const float4* __res
     if (tid < 5) theta0[(5LL * b) * s.K + 5LL * k + tid] = (float)(red[tid][0] / red[5][0]);
 }
 
-// One workgroup per (image, cell).  As in the hard assignment, candidates are
+// One workgroup per (image, cell, slice) work item, one pixel per lane, as
+// in the hard assignment: a cell with more pixels than the workgroup has
+// lanes is cut into spl slices of whole 64-pixel chunks.  Candidates are
 // taken one at a time: the workgroup writes a table of (d_c(q, k), w_q) over
-// the rectangle spanned by the cell and the candidate's endpoint (two tables
-// alternate, one barrier per candidate), and every lane walks its pixels'
-// paths over it, two adds per sample; a rectangle beyond the budget walks
-// from global memory.  Same FP32 operations, same order.
+// the rectangle spanned by the item's pixels and the candidate's endpoint
+// (two tables alternate, one barrier per candidate), and every lane walks
+// its pixel's path over it, two adds per sample; a rectangle beyond the
+// budget walks from global memory.  Same FP32 operations, same order.
 template <int WG>
 __global__ __launch_bounds__(WG) void k_soft_assign(SoftImg s, const float4* __restrict__ packed,
                                                     const float* __restrict__ theta_prev,
@@ -158,30 +161,44 @@ __global__ __launch_bounds__(WG) void k_soft_assign(SoftImg s, const float4* __r
     float2* tabs = reinterpret_cast<float2*>(lds_dyn);          // two tables of cap entries
     __shared__ SoftShared sh;
     const int item = xcd_remap(blockIdx.x, gridDim.x);
-    const int b = item / s.K, cell = item - b * s.K;
+    const int bc = item / s.spl, slice = item - bc * s.spl;
+    const int b = bc / s.K, cell = bc - b * s.K;
     const int tid = threadIdx.x;
     const int W = s.W, H = s.H;
     const int ci = cell / s.nx, cj = cell - ci * s.nx;
     const int x0 = cell_lo(cj, W, s.nx), x1 = cell_lo(cj + 1, W, s.nx);
     const int y0 = cell_lo(ci, H, s.ny), y1 = cell_lo(ci + 1, H, s.ny);
+    const int cw = x1 - x0, ch = y1 - y0, P = cw * ch;
+    const int chunks = (P + 63) >> 6;
+    const int t0 = 64 * (int)((long long)chunks * slice / s.spl);
+    const int t1 = min(P, 64 * (int)((long long)chunks * (slice + 1) / s.spl));
+    if (t1 <= t0) return;                                       // uniform: an empty slice
+    // columns of the item's pixels: the 8-column strips its range touches
+    int ix0 = x0, ix1 = x1;
+    if (s.spl > 1) {
+        ix0 = x0 + 8 * strip_of(t0, cw, ch);
+        ix1 = min(x1, x0 + 8 * strip_of(t1 - 1, cw, ch) + 8);
+    }
     const float4* __restrict__ img = packed + (long long)b * s.N;
     load_candidates(s, ci, cj, theta_prev + 5LL * s.K * b, img, sh);
+    const bool mine = tid < t1 - t0;
+    int x = 0, y = 0;
+    if (mine) {
+        cell_pixel(t0 + tid, cw, ch, x, y);
+        x += x0;
+        y += y0;
+    }
+    const int p = y * W + x;
     __syncthreads();
-    const int cw = x1 - x0, ch = y1 - y0, P = cw * ch;
-    const int lane = tid & 63, wave = tid >> 6;
     const float lambda = s.lambda, oml = 1.0f - lambda;
-    const long long base = 9LL * s.N * b;
+    const long long base = 9LL * s.N * b + p;
     int buf = 0;
 #pragma unroll 1
     for (int j = 0; j < 9; ++j) {
         const int k = sh.cand[j].k;
+        const long long o = base + (long long)j * s.N;
         if (k < 0) {                                            // uniform
-            for (int chunk = wave; chunk * 64 < P; chunk += WG / 64) {
-                const int t = chunk * 64 + lane;
-                if (t >= P) continue;
-                int x, y;
-                cell_pixel(t, cw, ch, x, y);
-                const long long o = base + (long long)j * s.N + (long long)(y + y0) * W + x + x0;
+            if (mine) {
                 fa[o] = 0.0f;
                 fb[o] = 0.0f;
             }
@@ -189,68 +206,53 @@ __global__ __launch_bounds__(WG) void k_soft_assign(SoftImg s, const float4* __r
         }
         const float l = sh.cand[j].l, a = sh.cand[j].a, bb = sh.cand[j].b;
         const int cx = sh.cand[j].cx, cy = sh.cand[j].cy;
-        const int tx0 = min(x0, cx), ty0 = min(y0, cy);
-        const int rwid = max(x1, cx + 1) - tx0, th = max(y1, cy + 1) - ty0;
+        const int tx0 = min(ix0, cx), ty0 = min(y0, cy);
+        const int rwid = max(ix1, cx + 1) - tx0, th = max(y1, cy + 1) - ty0;
         const int tw = rwid + (24 - rwid % 16) % 16;            // pitch: 8 (mod 16) entries
         const bool staged = (long long)tw * th <= cap;
         float2* tab = tabs + (buf ? cap : 0);
         if (staged) {                                           // uniform
-            const int area = tw * th;
-            for (int e = tid; e < area; e += WG) {
-                const int r = e / tw;
-                const int c = e - r * tw;
-                const float4 f = img[(long long)(ty0 + r) * W + min(tx0 + c, W - 1)];
-                tab[e] = make_float2(colour_dist(f, l, a, bb), f.w);
-            }
+            fill_table<WG>(tab, img, W, tx0, ty0, tw, tw * th, l, a, bb);
             __syncthreads();
             buf ^= 1;
         }
+        if (!mine) continue;
         const float dcc = sh.cand[j].dcc, wc = sh.cand[j].wc;
         const float ccx = sh.cand[j].x, ccy = sh.cand[j].y;
-        for (int chunk = wave; chunk * 64 < P; chunk += WG / 64) {
-            const int t = chunk * 64 + lane;
-            if (t >= P) continue;
-            int x, y;
-            cell_pixel(t, cw, ch, x, y);
-            x += x0;
-            y += y0;
-            const int p = y * W + x;
-            const int dx = cx - x, dy = cy - y;
-            const int adx = dx < 0 ? -dx : dx, ady = dy < 0 ? -dy : dy;
-            const int n = adx > ady ? adx : ady;
-            const double inv = path_recip(n);
-            float dcp, sc, sw;
-            if (staged) {
-                const int lidx = (y - ty0) * tw + (x - tx0);
-                const float2 e0 = tab[lidx];
-                dcp = e0.x;
-                sc = dcp;
-                sw = e0.y;
-                walk_table(tab, lidx, tw, dx, dy, sc, sw);
-            } else {
-                const float4 fp = img[p];
-                dcp = colour_dist(fp, l, a, bb);
-                sc = dcp;
-                sw = fp.w;
-                walk_path(img, p, 1, W, dx, dy, l, a, bb, sc, sw);
-            }
-            if (n > 0) {
-                sc = sc + dcc;
-                sw = sw + wc;
-            }
-            float qc, qw;
-            div_path_len(sc, sw, n, inv, qc, qw);
-            const float A = lambda * dcp + oml * qc;
-            const float Bw = 1.0f + s.gamma * qw;
-            const float ex = (float)x - ccx, ey = (float)y - ccy;
-            const float D = A * Bw + (ex * ex + ey * ey) * s.spw;
-            // D goes to the Q buffer (k_soft_softmax turns it into Q); A and B
-            // go straight to the saved factors
-            const long long o = base + (long long)j * s.N + p;
-            q[o] = D;
-            fa[o] = A;
-            fb[o] = Bw;
+        const int dx = cx - x, dy = cy - y;
+        const int adx = dx < 0 ? -dx : dx, ady = dy < 0 ? -dy : dy;
+        const int n = adx > ady ? adx : ady;
+        const double inv = path_recip(n);
+        float dcp, sc, sw;
+        if (staged) {
+            const int lidx = (y - ty0) * tw + (x - tx0);
+            const float2 e0 = tab[lidx];
+            dcp = e0.x;
+            sc = dcp;
+            sw = e0.y;
+            walk_table(tab, lidx, tw, dx, dy, sc, sw);
+        } else {
+            const float4 fp = img[p];
+            dcp = colour_dist(fp, l, a, bb);
+            sc = dcp;
+            sw = fp.w;
+            walk_path(img, p, 1, W, dx, dy, l, a, bb, sc, sw);
         }
+        if (n > 0) {
+            sc = sc + dcc;
+            sw = sw + wc;
+        }
+        float qc, qw;
+        div_path_len(sc, sw, n, inv, qc, qw);
+        const float A = lambda * dcp + oml * qc;
+        const float Bw = 1.0f + s.gamma * qw;
+        const float ex = (float)x - ccx, ey = (float)y - ccy;
+        const float D = A * Bw + (ex * ex + ey * ey) * s.spw;
+        // D goes to the Q buffer (k_soft_softmax turns it into Q); A and B
+        // go straight to the saved factors
+        q[o] = D;
+        fa[o] = A;
+        fb[o] = Bw;
     }
 }
 
@@ -532,24 +534,39 @@ __global__ __launch_bounds__(WG) void k_soft_bwd_path(SoftImg s, const float4* _
                     atomicAdd(&accx[li], lf * dl);
                     atomicAdd(&accy[li], lf * da);
                     atomicAdd(&accz[li], lf * db);
-                    for (int i = 0; i < n; ++i) {
-                        if (i > 0) {
-                            rem += inc;
-                            const bool st = rem >= two_n;
-                            rem -= st ? two_n : 0;
-                            li += st ? sdiag : smaj;
-                            gi += st ? gdiag : gmaj;
+                    // four samples per trip: the texel loads of a trip are all
+                    // issued before the first is used
+                    for (int i0 = 0; i0 < n; i0 += 4) {
+                        int lis[4];
+                        float4 fq[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            if (i0 + u < n) {
+                                if (i0 + u > 0) {
+                                    rem += inc;
+                                    const bool st = rem >= two_n;
+                                    rem -= st ? two_n : 0;
+                                    li += st ? sdiag : smaj;
+                                    gi += st ? gdiag : gmaj;
+                                }
+                                lis[u] = li;
+                                fq[u] = img[gi];
+                            }
                         }
-                        const float4 fq = img[gi];
-                        const float el = cf * (fq.x - c.l), ea = cf * (fq.y - c.a),
-                                    eb = cf * (fq.z - c.b);
-                        atomicAdd(&accx[li], el);
-                        atomicAdd(&accy[li], ea);
-                        atomicAdd(&accz[li], eb);
-                        atomicAdd(&accw[li], cw_);
-                        gk[0] -= el;
-                        gk[1] -= ea;
-                        gk[2] -= eb;
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            if (i0 + u < n) {
+                                const float el = cf * (fq[u].x - c.l), ea = cf * (fq[u].y - c.a),
+                                            eb = cf * (fq[u].z - c.b);
+                                atomicAdd(&accx[lis[u]], el);
+                                atomicAdd(&accy[lis[u]], ea);
+                                atomicAdd(&accz[lis[u]], eb);
+                                atomicAdd(&accw[lis[u]], cw_);
+                                gk[0] -= el;
+                                gk[1] -= ea;
+                                gk[2] -= eb;
+                            }
+                        }
                     }
                     cf_end = cf;
                     cw_end = cw_;
@@ -581,20 +598,17 @@ __global__ __launch_bounds__(WG) void k_soft_bwd_path(SoftImg s, const float4* _
                     }
                 }
             }
-            // one butterfly for the seven wave sums: each step issues seven
-            // independent shuffles
+            // seven wave sums by DPP, interleaved so that each step issues
+            // seven independent instructions; the totals land in lane 63
             float red[7] = {gk[0], gk[1], gk[2], gk[3], gk[4], cf_end, cw_end};
 #pragma unroll
-            for (int o = 32; o > 0; o >>= 1) {
-#pragma unroll
-                for (int v = 0; v < 7; ++v) red[v] += __shfl_xor(red[v], o, 64);
-            }
+            for (int v = 0; v < 7; ++v) red[v] = wave_sum_last(red[v]);
 #pragma unroll
             for (int v = 0; v < 5; ++v) gk[v] = red[v];
             if (c.staged) {                                     // uniform
                 // the endpoint: (sum cf) (f_c - f_k) and sum dL/dw
                 const float se = red[5], swe = red[6];
-                if (lane == 0 && (se != 0.0f || swe != 0.0f)) {
+                if (lane == 63 && (se != 0.0f || swe != 0.0f)) {
                     const int lic = (c.cy - ry0) * rw + (c.cx - rx0);
                     const float4 fc = img[(long long)c.cy * W + c.cx];
                     const float el = se * (fc.x - c.l), ea = se * (fc.y - c.a),
@@ -608,7 +622,7 @@ __global__ __launch_bounds__(WG) void k_soft_bwd_path(SoftImg s, const float4* _
                     gk[2] -= eb;
                 }
             }
-            if (lane == 0)
+            if (lane == 63)
                 for (int v = 0; v < 5; ++v)
                     if (gk[v] != 0.0f) atomicAdd(&sh.bins[j][v], gk[v]);
         }
@@ -688,10 +702,17 @@ static dim3 pixel_grid(const SoftImg& s) {
     return dim3((unsigned)bx, (unsigned)std::min(by, 65535), (unsigned)s.B);
 }
 
+int soft_slices(int W, int H, int nx, int ny, int wg) {
+    const long long cw = (W + nx - 1) / nx, ch = (H + ny - 1) / ny;
+    const long long chunks = (cw * ch + 63) / 64, per = wg / 64;
+    return (int)std::max<long long>(1, (chunks + per - 1) / per);
+}
+
 static SoftImg to_img(const SoftGeom& g) {
     SoftImg s;
     s.W = g.W; s.H = g.H; s.nx = g.nx; s.ny = g.ny; s.K = g.nx * g.ny; s.B = g.B;
     s.N = (long long)g.W * g.H;
+    s.spl = soft_slices(g.W, g.H, g.nx, g.ny, g.wg);
     s.spw = g.spw; s.gamma = g.gamma; s.lambda = g.lambda; s.inv_t = 1.0f / g.temperature;
     s.temp = (double)g.temperature;
     return s;
@@ -719,7 +740,7 @@ int launch_soft_init(const SoftGeom& g, const float4* packed, float* theta0, hip
 template <int WG>
 static int soft_assign_t(const SoftImg& s, const float4* packed, const float* theta_prev, float* q,
                          float* fa, float* fb, int cap, hipStream_t st) {
-    hipLaunchKernelGGL(k_soft_assign<WG>, dim3(s.B * s.K), dim3(WG), (size_t)cap * sizeof(float4),
+    hipLaunchKernelGGL(k_soft_assign<WG>, dim3(s.B * s.K * s.spl), dim3(WG), (size_t)cap * sizeof(float4),
                        st, s, packed, theta_prev, q, fa, fb, cap);
     return hipGetLastError();
 }

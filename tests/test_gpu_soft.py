@@ -99,6 +99,21 @@ def test_soft_forward_matches_oracle(orc, W, H, k, B, T, iters, seed):
     assert np.allclose(q_t.sum(axis=2), 1.0, atol=1e-5)
 
 
+@pytest.mark.parametrize("wg", [256, 512, 1024])
+def test_soft_forward_sliced_cells(orc, wg):
+    """Cells of 32 x 40 = 1280 pixels exceed every workgroup size, so each is cut
+    into 5, 3 or 2 work items of whole 64-pixel chunks."""
+    W, H, k, B, T, iters, seed = 96, 80, 6, 2, 0.5, 2, 630
+    lab, con = _batch(B, (W, H), 8, seed)
+    th_o, q_o, z_o = orc.soft_forward(lab, con, k, iterations=iters, T=T, d32=True)
+    eng = _engine(W, H, k, B, T, iters, wg_size=wg)
+    assert (eng.grid.nx, eng.grid.ny) == (3, 2)
+    say("soft forward sliced", wg)
+    c_t, q_t, saved = eng.forward(dev(lab), dev(con))
+    c_t, q_t = host(c_t), host(q_t)
+    assert compare_forward(c_t, q_t, th_o, q_o, W, H) == iters
+
+
 @pytest.mark.parametrize("W,H,k,B,T,iters,seed", CASES)
 def test_soft_backward_matches_oracle(orc, W, H, k, B, T, iters, seed):
     lab, con = _batch(B, (W, H), 8, seed)
