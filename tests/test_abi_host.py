@@ -119,6 +119,12 @@ def test_mode_parameters_are_validated_on_host():
     for batch in (0, 65536):
         assert lib.scalp_soft_forward(ctypes.byref(g), ctypes.byref(p), ctypes.c_float(0.5), batch,
                                       fake, fake, fake, fake, fake, fake, sw, None) == L.SCALP_ERR_ARG
+    # 200 images of 8192 x 8192 with 2x2-pixel cells: 200 * 2^24 work items
+    # do not fit a 32-bit grid (while 200 * 2^26 pixels are within the pixel limit)
+    big = L.make_grid(8192, 8192, 8192 * 8192 // 4)
+    assert big.num_sp == 4096 * 4096
+    assert lib.scalp_soft_forward(ctypes.byref(big), ctypes.byref(p), ctypes.c_float(0.5), 200,
+                                  fake, fake, fake, fake, fake, fake, 1 << 62, None) == L.SCALP_ERR_ARG
     with pytest.raises(TypeError):
         L.default_params(not_a_parameter=1)
 
