@@ -226,10 +226,23 @@ def cpu_baseline(img, k, iters):
         # a bounded sample: at least 10 s of CPU work, at most 12 full runs
         if el >= 10.0 or reps >= 12:
             break
-    return {"value": round(W * H * iters * reps / el / 1e6, 3), "unit": "Mpixel-iter/s",
-            "cores": threads, "kind": "oracle",
-            "sample": f"{reps} full run(s) of {W}x{H} k={k}, {iters} iterations, "
-                      f"{el:.1f} s on {threads} OpenMP threads"}
+    out = {"value": round(W * H * iters * reps / el / 1e6, 3), "unit": "Mpixel-iter/s",
+           "cores": threads, "kind": "oracle",
+           "sample": f"{reps} full run(s) of {W}x{H} k={k}, {iters} iterations, "
+                     f"{el:.1f} s on {threads} OpenMP threads"}
+    # the same oracle on one thread, over a shorter run of the same workload
+    # (the iterations cost about the same, so the rate per pixel-iteration carries over)
+    it1 = 2
+    orc.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        orc.run(img.lab, img.contour, k, iterations=it1)
+        el1 = time.perf_counter() - t0
+    finally:
+        orc.set_threads(threads)
+    out["one_thread"] = {"value": round(W * H * it1 / el1 / 1e6, 3), "unit": "Mpixel-iter/s",
+                         "sample": f"1 run of {W}x{H} k={k}, {it1} iterations, {el1:.1f} s on 1 thread"}
+    return out
 
 
 def bench_batched(torch, args, tuned):
