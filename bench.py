@@ -3,13 +3,15 @@
 
 Headline: Mpixel-iterations/s of hard SCALP on the 1920x1080 synthetic
 Voronoi workload with k = 2000 and 10 iterations.  One step is one whole job
-from inputs resident in HBM: pack (l, a, b, w), grid initialisation, then
-10 x (fused assignment + update, finalize + Eq. (4) projection).
+from inputs resident in HBM: pack (l, a, b, w) and grid initialisation
+(eager), then 10 x (fused assignment + update, finalize + Eq. (4)
+projection) as one hipGraph replay.
 
 Also reported on the same JSON line:
   roofline      the fused assignment kernel (the dominant kernel): algorithmic
                 FP32 operations per launch / its average duration, measured with
-                HIP events around every launch inside the timed region, against
+                HIP events around every launch in a second loop of the same
+                steps launched kernel by kernel (eager_ms_per_step), against
                 the FP32 VALU issue peak for non-fused, non-packed operations;
   cpu_baseline  the plain C oracle timed on this host's cores on the same
                 workload;
@@ -135,6 +137,30 @@ def bench_hard(torch, args):
         s.finalize(l, c, e, n)
     torch.cuda.synchronize()
 
+    # the timed region: the 10 iterations as one hipGraph replay (the
+    # iteration driver), each step preceded by the eager pack + grid init
+    gr = s.graph(c, e, l, n)
+    for _ in range(args.warmup):
+        s.init_grid(lab, con, out=(c, e, l))
+        gr.launch()
+    torch.cuda.synchronize()
+    g0 = torch.cuda.Event(enable_timing=True)
+    g1 = torch.cuda.Event(enable_timing=True)
+    wall0 = time.perf_counter()
+    g0.record()
+    for _ in range(args.steps):
+        s.init_grid(lab, con, out=(c, e, l))
+        gr.launch()
+    g1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms_step = g0.elapsed_time(g1) / args.steps
+    gr.close()
+
+    # the same steps launched one kernel at a time, with HIP events around
+    # every assignment launch on the stream it runs on: the kernel's own
+    # duration (the events add a little time between launches, so this
+    # loop's step time is reported separately, not as the value)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -143,33 +169,14 @@ def bench_hard(torch, args):
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
-    wall0 = time.perf_counter()
     t_start.record()
     for k in range(args.steps):
         step(evs[k])
     t_end.record()
     torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    ms_step = t_start.elapsed_time(t_end) / args.steps
+    eager_ms = t_start.elapsed_time(t_end) / args.steps
     per_it = [sum(evs[k][it][0].elapsed_time(evs[k][it][1]) for k in range(args.steps)) / args.steps
               for it in range(iters)]
-
-    # the same loop as one hipGraph replay after an eager init
-    gr = s.graph(c, e, l, n)
-    for _ in range(args.warmup):
-        s.init_grid(lab, con, out=(c, e, l))
-        gr.launch()
-    torch.cuda.synchronize()
-    g0 = torch.cuda.Event(enable_timing=True)
-    g1 = torch.cuda.Event(enable_timing=True)
-    g0.record()
-    for _ in range(args.steps):
-        s.init_grid(lab, con, out=(c, e, l))
-        gr.launch()
-    g1.record()
-    torch.cuda.synchronize()
-    graph_ms = g0.elapsed_time(g1) / args.steps
-    gr.close()
 
     N = W * H
     value = N * iters / (ms_step * 1e-3) / 1e6
@@ -195,7 +202,7 @@ def bench_hard(torch, args):
         "lds_peak_TBps": round(LDS_PEAK_TBPS, 1),
         "kernel_source_sha256_16": digest,
     }
-    log(f"hard: {ms_step:.3f} ms/step eager, {graph_ms:.3f} ms/step graph, wall {wall:.2f}s")
+    log(f"hard: {ms_step:.3f} ms/step graph, {eager_ms:.3f} ms/step eager with events, wall {wall:.2f}s")
     if args.copy_probe:
         src = torch.empty(512 * 2**20, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
@@ -204,11 +211,12 @@ def bench_hard(torch, args):
         torch.cuda.synchronize()
         log("copy probe: 3 x 512 MiB device copies")
     return img, tuned, {
-        "value": value, "ms_per_step": ms_step, "graph_ms_per_step": graph_ms,
-        "graph_value": N * iters / (graph_ms * 1e-3) / 1e6, "roofline": roofline,
+        "value": value, "ms_per_step": ms_step, "eager_ms_per_step": eager_ms,
+        "eager_value": N * iters / (eager_ms * 1e-3) / 1e6, "roofline": roofline,
         "config": {"workload": wl.name, "width": W, "height": H, "k": wl.k,
                    "num_sp": s.grid.num_sp, "iterations": iters, "launch": tuned,
-                   "step": "pack + grid init + 10 x (fused assign/update, finalize/projection)"},
+                   "step": "pack + grid init (eager) + 10 x (fused assign/update, finalize/projection) "
+                           "as one hipGraph replay"},
     }
 
 
@@ -512,8 +520,8 @@ def main():
         "ms_per_step": round(hard["ms_per_step"], 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": hard["config"], "roofline": hard["roofline"],
-        "graph_ms_per_step": round(hard["graph_ms_per_step"], 4),
-        "graph_value": round(hard["graph_value"], 1),
+        "eager_ms_per_step": round(hard["eager_ms_per_step"], 4),
+        "eager_value": round(hard["eager_value"], 1),
     }
     if not args.no_extensions:
         runs = [("batched", lambda: bench_batched(torch, args, tuned)),
