@@ -216,10 +216,11 @@ size_t scalp_batch_workspace_bytes(const scalp_batch_desc_t* descs, int32_t n_im
 
 /* Algorithm 1 on every image of the batch: prepare, init and
  * p->iterations x (assign + update, projection), each iteration one
- * persistent launch over a work queue of (image, cell) items.  Results are
- * identical to scalp_run on each image alone.  descs: host array; all other
- * arrays are device arrays concatenated as described above.  gamma < 0
- * selects 2r per image. */
+ * persistent launch over a work queue of (image, cell, slice) items (a
+ * cell larger than the workgroup is cut into slices of whole 64-pixel
+ * chunks).  Results are identical to scalp_run on each image alone.
+ * descs: host array; all other arrays are device arrays concatenated as
+ * described above.  gamma < 0 selects 2r per image. */
 int scalp_run_batched(const scalp_batch_desc_t* descs, int32_t n_images, const scalp_params_t* p,
                       const float* lab, const float* contour, float* centers,
                       int32_t* endpoints, int32_t* labels, int32_t* counts, void* workspace,

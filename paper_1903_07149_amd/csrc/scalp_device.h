@@ -8,9 +8,19 @@ namespace dev {
 
 // First coordinate of grid cell `idx` of `n` along an axis of `len` pixels:
 // pixel c is in cell floor(c * n / len), i.e. cell idx starts at
-// ceil(idx * len / n).
+// ceil(idx * len / n).  With n <= len < 2^16 every product fits 32 bits and
+// the division is a 32-bit one (len and n are uniform, so is the branch).
 __device__ __forceinline__ int cell_lo(int idx, int len, int n) {
+    if (len < 65536)
+        return (int)(((unsigned)idx * (unsigned)len + (unsigned)(n - 1)) / (unsigned)n);
     return (int)(((long long)idx * len + n - 1) / n);
+}
+
+// Grid cell of coordinate c along an axis of `len` pixels cut into n cells:
+// floor(c * n / len), in 32 bits when len < 2^16.
+__device__ __forceinline__ int cell_of(int c, int n, int len) {
+    if (len < 65536) return (int)(((unsigned)c * (unsigned)n) / (unsigned)len);
+    return (int)(((long long)c * n) / len);
 }
 
 __device__ __forceinline__ float colour_dist(float4 f, float l, float a, float b) {

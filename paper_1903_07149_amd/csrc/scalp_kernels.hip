@@ -4,17 +4,19 @@
 //                     summand of Eq. (2), evaluated in FP64 and rounded once.
 //   k_init_cells      Algorithm 1 initialisation: labels = grid cell, per-cell
 //                     integer sums (Sec. II-A regular grid).
-//   k_assign*         Algorithm 1 assignment: one workgroup per grid cell.  The
-//                     rectangle of the packed image that the cell's paths can
-//                     reach (the cell plus its <= 9 candidates' endpoints) is
-//                     staged in LDS; every lane walks the Bresenham path
-//                     (Sec. II-B) from its pixel to each candidate's endpoint,
-//                     accumulating Eq. (1)'s colour term and Eq. (2)'s contour
-//                     term in a fixed FP32 order, forms D of Eq. (3) and keeps
-//                     the first strict minimum.  With ACCUM the update's sums
-//                     are fused in: each pixel can only choose among the cell's
-//                     9 candidates, so they reduce into 9 LDS bins and leave
-//                     the workgroup as 54 integer atomics.
+//   k_assign*         Algorithm 1 assignment: one workgroup per (cell, slice)
+//                     work item, one pixel per lane.  For each of the <= 9
+//                     candidates in turn the workgroup writes an LDS table of
+//                     (colour distance, w) over the rectangle of the item and
+//                     the candidate's endpoint; every lane then walks the
+//                     discrete line (Sec. II-B) from its pixel to the endpoint
+//                     over the table, accumulating Eq. (1)'s colour term and
+//                     Eq. (2)'s contour term in a fixed FP32 order, forms D of
+//                     Eq. (3) and keeps the first strict minimum.  With ACCUM
+//                     the update's sums are fused in: each pixel can only
+//                     choose among the cell's 9 candidates, so they reduce
+//                     into 9 LDS bins and leave the workgroup as at most 54
+//                     integer atomics.
 //   k_finalize*       Algorithm 1 update: means from the integer sums, the
 //                     rounded barycenter, and the membership test of the
 //                     Sec. II-D Remark; clusters that fail it are queued.

@@ -78,7 +78,11 @@ __global__ __launch_bounds__(256) void k_gradient_max(const float* __restrict__ 
                                                                        : red[threadIdx.x + h];
         __syncthreads();
     }
-    if (threadIdx.x == 0) atomicMax(mx, red[0]);
+    // most blocks find a maximum below what an earlier block has stored:
+    // only a larger value goes to the atomic (a stale read only costs an
+    // atomic that changes nothing)
+    if (threadIdx.x == 0 && red[0] > *reinterpret_cast<volatile unsigned long long*>(mx))
+        atomicMax(mx, red[0]);
 }
 
 // Contour value of pixel p as the standalone map stores it (FP32).

@@ -8,10 +8,10 @@
 // membership); the rounding is piecewise constant, so it carries no gradient.
 //
 // Forward, per iteration:
-//   k_soft_assign  workgroup per (image, cell): per-candidate LDS tables of
-//                  (colour distance, w) and per-lane path walks as in the
-//                  hard kernel; writes D and the factors A (Eq. (1)) and
-//                  B (Eq. (2)).
+//   k_soft_assign  workgroup per (image, cell, slice), one pixel per lane:
+//                  per-candidate LDS tables of (colour distance, w) and
+//                  per-lane path walks as in the hard kernel; writes D and
+//                  the factors A (Eq. (1)) and B (Eq. (2)).
 //   k_soft_softmax FP64 softmax of -D/T over the 9 slots, written as Q.
 //   k_soft_update  workgroup per (image, superpixel): gathers Q over the 3x3
 //                  cell block in a fixed order (FP64 partial sums, tree
@@ -272,7 +272,7 @@ __global__ __launch_bounds__(WG) void k_soft_assign(SoftImg s, const float4* __r
 __global__ __launch_bounds__(256) void k_soft_softmax(SoftImg s, float* __restrict__ q) {
     SOFT_FOR_PIXELS(s) {
         const long long p = (long long)y * s.W + x;
-        const int ci = (int)(((long long)y * s.ny) / s.H), cj = (int)(((long long)x * s.nx) / s.W);
+        const int ci = cell_of(y, s.ny, s.H), cj = cell_of(x, s.nx, s.W);
         const long long base = 9LL * s.N * b + p;
         float D[9];
         bool ok[9];
@@ -331,9 +331,15 @@ __global__ __launch_bounds__(WG) void k_soft_update(SoftImg s, const float* __re
     const int yb1 = cell_lo(ci, s.H, s.ny), yb2 = cell_lo(ci + 1, s.H, s.ny);
     const int xb1 = cell_lo(cj, s.W, s.nx), xb2 = cell_lo(cj + 1, s.W, s.nx);
     double acc[6] = {0, 0, 0, 0, 0, 0};
+    // element e = r * bw + c; lanes step by WG elements = (dr rows, dc columns)
+    const int dr = WG / bw, dc = WG - dr * bw;
+    int r = tid / bw, c = tid - r * bw;
     for (int e = tid; e < area; e += WG) {
-        const int r = e / bw;
-        const int x = X0 + (e - r * bw), y = Y0 + r;
+        const int x = X0 + c, y = Y0 + r;
+        c += dc;
+        const bool wrap = c >= bw;
+        c -= wrap ? bw : 0;
+        r += dr + (wrap ? 1 : 0);
         const int di = (y >= yb1 ? 1 : 0) + (y >= yb2 ? 1 : 0);
         const int dj = (x >= xb1 ? 1 : 0) + (x >= xb2 ? 1 : 0);
         const int j = (2 - di) * 3 + (2 - dj);      // the pixel's slot that points at k
@@ -371,7 +377,7 @@ __global__ __launch_bounds__(256) void k_soft_bwd_update(SoftImg s, int first,
     SOFT_FOR_PIXELS(s) {
         const long long p = (long long)y * s.W + x;
         const long long i = (long long)b * s.N + p;
-        const int ci = (int)(((long long)y * s.ny) / s.H), cj = (int)(((long long)x * s.nx) / s.W);
+        const int ci = cell_of(y, s.ny, s.H), cj = cell_of(x, s.nx, s.W);
         const float4 f = packed[i];
         const float feat[5] = {f.x, f.y, f.z, (float)x, (float)y};
         const long long qb = 9LL * s.N * b + p;
@@ -659,7 +665,7 @@ __global__ __launch_bounds__(256) void k_soft_bwd_finish(SoftImg s, const float4
     SOFT_FOR_PIXELS(s) {
         const long long p = (long long)y * s.W + x;
         const long long i = (long long)b * s.N + p;
-        const int ci = (int)(((long long)y * s.ny) / s.H), cj = (int)(((long long)x * s.nx) / s.W);
+        const int ci = cell_of(y, s.ny, s.H), cj = cell_of(x, s.nx, s.W);
         const int cnt = (cell_lo(cj + 1, s.W, s.nx) - cell_lo(cj, s.W, s.nx)) *
                         (cell_lo(ci + 1, s.H, s.ny) - cell_lo(ci, s.H, s.ny));
         const float* g0 = gth0 + 5LL * s.K * b + 5LL * (ci * s.nx + cj);
