@@ -210,6 +210,13 @@ def test_run_bit_exact_small(orc, W, H, k):
     _compare_runs(orc, _image(W, H, 7), k, 10)
 
 
+@pytest.mark.parametrize("W,H,k", [(70000, 3, 60), (3, 66000, 40)])
+def test_run_bit_exact_wide_axis(orc, W, H, k):
+    """An axis of 2^16 pixels or more takes the 64-bit branch of the cell
+    arithmetic (below that, every product fits 32 bits)."""
+    _compare_runs(orc, _image(W, H, 17, regions=40), k, 4)
+
+
 def test_run_bsd_shape_workload(orc):
     _compare_runs(orc, synth.workload_image(synth.BSD_SHAPE), 250, 10)
 

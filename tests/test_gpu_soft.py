@@ -114,6 +114,19 @@ def test_soft_forward_sliced_cells(orc, wg):
     assert compare_forward(c_t, q_t, th_o, q_o, W, H) == iters
 
 
+def test_soft_forward_wide_axis(orc):
+    """A 70000-pixel-wide image: the per-pixel soft kernels find their cell with
+    the 64-bit branch of the cell arithmetic."""
+    W, H, k, B, T, iters, seed = 70000, 2, 40, 1, 5.0, 2, 640
+    lab, con = _batch(B, (W, H), 40, seed)
+    th_o, q_o, z_o = orc.soft_forward(lab, con, k, iterations=iters, T=T, d32=True)
+    eng = _engine(W, H, k, B, T, iters)
+    say("soft forward wide", W, H, k)
+    c_t, q_t, saved = eng.forward(dev(lab), dev(con))
+    c_t, q_t = host(c_t), host(q_t)
+    assert compare_forward(c_t, q_t, th_o, q_o, W, H) == iters
+
+
 @pytest.mark.parametrize("W,H,k,B,T,iters,seed", CASES)
 def test_soft_backward_matches_oracle(orc, W, H, k, B, T, iters, seed):
     lab, con = _batch(B, (W, H), 8, seed)
