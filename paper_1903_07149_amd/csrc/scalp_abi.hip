@@ -572,8 +572,9 @@ SoftSaved soft_saved_layout(const scalp_grid_t* g, long long B, long long T) {
 }
 
 // workspace: [packed B*N float4][gd B*9*N][gf B*N float4][gth 2 x B*K*5]
+// [cand B*K*2 float4]
 struct SoftWs {
-    size_t packed, gd, gf, gth0, gth1, total;
+    size_t packed, gd, gf, gth0, gth1, cand, total;
 };
 
 SoftWs soft_ws_layout(const scalp_grid_t* g, long long B) {
@@ -584,7 +585,8 @@ SoftWs soft_ws_layout(const scalp_grid_t* g, long long B) {
     w.gf = w.gd + align_up((size_t)(B * 9 * N) * 4);
     w.gth0 = w.gf + align_up((size_t)(B * N) * 16);
     w.gth1 = w.gth0 + align_up((size_t)(B * K * 5) * 4);
-    w.total = w.gth1 + align_up((size_t)(B * K * 5) * 4);
+    w.cand = w.gth1 + align_up((size_t)(B * K * 5) * 4);
+    w.total = w.cand + align_up((size_t)(B * K * 2) * 16);
     return w;
 }
 
@@ -688,6 +690,7 @@ int scalp_soft_backward(const scalp_grid_t* g, const scalp_params_t* p, float te
     float* gd = reinterpret_cast<float*>(wb + W.gd);
     float4* gf = reinterpret_cast<float4*>(wb + W.gf);
     float* gth[2] = {reinterpret_cast<float*>(wb + W.gth0), reinterpret_cast<float*>(wb + W.gth1)};
+    float4* cand = reinterpret_cast<float4*>(wb + W.cand);
     const float* fa = reinterpret_cast<const float*>(sb + S.a);
     const float* fb = reinterpret_cast<const float*>(sb + S.bf);
     const double* z = reinterpret_cast<const double*>(sb + S.z);
@@ -701,7 +704,7 @@ int scalp_soft_backward(const scalp_grid_t* g, const scalp_params_t* p, float te
         const double* zt = z + (long long)t * B * K;
         CHECK_HIP(launch_soft_bwd_update(geo, t == T - 1, q_t + qo, zt,
                                          centers_t + (long long)(t + 1) * B * K * 5, packed,
-                                         gth[cur], grad_q, gd, gf, s));
+                                         gth[cur], grad_q, gd, gf, cand, s));
         CHECK_HIP(launch_soft_bwd_pass(geo, zt, gth[cur], gth[1 - cur], s));
         CHECK_HIP(launch_soft_bwd_path(geo, packed, centers_t + (long long)t * B * K * 5, fa + qo,
                                        fb + qo, gd, gf, gth[1 - cur], cap, s));

@@ -114,9 +114,11 @@ int launch_soft_assign(const SoftGeom& g, const float4* packed, const float* the
                        float* fa, float* fb, int cap, hipStream_t st);
 int launch_soft_update(const SoftGeom& g, const float* q, const float4* packed,
                        const float* theta_prev, float* theta_next, double* z, hipStream_t st);
+// cand: scratch of 2 * B * K float4 (per-superpixel terms of the update backward)
 int launch_soft_bwd_update(const SoftGeom& g, int first, const float* q, const double* z,
                            const float* theta, const float4* packed, const float* gth,
-                           const float* gq_in, float* gd, float4* gf, hipStream_t st);
+                           const float* gq_in, float* gd, float4* gf, float4* cand,
+                           hipStream_t st);
 int launch_soft_bwd_pass(const SoftGeom& g, const double* z, const float* gth, float* gth_prev,
                          hipStream_t st);
 int launch_soft_bwd_path(const SoftGeom& g, const float4* packed, const float* theta_prev,

@@ -363,14 +363,39 @@ __global__ __launch_bounds__(WG) void k_soft_update(SoftImg s, const float* __re
 
 // ------------------------------------------------------------------ backward
 
+// Per superpixel, what the soft-update backward needs of it, in two float4:
+// u = dL/dTheta_k / Z_k (5 values) and v = u . Theta_k, all zero when Z_k is
+// below kZMin (such a superpixel kept its centre and passes no gradient to
+// Q or f).
+__global__ void k_soft_bwd_cand(SoftImg s, const double* __restrict__ z,
+                                const float* __restrict__ theta, const float* __restrict__ gth,
+                                float4* __restrict__ cand) {
+    const long long total = (long long)s.B * s.K;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+         i += (long long)gridDim.x * blockDim.x) {
+        float u[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+        float v = 0.0f;
+        const double Zd = z[i];
+        if (Zd >= kZMin) {
+            const float Z = (float)Zd;
+            for (int c = 0; c < 5; ++c) {
+                u[c] = gth[5 * i + c] / Z;
+                v += u[c] * theta[5 * i + c];
+            }
+        }
+        cand[2 * i] = make_float4(u[0], u[1], u[2], u[3]);
+        cand[2 * i + 1] = make_float4(u[4], v, 0.0f, 0.0f);
+    }
+}
+
 // Soft-update backward (theta_t = sum Q feat / Z) and softmax backward:
 // gd[j] = dL/dD_pj (0 where Q_pj < kQMin).  gf += dL/df_p through the update.
+// With u, v of k_soft_bwd_cand: dL/dQ_pk += u . feat_p - v and
+// dL/df_p += Q_pk u[0..2].
 __global__ __launch_bounds__(256) void k_soft_bwd_update(SoftImg s, int first,
                                                          const float* __restrict__ q,
-                                                         const double* __restrict__ z,
-                                                         const float* __restrict__ theta,
+                                                         const float4* __restrict__ cand,
                                                          const float4* __restrict__ packed,
-                                                         const float* __restrict__ gth,
                                                          const float* __restrict__ gq_in,
                                                          float* __restrict__ gd,
                                                          float4* __restrict__ gf) {
@@ -379,8 +404,9 @@ __global__ __launch_bounds__(256) void k_soft_bwd_update(SoftImg s, int first,
         const long long i = (long long)b * s.N + p;
         const int ci = cell_of(y, s.ny, s.H), cj = cell_of(x, s.nx, s.W);
         const float4 f = packed[i];
-        const float feat[5] = {f.x, f.y, f.z, (float)x, (float)y};
+        const float fx = (float)x, fy = (float)y;
         const long long qb = 9LL * s.N * b + p;
+        const float4* cb = cand + 2LL * s.K * b;
         float Q[9], G[9];
         float gfl = 0.0f, gfa = 0.0f, gfb = 0.0f, dot = 0.0f;
 #pragma unroll
@@ -390,19 +416,11 @@ __global__ __launch_bounds__(256) void k_soft_bwd_update(SoftImg s, int first,
             G[j] = first ? gq_in[qb + (long long)j * s.N] : 0.0f;
             if (ii < 0 || ii >= s.ny || jj < 0 || jj >= s.nx) continue;
             const int k = ii * s.nx + jj;
-            const double Zd = z[(long long)s.K * b + k];
-            if (Zd >= kZMin) {
-                const float Z = (float)Zd;
-                const float* g = gth + 5LL * s.K * b + 5LL * k;
-                const float* th = theta + 5LL * s.K * b + 5LL * k;
-                float acc = 0.0f;
-                for (int c = 0; c < 5; ++c) acc += g[c] * (feat[c] - th[c]);
-                G[j] += acc / Z;
-                const float w = Q[j] / Z;
-                gfl += g[0] * w;
-                gfa += g[1] * w;
-                gfb += g[2] * w;
-            }
+            const float4 u = cb[2 * k], u4v = cb[2 * k + 1];
+            G[j] += (((u.x * f.x + u.y * f.y) + (u.z * f.z + u.w * fx)) + u4v.x * fy) - u4v.y;
+            gfl += u.x * Q[j];
+            gfa += u.y * Q[j];
+            gfb += u.z * Q[j];
             dot += Q[j] * G[j];
         }
         // A slot's whole path contribution is proportional to Q_pj; below
@@ -773,10 +791,13 @@ int launch_soft_update(const SoftGeom& g, const float* q, const float4* packed,
 
 int launch_soft_bwd_update(const SoftGeom& g, int first, const float* q, const double* z,
                            const float* theta, const float4* packed, const float* gth,
-                           const float* gq_in, float* gd, float4* gf, hipStream_t st) {
+                           const float* gq_in, float* gd, float4* gf, float4* cand,
+                           hipStream_t st) {
     const SoftImg s = to_img(g);
-    hipLaunchKernelGGL(k_soft_bwd_update, pixel_grid(s), dim3(256), 0, st, s, first, q,
-                       z, theta, packed, gth, gq_in, gd, gf);
+    hipLaunchKernelGGL(k_soft_bwd_cand, dim3(grid_for((long long)s.B * s.K)), dim3(256), 0, st, s,
+                       z, theta, gth, cand);
+    hipLaunchKernelGGL(k_soft_bwd_update, pixel_grid(s), dim3(256), 0, st, s, first, q, cand,
+                       packed, gq_in, gd, gf);
     return hipGetLastError();
 }
 
