@@ -334,24 +334,40 @@ __global__ __launch_bounds__(WG) void k_soft_update(SoftImg s, const float* __re
     // element e = r * bw + c; lanes step by WG elements = (dr rows, dc columns)
     const int dr = WG / bw, dc = WG - dr * bw;
     int r = tid / bw, c = tid - r * bw;
-    for (int e = tid; e < area; e += WG) {
-        const int x = X0 + c, y = Y0 + r;
-        c += dc;
-        const bool wrap = c >= bw;
-        c -= wrap ? bw : 0;
-        r += dr + (wrap ? 1 : 0);
-        const int di = (y >= yb1 ? 1 : 0) + (y >= yb2 ? 1 : 0);
-        const int dj = (x >= xb1 ? 1 : 0) + (x >= xb2 ? 1 : 0);
-        const int j = (2 - di) * 3 + (2 - dj);      // the pixel's slot that points at k
-        const long long p = (long long)y * s.W + x;
-        const double Q = qb[(long long)j * s.N + p];
-        const float4 f = img[p];
-        acc[0] += Q;
-        acc[1] += Q * f.x;
-        acc[2] += Q * f.y;
-        acc[3] += Q * f.z;
-        acc[4] += Q * x;
-        acc[5] += Q * y;
+    // kU elements per trip (e, e + WG, ...: the thread's order is unchanged),
+    // their Q loads issued first; a texel is read only where its Q is not 0
+    // (at low T most slots underflow to 0, and 0 * f adds exactly nothing)
+    constexpr int kU = 4;
+    for (int e = tid; e < area; e += kU * WG) {
+        int xs[kU], ys[kU];
+        long long ps[kU];
+        double Qs[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            xs[u] = X0 + c;
+            ys[u] = Y0 + r;
+            c += dc;
+            const bool wrap = c >= bw;
+            c -= wrap ? bw : 0;
+            r += dr + (wrap ? 1 : 0);
+            const int di = (ys[u] >= yb1 ? 1 : 0) + (ys[u] >= yb2 ? 1 : 0);
+            const int dj = (xs[u] >= xb1 ? 1 : 0) + (xs[u] >= xb2 ? 1 : 0);
+            const int j = (2 - di) * 3 + (2 - dj);  // the pixel's slot that points at k
+            ps[u] = (long long)ys[u] * s.W + xs[u];
+            Qs[u] = e + u * WG < area ? (double)qb[(long long)j * s.N + ps[u]] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            if (Qs[u] == 0.0) continue;
+            const double Q = Qs[u];
+            const float4 f = img[ps[u]];
+            acc[0] += Q;
+            acc[1] += Q * f.x;
+            acc[2] += Q * f.y;
+            acc[3] += Q * f.z;
+            acc[4] += Q * xs[u];
+            acc[5] += Q * ys[u];
+        }
     }
     block_sum6<WG>(acc, red);
     if (tid < 5) {
