@@ -284,14 +284,20 @@ __global__ __launch_bounds__(256) void k_soft_softmax(SoftImg s, float* __restri
             D[j] = ok[j] ? q[base + (long long)j * s.N] : INFINITY;
             dmin = fminf(dmin, D[j]);
         }
+        // a slot with (D - Dmin) / T > 110 has exp < 2^-158: added to the sum
+        // (at least 1, the minimum's term) it changes nothing in FP64, and its
+        // Q rounds to 0 in FP32, so neither the exponential nor the quotient
+        // is computed (same results, most slots at low T)
         double e[9], sum = 0.0;
 #pragma unroll
         for (int j = 0; j < 9; ++j) {
-            e[j] = ok[j] ? exp(-((double)D[j] - (double)dmin) / s.temp) : 0.0;
+            const double t = ((double)D[j] - (double)dmin) / s.temp;
+            e[j] = ok[j] && t <= 110.0 ? exp(-t) : 0.0;
             sum += e[j];
         }
 #pragma unroll
-        for (int j = 0; j < 9; ++j) q[base + (long long)j * s.N] = (float)(e[j] / sum);
+        for (int j = 0; j < 9; ++j)
+            q[base + (long long)j * s.N] = e[j] == 0.0 ? 0.0f : (float)(e[j] / sum);
     }
 }
 
