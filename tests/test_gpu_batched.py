@@ -62,3 +62,38 @@ def test_batched_graph_replays():
         for a, r in zip(got, ref):
             assert (a == r).all(), rep
     gr.close()
+
+
+@pytest.mark.timeout(400)   # generating the 64 images takes most of it
+def test_batched_full_size_workload(orc):
+    """The benchmark's batch (64 ragged images, 92 Mpx, k = HW/1000, 10 iterations)
+    in the launch shape the benchmark uses: every image equals the single-image
+    path bit for bit, and three sampled images (the smallest, a middle one and
+    the largest) equal the oracle."""
+    from paper_1903_07149_amd.scalp import Scalp, ScalpBatch
+    orc.set_threads(min(16, os.cpu_count() or 1))
+    wls = synth.batch_workloads()
+    assert len(wls) == 64
+    imgs = [synth.workload_image(w) for w in wls]
+    b = ScalpBatch([(w.width, w.height, w.k) for w in wls], iterations=10)
+    lab = dev(np.concatenate([i.lab.reshape(-1, 3) for i in imgs]))
+    con = dev(np.concatenate([i.contour.reshape(-1) for i in imgs]))
+    say("batched full size")
+    c, e, l, n = (host(t) for t in b.run(lab, con))
+    del lab, con
+    sizes = [w.width * w.height for w in wls]
+    order = np.argsort(sizes)
+    sampled = {int(order[0]), int(order[len(order) // 2]), int(order[-1])}
+    slices = list(zip(b.pixel_slices(), b.sp_slices()))
+    for i, (w, img) in enumerate(zip(wls, imgs)):
+        (p0, p1, H, W), (s0, s1) = slices[i]
+        s = Scalp(W, H, w.k, iterations=10)
+        r = s.run(dev(img.lab), dev(img.contour))
+        assert (l[p0:p1].reshape(H, W) == host(r.labels)).all(), w.name
+        assert (c[s0:s1] == host(r.centers)).all() and (e[s0:s1] == host(r.endpoints)).all()
+        assert (n[s0:s1] == host(r.counts)).all()
+        if i in sampled:
+            say("oracle", w.name)
+            ref = orc.run(img.lab, img.contour, w.k, iterations=10, mode=orc.MEAN_FIXED)
+            assert (l[p0:p1].reshape(H, W) == ref.labels).all(), w.name
+            assert (c[s0:s1] == ref.centres).all() and (e[s0:s1] == ref.endpoints).all()
