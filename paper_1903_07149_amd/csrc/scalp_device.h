@@ -36,11 +36,15 @@ __device__ __forceinline__ long long to_fixed(float v) {
 
 // Accumulates the samples i = 1 .. n-1 of the path from the pixel at linear
 // index `idx` toward (dx, dy): on major-axis step i the minor offset is
-// floor((2 i |d_minor| + n) / (2 n)), kept incrementally as a remainder
-// (exact for any n).  stepx / stepy are the index strides of one pixel in
-// x / y.  Global-memory variant, used when a candidate's path rectangle
-// exceeds the LDS tables: up to three texel loads in flight, accumulated in
-// path order.
+// floor((2 i |d_minor| + n) / (2 n)).  stepx / stepy are the index strides
+// of one pixel in x / y.  Global-memory variant, used when a candidate's
+// path rectangle exceeds the LDS tables; samples are accumulated in path
+// order, with up to three texel loads in flight.  Paths of up to 46340
+// steps count the minor steps as the carries of a 32-bit accumulator (exact
+// there, see walk_table); longer ones (only from caller-supplied endpoints
+// far across a very wide image) keep the remainder exactly.
+__device__ __forceinline__ unsigned step_increment(int am, int n);
+
 __device__ __forceinline__ void walk_path(const float4* __restrict__ base, int idx, int stepx,
                                           int stepy, int dx, int dy, float l, float a, float b,
                                           float& sc, float& sw) {
@@ -54,6 +58,46 @@ __device__ __forceinline__ void walk_path(const float4* __restrict__ base, int i
     const int sy = dy < 0 ? -stepy : stepy;
     const int smaj = xmaj ? sx : sy;
     const int sdiag = smaj + (xmaj ? sy : sx);
+#define SCALP_GACC(f)                                             \
+    do {                                                          \
+        const float dl_ = (f).x - l;                              \
+        const float da_ = (f).y - a;                              \
+        const float db_ = (f).z - b;                              \
+        const float dc_ = (dl_ * dl_ + da_ * da_) + db_ * db_;    \
+        sc = sc + dc_;                                            \
+        sw = sw + (f).w;                                          \
+    } while (0)
+    if (n <= 46340) {
+        const unsigned F = step_increment(am, n);
+        unsigned acc = 0x80000000u;
+#define SCALP_CSTEP()                                             \
+    do {                                                          \
+        const bool c_ = __builtin_add_overflow(acc, F, &acc);     \
+        idx += c_ ? sdiag : smaj;                                 \
+    } while (0)
+        SCALP_CSTEP();
+        float4 fa = base[idx];
+        unsigned trips = (unsigned)(n - 2) >> 1;
+        while (!__builtin_sub_overflow(trips, 1u, &trips)) {
+            SCALP_CSTEP();
+            const float4 fb = base[idx];
+            SCALP_CSTEP();
+            const float4 fc = base[idx];
+            SCALP_GACC(fa);
+            SCALP_GACC(fb);
+            fa = fc;
+            asm volatile("" : "+v"(acc));
+        }
+        if ((n - 2) & 1) {
+            SCALP_CSTEP();
+            const float4 fb = base[idx];
+            SCALP_GACC(fa);
+            fa = fb;
+        }
+        SCALP_GACC(fa);
+#undef SCALP_CSTEP
+        return;
+    }
     const int two_n = 2 * n;
     const int inc = 2 * am;
     int rem = n;
@@ -63,15 +107,6 @@ __device__ __forceinline__ void walk_path(const float4* __restrict__ base, int i
         const bool st_ = rem >= two_n;                            \
         rem -= st_ ? two_n : 0;                                   \
         idx += st_ ? sdiag : smaj;                                \
-    } while (0)
-#define SCALP_GACC(f)                                             \
-    do {                                                          \
-        const float dl_ = (f).x - l;                              \
-        const float da_ = (f).y - a;                              \
-        const float db_ = (f).z - b;                              \
-        const float dc_ = (dl_ * dl_ + da_ * da_) + db_ * db_;    \
-        sc = sc + dc_;                                            \
-        sw = sw + (f).w;                                          \
     } while (0)
     SCALP_GSTEP();
     float4 fa = base[idx];

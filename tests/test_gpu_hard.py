@@ -103,6 +103,24 @@ def test_assign_long_paths(orc, W, H, k, tune):
     assert (lbl == ol).all(), f"{int((lbl != ol).sum())} labels differ"
 
 
+def test_assign_paths_beyond_carry_range(orc):
+    """Caller-supplied endpoints of the last three superpixels of a 60000-pixel
+    row at its left end: the paths to them from the right end have more than
+    46340 steps (beyond the range of the carry-counting stepper) and take the
+    exact remainder stepping of the global-memory walk."""
+    W, H, k = 60000, 1, 100
+    img = _image(W, H, 21, regions=30)
+    g = orc.grid(W, H, k)
+    c, e = perturbed_state(orc, g, img.lab, seed=5, jitter=2.0)
+    e = e.copy()
+    e[-3:] = 0
+    s = _scalp(W, H, k)
+    say("assign paths beyond 46340 steps")
+    lbl = host(s.assign(dev(img.lab), dev(img.contour), dev(c), dev(e)))
+    ol, _, _ = orc.assign(g, img.lab, orc.wmap(img.contour), c, e)
+    assert (lbl == ol).all(), f"{int((lbl != ol).sum())} labels differ"
+
+
 @pytest.mark.parametrize("scale", [1e-21, 1e-17])
 def test_assign_tiny_colour_sums(orc, scale):
     """Lab values so small that the path colour sums fall below 2^-100 (down
