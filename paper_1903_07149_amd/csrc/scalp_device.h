@@ -41,8 +41,9 @@ __device__ __forceinline__ long long to_fixed(float v) {
 // path rectangle exceeds the LDS tables; samples are accumulated in path
 // order, with up to three texel loads in flight.  Paths of up to 46340
 // steps count the minor steps as the carries of a 32-bit accumulator (exact
-// there, see walk_table); longer ones (only from caller-supplied endpoints
-// far across a very wide image) keep the remainder exactly.
+// there, see walk_table); longer ones (cells over ~15000 pixels wide, or
+// caller-supplied endpoints far across a wide image) keep the remainder
+// exactly.
 __device__ __forceinline__ unsigned step_increment(int am, int n);
 
 __device__ __forceinline__ void walk_path(const float4* __restrict__ base, int idx, int stepx,
