@@ -234,8 +234,17 @@ def cpu_baseline(img, k, iters):
         # a bounded sample: at least 10 s of CPU work, at most 12 full runs
         if el >= 10.0 or reps >= 12:
             break
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     out = {"value": round(W * H * iters * reps / el / 1e6, 3), "unit": "Mpixel-iter/s",
-           "cores": threads, "kind": "oracle",
+           "cores": threads, "kind": "oracle", "cpu": cpu, "host_cpus": os.cpu_count(),
            "sample": f"{reps} full run(s) of {W}x{H} k={k}, {iters} iterations, "
                      f"{el:.1f} s on {threads} OpenMP threads"}
     # the same oracle on one thread, over a shorter run of the same workload
