@@ -60,7 +60,6 @@ struct SoftCand {
 struct SoftShared {
     SoftCand cand[9];
     int rx0, ry0, rw, rh;
-    float bins[9][5];
 };
 
 // Candidates of cell (ci, cj) from theta [K][5]; endpoint = rounded barycenter.
@@ -469,18 +468,27 @@ __global__ void k_soft_bwd_pass(SoftImg s, const double* __restrict__ z,
         gth_prev[i] = z[i / 5] >= kZMin ? 0.0f : gth[i];
 }
 
-// One workgroup per (image, cell), one pass: each lane loads its pixel's nine
-// dL/dD values and re-walks the path of every slot whose value is not zero
-// (at low T about one per pixel), scattering per sample
+// Per wave, the (pixel, slot) pairs of its 64-pixel chunk whose dL/dD is not
+// zero, slot-major, at most kBwdBatch at a time; per slot, the 5 centre-
+// gradient sums and the 2 endpoint sums in kBwdCopies copies.
+constexpr int kBwdBatch = 192;
+constexpr int kBwdCopies = 8;
+
+// One workgroup per (image, cell), one pass: every (pixel, slot) whose dL/dD
+// is not zero (at low T about one per pixel) re-walks its path, scattering
+// per sample
 //   dL/df_q += cf (f_q - f_k)   with cf = dL/dD * B (1 - lambda) 2 / |P|
 //   dL/dw_q += dL/dD * A gamma / |P|
 // into LDS tiles over the rectangle of the cell and its candidates'
-// endpoints (texel colours come through the cache); the candidate's centre gradient
-// takes the opposite colour terms and the spatial and lambda terms.  The
-// endpoint sample, shared by every path to a slot, is reduced over the wave
-// and added once.  Tiles leave the workgroup as float atomics (not
-// bit-reproducible).  Candidates whose endpoint lies outside the rectangle
-// scatter straight to global memory.
+// endpoints (texel colours come through the cache); the candidate's centre
+// gradient takes the opposite colour terms and the spatial and lambda terms.
+// Each wave lists its chunk's nonzero pairs in LDS and walks them 64 at a
+// time, one per lane, so no lane idles on a zero slot (with one lane per
+// pixel and slot, most lanes of a wave had nothing to walk for the
+// neighbouring slots).  The endpoint sample, shared by every path to a
+// slot, is summed per slot and added once at the end.  Tiles leave the
+// workgroup as float atomics (not bit-reproducible).  Candidates whose
+// endpoint lies outside the rectangle scatter straight to global memory.
 template <int WG>
 __global__ __launch_bounds__(WG) void k_soft_bwd_path(SoftImg s, const float4* __restrict__ packed,
                                                       const float* __restrict__ theta_prev,
@@ -491,6 +499,9 @@ __global__ __launch_bounds__(WG) void k_soft_bwd_path(SoftImg s, const float4* _
                                                       float* __restrict__ gth_prev, int cap) {
     extern __shared__ float4 lds_dyn[];
     __shared__ SoftShared sh;
+    __shared__ int wl_code[WG / 64][kBwdBatch];     // source lane | slot << 6
+    __shared__ float wl_g[WG / 64][kBwdBatch];      // its dL/dD
+    __shared__ float slot_acc[9][7][kBwdCopies];
     // four planar float tiles of cap texels: dL/dl, dL/da, dL/db, dL/dw
     float* accx = reinterpret_cast<float*>(lds_dyn);
     float* accy = accx + cap;
@@ -506,7 +517,7 @@ __global__ __launch_bounds__(WG) void k_soft_bwd_path(SoftImg s, const float4* _
     const float4* __restrict__ img = packed + (long long)b * s.N;
     float4* __restrict__ gimg = gf + (long long)b * s.N;
     load_candidates(s, ci, cj, theta_prev + 5LL * s.K * b, img, sh);
-    for (int t = tid; t < 45; t += WG) (&sh.bins[0][0])[t] = 0.0f;
+    for (int t = tid; t < 9 * 7 * kBwdCopies; t += WG) (&slot_acc[0][0][0])[t] = 0.0f;
     __syncthreads();
     plan_rect(x0, x1, y0, y1, cap, sh);
     __syncthreads();
@@ -521,156 +532,202 @@ __global__ __launch_bounds__(WG) void k_soft_bwd_path(SoftImg s, const float4* _
     __syncthreads();
     const int cw = x1 - x0, ch = y1 - y0, P = cw * ch;
     const int lane = tid & 63, wave = tid >> 6;
+    const int cp = lane & (kBwdCopies - 1);
     const float lambda = s.lambda, oml = 1.0f - lambda;
     const long long base = 9LL * s.N * b;
     for (int chunk = wave; chunk * 64 < P; chunk += WG / 64) {
         const int t = chunk * 64 + lane;
         const bool valid = t < P;
-        int x = 0, y = 0;
+        int px = 0, py = 0;
         if (valid) {
-            cell_pixel(t, cw, ch, x, y);
-            x += x0;
-            y += y0;
+            cell_pixel(t, cw, ch, px, py);
+            px += x0;
+            py += y0;
         }
-        const int p = y * W + x;
         float g[9];
 #pragma unroll
         for (int j = 0; j < 9; ++j)
-            g[j] = valid && sh.cand[j].k >= 0 ? gd[base + (long long)j * s.N + p] : 0.0f;
-#pragma unroll 1
-        for (int j = 0; j < 9; ++j) {                           // uniform
-            const SoftCand c = sh.cand[j];
-            if (c.k < 0) continue;
-            const float gj = g[j];
-            // no lane of this wave has the slot: skip its walks and reductions
-            if (__ballot(gj != 0.0f) == 0ULL) continue;
-            float gk[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-            float cf_end = 0.0f, cw_end = 0.0f;
-            if (gj != 0.0f) {
-                const long long o = base + (long long)j * s.N + p;
-                const float A = fa[o], Bw = fb[o];
-                const int dx = c.cx - x, dy = c.cy - y;
-                const int adx = dx < 0 ? -dx : dx, ady = dy < 0 ? -dy : dy;
-                const int n = adx > ady ? adx : ady;
-                const float inv_np = 1.0f / (float)(n + 1);
-                const float cf = 2.0f * gj * Bw * oml * inv_np;  // per sample, times (f_q - f_k)
-                const float cw_ = gj * A * s.gamma * inv_np;     // per sample: dL/dw_q
-                const float lf = 2.0f * gj * Bw * lambda;        // lambda term of p
-                const float4 fp = img[p];
-                const float dl = fp.x - c.l, da = fp.y - c.a, db = fp.z - c.b;
-                gk[0] -= lf * dl;
-                gk[1] -= lf * da;
-                gk[2] -= lf * db;
-                gk[3] -= 2.0f * gj * s.spw * ((float)x - c.x);
-                gk[4] -= 2.0f * gj * s.spw * ((float)y - c.y);
-                // samples i = 0 .. n-1 (p itself first); i = n is the endpoint
-                const bool xmaj = adx >= ady;
-                const int am = xmaj ? ady : adx;
-                const int two_n = 2 * n, inc = 2 * am;
-                int rem = n;
-                if (c.staged) {
-                    const int stx = dx < 0 ? -1 : 1, sty = dy < 0 ? -rw : rw;
-                    const int smaj = xmaj ? stx : sty;
-                    const int sdiag = smaj + (xmaj ? sty : stx);
-                    const int gty = dy < 0 ? -W : W;                // the same steps in the image
-                    const int gmaj = xmaj ? stx : gty;
-                    const int gdiag = gmaj + (xmaj ? gty : stx);
-                    int li = (y - ry0) * rw + (x - rx0);
-                    int gi = p;
-                    atomicAdd(&accx[li], lf * dl);
-                    atomicAdd(&accy[li], lf * da);
-                    atomicAdd(&accz[li], lf * db);
-                    // four samples per trip: the texel loads of a trip are all
-                    // issued before the first is used
-                    for (int i0 = 0; i0 < n; i0 += 4) {
-                        int lis[4];
-                        float4 fq[4];
+            g[j] = valid && sh.cand[j].k >= 0
+                       ? gd[base + (long long)j * s.N + (long long)py * W + px] : 0.0f;
+        int jn = 0;                                             // next slot to list
+        while (jn < 9) {                                        // uniform
+            // list whole slots while they fit (a slot has at most 64 pairs)
+            int nb = 0;
+            while (jn < 9) {
+                float gj = 0.0f;
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            if (i0 + u < n) {
-                                if (i0 + u > 0) {
-                                    rem += inc;
-                                    const bool st = rem >= two_n;
-                                    rem -= st ? two_n : 0;
-                                    li += st ? sdiag : smaj;
-                                    gi += st ? gdiag : gmaj;
+                for (int j = 0; j < 9; ++j) gj = j == jn ? g[j] : gj;
+                const unsigned long long m = __ballot(gj != 0.0f);
+                const int cnt = __popcll(m);
+                if (nb + cnt > kBwdBatch) break;                // uniform
+                if (gj != 0.0f) {
+                    const int at = nb + (int)__builtin_amdgcn_mbcnt_hi(
+                                           (unsigned)(m >> 32),
+                                           __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+                    wl_code[wave][at] = lane | (jn << 6);
+                    wl_g[wave][at] = gj;
+                }
+                nb += cnt;
+                ++jn;
+            }
+            // the list is the wave's own: its LDS accesses stay in order,
+            // and the compiler must not move them across this point
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            for (int i = lane; i - lane < nb; i += 64) {        // uniform trip count
+                if (i >= nb) continue;
+                const int code = wl_code[wave][i];
+                const float gj = wl_g[wave][i];
+                const int jj = code >> 6;
+                int x, y;
+                cell_pixel(chunk * 64 + (code & 63), cw, ch, x, y);
+                x += x0;
+                y += y0;
+                const int p = y * W + x;
+                const SoftCand c = sh.cand[jj];
+                float gk[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+                float cf_end = 0.0f, cw_end = 0.0f;
+                {
+                    const long long o = base + (long long)jj * s.N + p;
+                    const float A = fa[o], Bw = fb[o];
+                    const int dx = c.cx - x, dy = c.cy - y;
+                    const int adx = dx < 0 ? -dx : dx, ady = dy < 0 ? -dy : dy;
+                    const int n = adx > ady ? adx : ady;
+                    const float inv_np = 1.0f / (float)(n + 1);
+                    const float cf = 2.0f * gj * Bw * oml * inv_np;  // per sample, times (f_q - f_k)
+                    const float cw_ = gj * A * s.gamma * inv_np;     // per sample: dL/dw_q
+                    const float lf = 2.0f * gj * Bw * lambda;        // lambda term of p
+                    const float4 fp = img[p];
+                    const float dl = fp.x - c.l, da = fp.y - c.a, db = fp.z - c.b;
+                    gk[0] -= lf * dl;
+                    gk[1] -= lf * da;
+                    gk[2] -= lf * db;
+                    gk[3] -= 2.0f * gj * s.spw * ((float)x - c.x);
+                    gk[4] -= 2.0f * gj * s.spw * ((float)y - c.y);
+                    // samples i = 0 .. n-1 (p itself first); i = n is the endpoint
+                    const bool xmaj = adx >= ady;
+                    const int am = xmaj ? ady : adx;
+                    const int two_n = 2 * n, inc = 2 * am;
+                    int rem = n;
+                    if (c.staged) {
+                        const int stx = dx < 0 ? -1 : 1, sty = dy < 0 ? -rw : rw;
+                        const int smaj = xmaj ? stx : sty;
+                        const int sdiag = smaj + (xmaj ? sty : stx);
+                        const int gty = dy < 0 ? -W : W;                // the same steps in the image
+                        const int gmaj = xmaj ? stx : gty;
+                        const int gdiag = gmaj + (xmaj ? gty : stx);
+                        int li = (y - ry0) * rw + (x - rx0);
+                        int gi = p;
+                        atomicAdd(&accx[li], lf * dl);
+                        atomicAdd(&accy[li], lf * da);
+                        atomicAdd(&accz[li], lf * db);
+                        // four samples per trip: the texel loads of a trip are all
+                        // issued before the first is used
+                        for (int i0 = 0; i0 < n; i0 += 4) {
+                            int lis[4];
+                            float4 fq[4];
+    #pragma unroll
+                            for (int u = 0; u < 4; ++u) {
+                                if (i0 + u < n) {
+                                    if (i0 + u > 0) {
+                                        rem += inc;
+                                        const bool st = rem >= two_n;
+                                        rem -= st ? two_n : 0;
+                                        li += st ? sdiag : smaj;
+                                        gi += st ? gdiag : gmaj;
+                                    }
+                                    lis[u] = li;
+                                    fq[u] = img[gi];
                                 }
-                                lis[u] = li;
-                                fq[u] = img[gi];
+                            }
+    #pragma unroll
+                            for (int u = 0; u < 4; ++u) {
+                                if (i0 + u < n) {
+                                    const float el = cf * (fq[u].x - c.l), ea = cf * (fq[u].y - c.a),
+                                                eb = cf * (fq[u].z - c.b);
+                                    atomicAdd(&accx[lis[u]], el);
+                                    atomicAdd(&accy[lis[u]], ea);
+                                    atomicAdd(&accz[lis[u]], eb);
+                                    atomicAdd(&accw[lis[u]], cw_);
+                                    gk[0] -= el;
+                                    gk[1] -= ea;
+                                    gk[2] -= eb;
+                                }
                             }
                         }
-#pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            if (i0 + u < n) {
-                                const float el = cf * (fq[u].x - c.l), ea = cf * (fq[u].y - c.a),
-                                            eb = cf * (fq[u].z - c.b);
-                                atomicAdd(&accx[lis[u]], el);
-                                atomicAdd(&accy[lis[u]], ea);
-                                atomicAdd(&accz[lis[u]], eb);
-                                atomicAdd(&accw[lis[u]], cw_);
-                                gk[0] -= el;
-                                gk[1] -= ea;
-                                gk[2] -= eb;
+                        cf_end = cf;
+                        cw_end = cw_;
+                    } else {
+                        const int stx = dx < 0 ? -1 : 1, sty = dy < 0 ? -W : W;
+                        const int smaj = xmaj ? stx : sty;
+                        const int sdiag = smaj + (xmaj ? sty : stx);
+                        int gi = p;
+                        unsafeAtomicAdd(&gimg[gi].x, lf * dl);
+                        unsafeAtomicAdd(&gimg[gi].y, lf * da);
+                        unsafeAtomicAdd(&gimg[gi].z, lf * db);
+                        for (int i = 0; i <= n; ++i) {
+                            if (i > 0) {
+                                rem += inc;
+                                const bool st = rem >= two_n;
+                                rem -= st ? two_n : 0;
+                                gi += st ? sdiag : smaj;
                             }
+                            const float4 fq = img[gi];
+                            const float el = cf * (fq.x - c.l), ea = cf * (fq.y - c.a),
+                                        eb = cf * (fq.z - c.b);
+                            unsafeAtomicAdd(&gimg[gi].x, el);
+                            unsafeAtomicAdd(&gimg[gi].y, ea);
+                            unsafeAtomicAdd(&gimg[gi].z, eb);
+                            unsafeAtomicAdd(&gimg[gi].w, cw_);
+                            gk[0] -= el;
+                            gk[1] -= ea;
+                            gk[2] -= eb;
                         }
                     }
-                    cf_end = cf;
-                    cw_end = cw_;
-                } else {
-                    const int stx = dx < 0 ? -1 : 1, sty = dy < 0 ? -W : W;
-                    const int smaj = xmaj ? stx : sty;
-                    const int sdiag = smaj + (xmaj ? sty : stx);
-                    int gi = p;
-                    unsafeAtomicAdd(&gimg[gi].x, lf * dl);
-                    unsafeAtomicAdd(&gimg[gi].y, lf * da);
-                    unsafeAtomicAdd(&gimg[gi].z, lf * db);
-                    for (int i = 0; i <= n; ++i) {
-                        if (i > 0) {
-                            rem += inc;
-                            const bool st = rem >= two_n;
-                            rem -= st ? two_n : 0;
-                            gi += st ? sdiag : smaj;
-                        }
-                        const float4 fq = img[gi];
-                        const float el = cf * (fq.x - c.l), ea = cf * (fq.y - c.a),
-                                    eb = cf * (fq.z - c.b);
-                        unsafeAtomicAdd(&gimg[gi].x, el);
-                        unsafeAtomicAdd(&gimg[gi].y, ea);
-                        unsafeAtomicAdd(&gimg[gi].z, eb);
-                        unsafeAtomicAdd(&gimg[gi].w, cw_);
-                        gk[0] -= el;
-                        gk[1] -= ea;
-                        gk[2] -= eb;
-                    }
                 }
-            }
-            // seven wave sums by DPP, interleaved so that each step issues
-            // seven independent instructions; the totals land in lane 63
-            float red[7] = {gk[0], gk[1], gk[2], gk[3], gk[4], cf_end, cw_end};
 #pragma unroll
-            for (int v = 0; v < 7; ++v) red[v] = wave_sum_last(red[v]);
-#pragma unroll
-            for (int v = 0; v < 5; ++v) gk[v] = red[v];
-            if (c.staged) {                                     // uniform
-                // the endpoint: (sum cf) (f_c - f_k) and sum dL/dw
-                const float se = red[5], swe = red[6];
-                if (lane == 63 && (se != 0.0f || swe != 0.0f)) {
-                    const int lic = (c.cy - ry0) * rw + (c.cx - rx0);
-                    const float4 fc = img[(long long)c.cy * W + c.cx];
-                    const float el = se * (fc.x - c.l), ea = se * (fc.y - c.a),
-                                eb = se * (fc.z - c.b);
-                    atomicAdd(&accx[lic], el);
-                    atomicAdd(&accy[lic], ea);
-                    atomicAdd(&accz[lic], eb);
-                    atomicAdd(&accw[lic], swe);
-                    gk[0] -= el;
-                    gk[1] -= ea;
-                    gk[2] -= eb;
-                }
-            }
-            if (lane == 63)
                 for (int v = 0; v < 5; ++v)
-                    if (gk[v] != 0.0f) atomicAdd(&sh.bins[j][v], gk[v]);
+                    if (gk[v] != 0.0f) atomicAdd(&slot_acc[jj][v][cp], gk[v]);
+                if (c.staged) {
+                    atomicAdd(&slot_acc[jj][5][cp], cf_end);
+                    atomicAdd(&slot_acc[jj][6][cp], cw_end);
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+    }
+    __syncthreads();
+    // per slot: the endpoint sample, (sum cf) (f_c - f_k) and sum dL/dw, then
+    // the centre gradient
+    if (tid < 9) {
+        const SoftCand c = sh.cand[tid];
+        if (c.k >= 0) {
+            float v[7];
+#pragma unroll
+            for (int q = 0; q < 7; ++q) {
+                float a = 0.0f;
+                for (int k = 0; k < kBwdCopies; ++k) a += slot_acc[tid][q][k];
+                v[q] = a;
+            }
+            if (c.staged && (v[5] != 0.0f || v[6] != 0.0f)) {
+                const int lic = (c.cy - ry0) * rw + (c.cx - rx0);
+                const float4 fc = img[(long long)c.cy * W + c.cx];
+                const float el = v[5] * (fc.x - c.l), ea = v[5] * (fc.y - c.a),
+                            eb = v[5] * (fc.z - c.b);
+                atomicAdd(&accx[lic], el);
+                atomicAdd(&accy[lic], ea);
+                atomicAdd(&accz[lic], eb);
+                atomicAdd(&accw[lic], v[6]);
+                v[0] -= el;
+                v[1] -= ea;
+                v[2] -= eb;
+            }
+            for (int q = 0; q < 5; ++q)
+                if (v[q] != 0.0f)
+                    unsafeAtomicAdd(&gth_prev[5LL * s.K * b + 5LL * c.k + q], v[q]);
         }
     }
     __syncthreads();
@@ -685,12 +742,6 @@ __global__ __launch_bounds__(WG) void k_soft_bwd_path(SoftImg s, const float4* _
             unsafeAtomicAdd(&d->z, vz);
             unsafeAtomicAdd(&d->w, vw);
         }
-    }
-    if (tid < 45) {
-        const int j = tid / 5, v = tid - 5 * (tid / 5);
-        const int k = sh.cand[j].k;
-        if (k >= 0 && sh.bins[j][v] != 0.0f)
-            unsafeAtomicAdd(&gth_prev[5LL * s.K * b + 5LL * k + v], sh.bins[j][v]);
     }
 }
 
@@ -726,6 +777,11 @@ __global__ void k_copy_f32(const float* __restrict__ src, float* __restrict__ ds
 
 constexpr int kSoftWG = 256;
 constexpr int kSoftBwdWG = 512;
+// Tile budget of the backward path pass in texels (16 bytes each): with its
+// static LDS (the waves' pair lists, the slot sums, the candidates) two
+// 512-lane workgroups still fit in a CU's 160 KiB.  A rectangle beyond it
+// scatters to global memory instead.
+constexpr int kBwdTileCap = 4096;
 
 unsigned grid_for(long long n) {
     return (unsigned)std::max<long long>(1, std::min<long long>((n + 255) / 256, 65536));
@@ -768,12 +824,15 @@ void lift_soft_lds_limits() {
     const size_t cap = 160 * 1024 - sizeof(SoftShared) - 64;
     for (const void* k : {reinterpret_cast<const void*>(k_soft_assign<256>),
                           reinterpret_cast<const void*>(k_soft_assign<512>),
-                          reinterpret_cast<const void*>(k_soft_assign<1024>),
-                          reinterpret_cast<const void*>(k_soft_bwd_path<kSoftBwdWG>)}) {
+                          reinterpret_cast<const void*>(k_soft_assign<1024>)}) {
         static_cast<void>(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                               (int)cap));
         static_cast<void>(hipGetLastError());
     }
+    static_cast<void>(hipFuncSetAttribute(
+        reinterpret_cast<const void*>(k_soft_bwd_path<kSoftBwdWG>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, kBwdTileCap * 4 * (int)sizeof(float)));
+    static_cast<void>(hipGetLastError());
 }
 
 int launch_soft_init(const SoftGeom& g, const float4* packed, float* theta0, hipStream_t st) {
@@ -847,7 +906,7 @@ int launch_soft_bwd_path(const SoftGeom& g, const float4* packed, const float* t
     // one shape for the backward pass whatever the assignment's (measured
     // fastest on 16 x 512x512, k = 400: 512 lanes)
     return soft_bwd_path_t<kSoftBwdWG>(to_img(g), packed, theta_prev, fa, fb, gd, gf, gth_prev,
-                                       cap, st);
+                                       std::min(cap, kBwdTileCap), st);
 }
 
 int launch_soft_bwd_finish(const SoftGeom& g, const float4* gf, const float* gth0,
