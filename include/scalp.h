@@ -262,7 +262,9 @@ int scalp_soft_forward(const scalp_grid_t* g, const scalp_params_t* p, float tem
  * (grad_centers: [B][K'][5]) with respect to lab (grad_lab: [B][H][W][3],
  * output) and contour (grad_contour: [B][H][W], output).  Path samples are
  * recomputed, not stored; slots whose Q is below 2^-24 contribute no path
- * terms (each is proportional to Q).  contour is always required (dw/dC
+ * terms (each is proportional to Q).  The gradient tiles of a cell take
+ * min(lds_pixels, 3968) texels; a cell whose rectangle is larger scatters
+ * to global memory instead.  contour is always required (dw/dC
  * needs it); lab may be null when reuse_prepared is set and the workspace
  * holds the packed image of the forward call.  FP32 with float atomics: not
  * bit-reproducible. */

@@ -468,9 +468,11 @@ __global__ void k_soft_bwd_pass(SoftImg s, const double* __restrict__ z,
         gth_prev[i] = z[i / 5] >= kZMin ? 0.0f : gth[i];
 }
 
-// Per wave, the (pixel, slot) pairs of its 64-pixel chunk whose dL/dD is not
-// zero, slot-major, at most kBwdBatch at a time; per slot, the 5 centre-
-// gradient sums and the 2 endpoint sums in kBwdCopies copies.
+// Per wave, a list of (pixel, slot) pairs whose dL/dD is not zero, listed
+// chunk by chunk and slot by slot, walked in whole rounds of 64 whenever the
+// next slot would overflow its kBwdBatch entries (the rest carried over);
+// per slot, the 5 centre-gradient sums and the 2 endpoint sums in
+// kBwdCopies copies.
 constexpr int kBwdBatch = 192;
 constexpr int kBwdCopies = 8;
 
@@ -482,10 +484,10 @@ constexpr int kBwdCopies = 8;
 // into LDS tiles over the rectangle of the cell and its candidates'
 // endpoints (texel colours come through the cache); the candidate's centre
 // gradient takes the opposite colour terms and the spatial and lambda terms.
-// Each wave lists its chunk's nonzero pairs in LDS and walks them 64 at a
-// time, one per lane, so no lane idles on a zero slot (with one lane per
-// pixel and slot, most lanes of a wave had nothing to walk for the
-// neighbouring slots).  The endpoint sample, shared by every path to a
+// Each wave lists its nonzero pairs in LDS and walks them 64 at a time, one
+// per lane, so no lane idles on a zero slot (with one lane per pixel and
+// slot, most lanes of a wave had nothing to walk for the neighbouring
+// slots), and only the wave's last round is partial.  The endpoint sample, shared by every path to a
 // slot, is summed per slot and added once at the end.  Tiles leave the
 // workgroup as float atomics (not bit-reproducible).  Candidates whose
 // endpoint lies outside the rectangle scatter straight to global memory.
@@ -499,8 +501,9 @@ __global__ __launch_bounds__(WG) void k_soft_bwd_path(SoftImg s, const float4* _
                                                       float* __restrict__ gth_prev, int cap) {
     extern __shared__ float4 lds_dyn[];
     __shared__ SoftShared sh;
-    __shared__ int wl_code[WG / 64][kBwdBatch];     // source lane | slot << 6
-    __shared__ float wl_g[WG / 64][kBwdBatch];      // its dL/dD
+    __shared__ int wl_t[WG / 64][kBwdBatch];              // pixel index in the cell
+    __shared__ unsigned char wl_j[WG / 64][kBwdBatch];    // slot
+    __shared__ float wl_g[WG / 64][kBwdBatch];            // dL/dD
     __shared__ float slot_acc[9][7][kBwdCopies];
     // four planar float tiles of cap texels: dL/dl, dL/da, dL/db, dL/dw
     float* accx = reinterpret_cast<float*>(lds_dyn);
@@ -535,6 +538,138 @@ __global__ __launch_bounds__(WG) void k_soft_bwd_path(SoftImg s, const float4* _
     const int cp = lane & (kBwdCopies - 1);
     const float lambda = s.lambda, oml = 1.0f - lambda;
     const long long base = 9LL * s.N * b;
+    // walks listed pair i of this wave (the lanes of a wave call it together)
+    auto walk_pair = [&](int i) {
+        const int jj = wl_j[wave][i];
+        const float gj = wl_g[wave][i];
+        int x, y;
+        cell_pixel(wl_t[wave][i], cw, ch, x, y);
+        x += x0;
+        y += y0;
+        const int p = y * W + x;
+        const SoftCand c = sh.cand[jj];
+        float gk[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+        float cf_end = 0.0f, cw_end = 0.0f;
+        {
+            const long long o = base + (long long)jj * s.N + p;
+            const float A = fa[o], Bw = fb[o];
+            const int dx = c.cx - x, dy = c.cy - y;
+            const int adx = dx < 0 ? -dx : dx, ady = dy < 0 ? -dy : dy;
+            const int n = adx > ady ? adx : ady;
+            const float inv_np = 1.0f / (float)(n + 1);
+            const float cf = 2.0f * gj * Bw * oml * inv_np;  // per sample, times (f_q - f_k)
+            const float cw_ = gj * A * s.gamma * inv_np;     // per sample: dL/dw_q
+            const float lf = 2.0f * gj * Bw * lambda;        // lambda term of p
+            const float4 fp = img[p];
+            const float dl = fp.x - c.l, da = fp.y - c.a, db = fp.z - c.b;
+            gk[0] -= lf * dl;
+            gk[1] -= lf * da;
+            gk[2] -= lf * db;
+            gk[3] -= 2.0f * gj * s.spw * ((float)x - c.x);
+            gk[4] -= 2.0f * gj * s.spw * ((float)y - c.y);
+            // samples i = 0 .. n-1 (p itself first); i = n is the endpoint
+            const bool xmaj = adx >= ady;
+            const int am = xmaj ? ady : adx;
+            const int two_n = 2 * n, inc = 2 * am;
+            int rem = n;
+            if (c.staged) {
+                const int stx = dx < 0 ? -1 : 1, sty = dy < 0 ? -rw : rw;
+                const int smaj = xmaj ? stx : sty;
+                const int sdiag = smaj + (xmaj ? sty : stx);
+                const int gty = dy < 0 ? -W : W;                // the same steps in the image
+                const int gmaj = xmaj ? stx : gty;
+                const int gdiag = gmaj + (xmaj ? gty : stx);
+                int li = (y - ry0) * rw + (x - rx0);
+                int gi = p;
+                atomicAdd(&accx[li], lf * dl);
+                atomicAdd(&accy[li], lf * da);
+                atomicAdd(&accz[li], lf * db);
+                // four samples per trip: the texel loads of a trip are all
+                // issued before the first is used
+                for (int i0 = 0; i0 < n; i0 += 4) {
+                    int lis[4];
+                    float4 fq[4];
+    #pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        if (i0 + u < n) {
+                            if (i0 + u > 0) {
+                                rem += inc;
+                                const bool st = rem >= two_n;
+                                rem -= st ? two_n : 0;
+                                li += st ? sdiag : smaj;
+                                gi += st ? gdiag : gmaj;
+                            }
+                            lis[u] = li;
+                            fq[u] = img[gi];
+                        }
+                    }
+    #pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        if (i0 + u < n) {
+                            const float el = cf * (fq[u].x - c.l), ea = cf * (fq[u].y - c.a),
+                                        eb = cf * (fq[u].z - c.b);
+                            atomicAdd(&accx[lis[u]], el);
+                            atomicAdd(&accy[lis[u]], ea);
+                            atomicAdd(&accz[lis[u]], eb);
+                            atomicAdd(&accw[lis[u]], cw_);
+                            gk[0] -= el;
+                            gk[1] -= ea;
+                            gk[2] -= eb;
+                        }
+                    }
+                }
+                cf_end = cf;
+                cw_end = cw_;
+            } else {
+                const int stx = dx < 0 ? -1 : 1, sty = dy < 0 ? -W : W;
+                const int smaj = xmaj ? stx : sty;
+                const int sdiag = smaj + (xmaj ? sty : stx);
+                int gi = p;
+                unsafeAtomicAdd(&gimg[gi].x, lf * dl);
+                unsafeAtomicAdd(&gimg[gi].y, lf * da);
+                unsafeAtomicAdd(&gimg[gi].z, lf * db);
+                for (int i = 0; i <= n; ++i) {
+                    if (i > 0) {
+                        rem += inc;
+                        const bool st = rem >= two_n;
+                        rem -= st ? two_n : 0;
+                        gi += st ? sdiag : smaj;
+                    }
+                    const float4 fq = img[gi];
+                    const float el = cf * (fq.x - c.l), ea = cf * (fq.y - c.a),
+                                eb = cf * (fq.z - c.b);
+                    unsafeAtomicAdd(&gimg[gi].x, el);
+                    unsafeAtomicAdd(&gimg[gi].y, ea);
+                    unsafeAtomicAdd(&gimg[gi].z, eb);
+                    unsafeAtomicAdd(&gimg[gi].w, cw_);
+                    gk[0] -= el;
+                    gk[1] -= ea;
+                    gk[2] -= eb;
+                }
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < 5; ++v)
+            if (gk[v] != 0.0f) atomicAdd(&slot_acc[jj][v][cp], gk[v]);
+        if (c.staged) {
+            atomicAdd(&slot_acc[jj][5][cp], cf_end);
+            atomicAdd(&slot_acc[jj][6][cp], cw_end);
+        }
+    };
+    // walks pairs [0, upto) of the list, 64 per round; then the list's LDS
+    // may be rewritten (a wave's LDS accesses stay in order; the fences keep
+    // the compiler from moving them across)
+    auto walk_list = [&](int upto) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int i = lane; i - lane < upto; i += 64)            // uniform trip count
+            if (i < upto) walk_pair(i);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+    int nb = 0;                        // pairs listed and not walked yet (uniform over the wave)
     for (int chunk = wave; chunk * 64 < P; chunk += WG / 64) {
         const int t = chunk * 64 + lane;
         const bool valid = t < P;
@@ -549,156 +684,47 @@ __global__ __launch_bounds__(WG) void k_soft_bwd_path(SoftImg s, const float4* _
         for (int j = 0; j < 9; ++j)
             g[j] = valid && sh.cand[j].k >= 0
                        ? gd[base + (long long)j * s.N + (long long)py * W + px] : 0.0f;
-        int jn = 0;                                             // next slot to list
-        while (jn < 9) {                                        // uniform
-            // list whole slots while they fit (a slot has at most 64 pairs)
-            int nb = 0;
-            while (jn < 9) {
-                float gj = 0.0f;
+#pragma unroll 1
+        for (int jn = 0; jn < 9; ++jn) {                        // uniform
+            float gj = 0.0f;
 #pragma unroll
-                for (int j = 0; j < 9; ++j) gj = j == jn ? g[j] : gj;
-                const unsigned long long m = __ballot(gj != 0.0f);
-                const int cnt = __popcll(m);
-                if (nb + cnt > kBwdBatch) break;                // uniform
-                if (gj != 0.0f) {
-                    const int at = nb + (int)__builtin_amdgcn_mbcnt_hi(
-                                           (unsigned)(m >> 32),
-                                           __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-                    wl_code[wave][at] = lane | (jn << 6);
-                    wl_g[wave][at] = gj;
+            for (int j = 0; j < 9; ++j) gj = j == jn ? g[j] : gj;
+            const unsigned long long m = __ballot(gj != 0.0f);
+            const int cnt = __popcll(m);
+            if (nb + cnt > kBwdBatch) {                         // uniform: make room
+                // walk the whole rounds, move the rest (< 64 pairs) to the front
+                const int full = nb & ~63;
+                walk_list(full);
+                const int left = nb - full;
+                int lt = 0, lj = 0;
+                float lg = 0.0f;
+                if (lane < left) {
+                    lt = wl_t[wave][full + lane];
+                    lj = wl_j[wave][full + lane];
+                    lg = wl_g[wave][full + lane];
                 }
-                nb += cnt;
-                ++jn;
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                if (lane < left) {
+                    wl_t[wave][lane] = lt;
+                    wl_j[wave][lane] = (unsigned char)lj;
+                    wl_g[wave][lane] = lg;
+                }
+                nb = left;
             }
-            // the list is the wave's own: its LDS accesses stay in order,
-            // and the compiler must not move them across this point
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            for (int i = lane; i - lane < nb; i += 64) {        // uniform trip count
-                if (i >= nb) continue;
-                const int code = wl_code[wave][i];
-                const float gj = wl_g[wave][i];
-                const int jj = code >> 6;
-                int x, y;
-                cell_pixel(chunk * 64 + (code & 63), cw, ch, x, y);
-                x += x0;
-                y += y0;
-                const int p = y * W + x;
-                const SoftCand c = sh.cand[jj];
-                float gk[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-                float cf_end = 0.0f, cw_end = 0.0f;
-                {
-                    const long long o = base + (long long)jj * s.N + p;
-                    const float A = fa[o], Bw = fb[o];
-                    const int dx = c.cx - x, dy = c.cy - y;
-                    const int adx = dx < 0 ? -dx : dx, ady = dy < 0 ? -dy : dy;
-                    const int n = adx > ady ? adx : ady;
-                    const float inv_np = 1.0f / (float)(n + 1);
-                    const float cf = 2.0f * gj * Bw * oml * inv_np;  // per sample, times (f_q - f_k)
-                    const float cw_ = gj * A * s.gamma * inv_np;     // per sample: dL/dw_q
-                    const float lf = 2.0f * gj * Bw * lambda;        // lambda term of p
-                    const float4 fp = img[p];
-                    const float dl = fp.x - c.l, da = fp.y - c.a, db = fp.z - c.b;
-                    gk[0] -= lf * dl;
-                    gk[1] -= lf * da;
-                    gk[2] -= lf * db;
-                    gk[3] -= 2.0f * gj * s.spw * ((float)x - c.x);
-                    gk[4] -= 2.0f * gj * s.spw * ((float)y - c.y);
-                    // samples i = 0 .. n-1 (p itself first); i = n is the endpoint
-                    const bool xmaj = adx >= ady;
-                    const int am = xmaj ? ady : adx;
-                    const int two_n = 2 * n, inc = 2 * am;
-                    int rem = n;
-                    if (c.staged) {
-                        const int stx = dx < 0 ? -1 : 1, sty = dy < 0 ? -rw : rw;
-                        const int smaj = xmaj ? stx : sty;
-                        const int sdiag = smaj + (xmaj ? sty : stx);
-                        const int gty = dy < 0 ? -W : W;                // the same steps in the image
-                        const int gmaj = xmaj ? stx : gty;
-                        const int gdiag = gmaj + (xmaj ? gty : stx);
-                        int li = (y - ry0) * rw + (x - rx0);
-                        int gi = p;
-                        atomicAdd(&accx[li], lf * dl);
-                        atomicAdd(&accy[li], lf * da);
-                        atomicAdd(&accz[li], lf * db);
-                        // four samples per trip: the texel loads of a trip are all
-                        // issued before the first is used
-                        for (int i0 = 0; i0 < n; i0 += 4) {
-                            int lis[4];
-                            float4 fq[4];
-    #pragma unroll
-                            for (int u = 0; u < 4; ++u) {
-                                if (i0 + u < n) {
-                                    if (i0 + u > 0) {
-                                        rem += inc;
-                                        const bool st = rem >= two_n;
-                                        rem -= st ? two_n : 0;
-                                        li += st ? sdiag : smaj;
-                                        gi += st ? gdiag : gmaj;
-                                    }
-                                    lis[u] = li;
-                                    fq[u] = img[gi];
-                                }
-                            }
-    #pragma unroll
-                            for (int u = 0; u < 4; ++u) {
-                                if (i0 + u < n) {
-                                    const float el = cf * (fq[u].x - c.l), ea = cf * (fq[u].y - c.a),
-                                                eb = cf * (fq[u].z - c.b);
-                                    atomicAdd(&accx[lis[u]], el);
-                                    atomicAdd(&accy[lis[u]], ea);
-                                    atomicAdd(&accz[lis[u]], eb);
-                                    atomicAdd(&accw[lis[u]], cw_);
-                                    gk[0] -= el;
-                                    gk[1] -= ea;
-                                    gk[2] -= eb;
-                                }
-                            }
-                        }
-                        cf_end = cf;
-                        cw_end = cw_;
-                    } else {
-                        const int stx = dx < 0 ? -1 : 1, sty = dy < 0 ? -W : W;
-                        const int smaj = xmaj ? stx : sty;
-                        const int sdiag = smaj + (xmaj ? sty : stx);
-                        int gi = p;
-                        unsafeAtomicAdd(&gimg[gi].x, lf * dl);
-                        unsafeAtomicAdd(&gimg[gi].y, lf * da);
-                        unsafeAtomicAdd(&gimg[gi].z, lf * db);
-                        for (int i = 0; i <= n; ++i) {
-                            if (i > 0) {
-                                rem += inc;
-                                const bool st = rem >= two_n;
-                                rem -= st ? two_n : 0;
-                                gi += st ? sdiag : smaj;
-                            }
-                            const float4 fq = img[gi];
-                            const float el = cf * (fq.x - c.l), ea = cf * (fq.y - c.a),
-                                        eb = cf * (fq.z - c.b);
-                            unsafeAtomicAdd(&gimg[gi].x, el);
-                            unsafeAtomicAdd(&gimg[gi].y, ea);
-                            unsafeAtomicAdd(&gimg[gi].z, eb);
-                            unsafeAtomicAdd(&gimg[gi].w, cw_);
-                            gk[0] -= el;
-                            gk[1] -= ea;
-                            gk[2] -= eb;
-                        }
-                    }
-                }
-#pragma unroll
-                for (int v = 0; v < 5; ++v)
-                    if (gk[v] != 0.0f) atomicAdd(&slot_acc[jj][v][cp], gk[v]);
-                if (c.staged) {
-                    atomicAdd(&slot_acc[jj][5][cp], cf_end);
-                    atomicAdd(&slot_acc[jj][6][cp], cw_end);
-                }
+            if (gj != 0.0f) {
+                const int at = nb + (int)__builtin_amdgcn_mbcnt_hi(
+                                       (unsigned)(m >> 32),
+                                       __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+                wl_t[wave][at] = t;
+                wl_j[wave][at] = (unsigned char)jn;
+                wl_g[wave][at] = gj;
             }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            nb += cnt;
         }
     }
+    walk_list(nb);
     __syncthreads();
     // per slot: the endpoint sample, (sum cf) (f_c - f_k) and sum dL/dw, then
     // the centre gradient
@@ -778,10 +804,11 @@ __global__ void k_copy_f32(const float* __restrict__ src, float* __restrict__ ds
 constexpr int kSoftWG = 256;
 constexpr int kSoftBwdWG = 512;
 // Tile budget of the backward path pass in texels (16 bytes each): with its
-// static LDS (the waves' pair lists, the slot sums, the candidates) two
-// 512-lane workgroups still fit in a CU's 160 KiB.  A rectangle beyond it
-// scatters to global memory instead.
-constexpr int kBwdTileCap = 4096;
+// ~16 KiB of static LDS (the waves' pair lists, the slot sums, the
+// candidates) two 512-lane workgroups still fit in a CU's 160 KiB, with
+// room for allocation granularity.  A rectangle beyond it scatters to
+// global memory instead.
+constexpr int kBwdTileCap = 3968;
 
 unsigned grid_for(long long n) {
     return (unsigned)std::max<long long>(1, std::min<long long>((n + 255) / 256, 65536));
