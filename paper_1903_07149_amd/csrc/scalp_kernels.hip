@@ -355,7 +355,10 @@ __global__ __launch_bounds__(WG) void k_assign_window(Img im, const float4* __re
         const float ex = (float)x - xk, ey = (float)y - yk;
         const float D = A * B + (ex * ex + ey * ey) * im.spw;
         const unsigned long long key = ((unsigned long long)__float_as_uint(D) << 32) | (unsigned)k;
-        atomicMin(&keys[im.pix + p], key);
+        // keys only ever decrease: a stored key at or below this one (even
+        // read stale) means the atomic would change nothing
+        unsigned long long* kp = &keys[im.pix + p];
+        if (key < *reinterpret_cast<volatile unsigned long long*>(kp)) atomicMin(kp, key);
     }
 }
 
