@@ -160,7 +160,9 @@ def test_autograd_function_and_lds_fallback(orc):
     glab_o, gcon_o = orc.soft_backward(lab, con, k, gq.transpose(0, 2, 3, 1), gth,
                                        iterations=iters, T=T, d32=True)
     results = []
-    for lds in (0, 1, 300):                       # default; no LDS tables; partial
+    # default; no LDS tables; partial; the largest budget (the backward's
+    # tiles are capped below it)
+    for lds in (0, 1, 300, 9728):
         eng = _engine(W, H, k, B, T, iters, lds_pixels=lds)
         L = dev(lab).requires_grad_(True)
         C = dev(con).requires_grad_(True)
@@ -172,6 +174,31 @@ def test_autograd_function_and_lds_fallback(orc):
     for glab, gcon in results:
         assert np.linalg.norm(glab - glab_o) / np.linalg.norm(glab_o) <= 1e-3
         assert np.linalg.norm(gcon - gcon_o) / np.linalg.norm(gcon_o) <= 1e-3
+
+
+def test_soft_large_cells_largest_budget(orc):
+    """64x64-pixel cells with the largest LDS budget: the forward stages every
+    candidate's table, while the backward's tile rectangle (cell plus all
+    endpoints) exceeds its capped budget and scatters to global memory.  At
+    T = 50 the softmax is far from one-hot, so both gradients are large."""
+    W, H, k, B, T, iters = 128, 128, 4, 1, 50.0, 2
+    lab, con = _batch(B, (W, H), 6, 720)
+    rng = np.random.default_rng(6)
+    K = orc.grid(W, H, k).num_sp
+    assert K == 4
+    gq = rng.normal(0, 1, (B, 9, H, W)).astype(np.float32)
+    gth = rng.normal(0, 1, (B, K, 5)).astype(np.float32)
+    th_o, q_o, _ = orc.soft_forward(lab, con, k, iterations=iters, T=T, d32=True)
+    glab_o, gcon_o = orc.soft_backward(lab, con, k, gq.transpose(0, 2, 3, 1), gth,
+                                       iterations=iters, T=T, d32=True)
+    eng = _engine(W, H, k, B, T, iters, lds_pixels=9728)
+    say("soft large cells, lds 9728")
+    L, C = dev(lab), dev(con)
+    c_t, q_t, saved = eng.forward(L, C)
+    glab, gcon = (host(t) for t in eng.backward(L, C, c_t, q_t, saved, dev(gq), dev(gth)))
+    assert compare_forward(host(c_t), host(q_t), th_o, q_o, W, H) == iters
+    assert np.linalg.norm(glab - glab_o) / np.linalg.norm(glab_o) <= 1e-3
+    assert np.linalg.norm(gcon - gcon_o) / np.linalg.norm(gcon_o) <= 1e-3
 
 
 def test_soft_low_temperature_is_hard(orc):
