@@ -624,18 +624,26 @@ __device__ void scan_region(const int* __restrict__ lb, int W, int k, int X0, in
     const int bw = X1 - X0, area = bw * (Y1 - Y0);
     best = ~0ULL;
     found = 0;
-    for (int e0 = tid; e0 < area; e0 += 4 * WG) {
-        int lbl[4], xs[4], ys[4];
+    // element e = r * bw + c; lanes step by WG elements = (dr rows, dc
+    // columns), eight loads in flight per trip (the minimum over packed keys
+    // does not depend on the order)
+    constexpr int kU = 8;
+    const int dr = WG / bw, dc = WG - dr * bw;
+    int r = tid / bw, c = tid - r * bw;
+    for (int e0 = tid; e0 < area; e0 += kU * WG) {
+        int lbl[kU], xs[kU], ys[kU];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int e = e0 + u * WG;
-            const int r = e / bw;
-            xs[u] = X0 + (e - r * bw);
+        for (int u = 0; u < kU; ++u) {
+            xs[u] = X0 + c;
             ys[u] = Y0 + r;
-            lbl[u] = e < area ? lb[(long long)ys[u] * W + xs[u]] : -1;
+            lbl[u] = e0 + u * WG < area ? lb[(long long)ys[u] * W + xs[u]] : -1;
+            c += dc;
+            const bool wrap = c >= bw;
+            c -= wrap ? bw : 0;
+            r += dr + (wrap ? 1 : 0);
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < kU; ++u) {
             if (lbl[u] == k) {
                 ++found;
                 const unsigned long long key = proj_key(xs[u], ys[u], W, xk, yk);
