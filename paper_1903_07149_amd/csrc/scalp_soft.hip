@@ -54,7 +54,8 @@ struct SoftCand {
     float l, a, b, x, y;
     int cx, cy;
     float dcc, wc;
-    int staged;
+    int staged;                 // backward: endpoint inside the tile rectangle
+    int tx0, ty0, tw, th;       // forward: table origin, row pitch, rows; tw == 0: not staged
 };
 
 struct SoftShared {
@@ -180,6 +181,19 @@ __global__ __launch_bounds__(WG) void k_soft_assign(SoftImg s, const float4* __r
     }
     const float4* __restrict__ img = packed + (long long)b * s.N;
     load_candidates(s, ci, cj, theta_prev + 5LL * s.K * b, img, sh);
+    if (tid < 9) {                                              // the thread that loaded it
+        SoftCand& c = sh.cand[tid];
+        c.tw = 0;
+        c.tx0 = c.ty0 = c.th = 0;
+        if (c.k >= 0) {
+            const int tx0 = min(ix0, c.cx), ty0 = min(y0, c.cy);
+            const int rwid = max(ix1, c.cx + 1) - tx0, th = max(y1, c.cy + 1) - ty0;
+            const int tw = rwid + (24 - rwid % 16) % 16;        // pitch: 8 (mod 16) entries
+            if ((long long)tw * th <= cap) {
+                c.tx0 = tx0; c.ty0 = ty0; c.tw = tw; c.th = th;
+            }
+        }
+    }
     const bool mine = tid < t1 - t0;
     int x = 0, y = 0;
     if (mine) {
@@ -205,13 +219,11 @@ __global__ __launch_bounds__(WG) void k_soft_assign(SoftImg s, const float4* __r
         }
         const float l = sh.cand[j].l, a = sh.cand[j].a, bb = sh.cand[j].b;
         const int cx = sh.cand[j].cx, cy = sh.cand[j].cy;
-        const int tx0 = min(ix0, cx), ty0 = min(y0, cy);
-        const int rwid = max(ix1, cx + 1) - tx0, th = max(y1, cy + 1) - ty0;
-        const int tw = rwid + (24 - rwid % 16) % 16;            // pitch: 8 (mod 16) entries
-        const bool staged = (long long)tw * th <= cap;
+        const int tx0 = sh.cand[j].tx0, ty0 = sh.cand[j].ty0, tw = sh.cand[j].tw;
+        const bool staged = tw > 0;
         float2* tab = tabs + (buf ? cap : 0);
         if (staged) {                                           // uniform
-            fill_table<WG>(tab, img, W, tx0, ty0, tw, tw * th, l, a, bb);
+            fill_table<WG>(tab, img, W, tx0, ty0, tw, tw * sh.cand[j].th, l, a, bb);
             __syncthreads();
             buf ^= 1;
         }
