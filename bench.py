@@ -428,6 +428,19 @@ def quality(torch, tuned):
         r = s.run(lab, con)
         m = metrics(r.labels, gt, num_sp=s.K)
         out[name] = {k: round(v, 4) for k, v in m.items() if k in ("br", "asa", "ue", "co")}
+    # the metric kernels themselves, on the 1920x1080 workload's SCALP labels
+    # against its 400-region ground truth
+    from paper_1903_07149_amd.metrics import Metrics
+    hd = synth.workload_image(synth.HD)
+    Hh, Wh = hd.contour.shape
+    s = Scalp(Wh, Hh, synth.HD.k, **tuned)
+    r = s.run(torch.from_numpy(hd.lab).cuda(), torch.from_numpy(hd.contour).cuda())
+    gth = torch.from_numpy(hd.gt).cuda()
+    mk = Metrics(Wh, Hh, s.K, int(hd.gt.max()) + 1)
+    ms = _time(torch, lambda: mk.run(r.labels, gth), 20)
+    out["metrics_1920x1080"] = {"ms": round(ms, 4),
+                                "mpx_s": round(Wh * Hh / (ms * 1e-3) / 1e6, 1),
+                                "regions": int(hd.gt.max()) + 1, "num_sp": s.K}
     return out
 
 

@@ -4,12 +4,13 @@
 // against a ground-truth partition.
 //
 //   k_metric_pixels  one pass over the pixels: the overlap table
-//                    |S_k n G_i| (32-bit atomics), the perimeter of every
+//                    |S_k n G_i| (32-bit atomics, one per distinct pair
+//                    among a wave's pixels), the perimeter of every
 //                    superpixel in pixel edges (4-connectivity, image border
 //                    included), and the boundary-recall counts (ground-truth
 //                    boundary pixels, and those with a superpixel boundary
 //                    pixel at distance < epsilon), reduced per workgroup.
-//   k_metric_rows    thread per superpixel: area, largest overlap, UE row sum
+//   k_metric_rows    wave per superpixel: area, largest overlap, UE row sum
 //                    (integers) and the CO term 4 pi A^2 / P^2 (FP64).
 //   k_metric_final   one workgroup: fixed-order sums, so the result does not
 //                    depend on the order of the atomics.
@@ -41,21 +42,42 @@ __device__ __forceinline__ bool is_boundary(const int* L, int W, int H, int x, i
            (y > 0 && label_at(L, W, H, x, y - 1) != v);
 }
 
+// Adds 1 to table[k * R + i] for every lane of the wave with `ok`, one
+// atomic per distinct (k, i) among the lanes: a wave covers 64 neighbouring
+// pixels, which mostly share their superpixel and region, and atomics on one
+// word serialise.
+__device__ __forceinline__ void wave_count(unsigned* __restrict__ table, int R, bool ok, int k,
+                                           int i) {
+    const int lane = threadIdx.x & 63;
+    unsigned long long pending = __ballot(ok);
+    while (pending != 0ULL) {                         // uniform over the wave
+        const int leader = __ffsll((long long)pending) - 1;
+        const int lk = __builtin_amdgcn_readlane(k, leader);
+        const int li = __builtin_amdgcn_readlane(i, leader);
+        const unsigned long long m = __ballot(ok && k == lk && i == li) & pending;
+        if (lane == leader) atomicAdd(&table[(long long)lk * R + li], (unsigned)__popcll(m));
+        pending &= ~m;
+    }
+}
+
+// Blocks of kMetricWG threads over row segments: x from the block column,
+// rows strided by the grid's height.
 __global__ __launch_bounds__(kMetricWG) void k_metric_pixels(MetricGeom g, const int* __restrict__ S,
                                                              const int* __restrict__ G,
                                                              unsigned* __restrict__ table,
                                                              unsigned* __restrict__ perim,
                                                              unsigned long long* __restrict__ cnt) {
     __shared__ unsigned long long red[3][kMetricWG];
-    const long long N = (long long)g.W * g.H;
     unsigned long long gb = 0, hit = 0, sb = 0;
-    for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < N;
-         p += (long long)gridDim.x * blockDim.x) {
-        const int y = (int)(p / g.W), x = (int)(p - (long long)y * g.W);
-        const int k = S[p], i = G[p];
+    const int x = blockIdx.x * kMetricWG + threadIdx.x;
+    for (int y = blockIdx.y; y < g.H; y += gridDim.y) {  // uniform
+        const bool in = x < g.W;
+        const long long p = (long long)y * g.W + x;
+        const int k = in ? S[p] : -1, i = in ? G[p] : -1;
         const bool ok = k >= 0 && k < g.K && i >= 0 && i < g.R;
+        wave_count(table, g.R, ok, k, i);
+        if (!in) continue;
         if (ok) {
-            atomicAdd(&table[(long long)k * g.R + i], 1u);
             unsigned e = 0;
             e += (x + 1 >= g.W || S[p + 1] != k) ? 1u : 0u;
             e += (x == 0 || S[p - 1] != k) ? 1u : 0u;
@@ -90,27 +112,39 @@ __global__ __launch_bounds__(kMetricWG) void k_metric_pixels(MetricGeom g, const
     if (tid < 3) atomicAdd(&cnt[tid], red[tid][0]);
 }
 
-// Per superpixel: area, largest overlap (ASA), sum over meeting regions of
-// |S_k| - |S_k n G_i| (UE), and the CO term.
-__global__ void k_metric_rows(MetricGeom g, const unsigned* __restrict__ table,
-                              const unsigned* __restrict__ perim,
-                              unsigned long long* __restrict__ row_max,
-                              unsigned long long* __restrict__ row_ue,
-                              double* __restrict__ row_co) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= g.K) return;
+// Per superpixel (one wave each, lanes striding over the regions): area,
+// largest overlap (ASA), sum over meeting regions of |S_k| - |S_k n G_i|
+// (UE), and the CO term.  Integer sums and maxima: exact in any order.
+__global__ __launch_bounds__(256) void k_metric_rows(MetricGeom g,
+                                                     const unsigned* __restrict__ table,
+                                                     const unsigned* __restrict__ perim,
+                                                     unsigned long long* __restrict__ row_max,
+                                                     unsigned long long* __restrict__ row_ue,
+                                                     double* __restrict__ row_co) {
+    const int k = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (k >= g.K) return;                             // uniform over the wave
     const unsigned* t = table + (long long)k * g.R;
-    unsigned long long area = 0, mx = 0, meet = 0;
-    for (int i = 0; i < g.R; ++i) {
+    unsigned long long area = 0, meet = 0;
+    unsigned mx = 0;
+    for (int i = lane; i < g.R; i += 64) {
         const unsigned c = t[i];
         area += c;
         mx = c > mx ? c : mx;
         meet += c ? 1ULL : 0ULL;
     }
-    row_max[k] = mx;
-    row_ue[k] = meet * area - area;   // sum over meeting i of (area - c_i)
-    const double P = (double)perim[k];
-    row_co[k] = area ? 4.0 * 3.14159265358979323846 * (double)area * (double)area / (P * P) : 0.0;
+    for (int o = 32; o > 0; o >>= 1) {
+        area += __shfl_xor(area, o, 64);
+        meet += __shfl_xor(meet, o, 64);
+        const unsigned m2 = __shfl_xor(mx, o, 64);
+        mx = m2 > mx ? m2 : mx;
+    }
+    if (lane == 0) {
+        row_max[k] = mx;
+        row_ue[k] = meet * area - area;   // sum over meeting i of (area - c_i)
+        const double P = (double)perim[k];
+        row_co[k] = area ? 4.0 * 3.14159265358979323846 * (double)area * (double)area / (P * P)
+                         : 0.0;
+    }
 }
 
 __global__ __launch_bounds__(1024) void k_metric_final(MetricGeom g,
@@ -189,11 +223,13 @@ int launch_metrics(int W, int H, const int* S, int K, const int* G, int R, float
     const unsigned zb = (unsigned)std::min<long long>((zero_words + 255) / 256, 65536);
     hipLaunchKernelGGL(k_zero_u32, dim3(zb), dim3(256), 0, st, table, zero_words);
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, reinterpret_cast<unsigned*>(cnt), 16);
-    const long long N = (long long)W * H;
-    const unsigned pb = (unsigned)std::min<long long>((N + kMetricWG - 1) / kMetricWG, 16384);
-    hipLaunchKernelGGL(k_metric_pixels, dim3(pb), dim3(kMetricWG), 0, st, g, S, G, table, perim, cnt);
-    hipLaunchKernelGGL(k_metric_rows, dim3((K + 255) / 256), dim3(256), 0, st, g, table, perim,
-                       row_max, row_ue, row_co);
+    // about 2048 blocks: whole rows, the row stride set by the grid height
+    const int bx = (W + kMetricWG - 1) / kMetricWG;
+    const int by = std::max(1, std::min(H, std::max(1, 2048 / bx)));
+    hipLaunchKernelGGL(k_metric_pixels, dim3((unsigned)bx, (unsigned)std::min(by, 65535)),
+                       dim3(kMetricWG), 0, st, g, S, G, table, perim, cnt);
+    hipLaunchKernelGGL(k_metric_rows, dim3((unsigned)((K + 3) / 4)), dim3(256), 0, st, g, table,
+                       perim, row_max, row_ue, row_co);
     hipLaunchKernelGGL(k_metric_final, dim3(1), dim3(1024), 0, st, g, row_max, row_ue, row_co, cnt,
                        out);
     return hipGetLastError();

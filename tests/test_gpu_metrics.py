@@ -68,3 +68,19 @@ def test_metrics_of_a_run_and_ablation():
     assert rows["scalp"]["asa"] > rows["slic"]["asa"]
     assert rows["scalp"]["co"] > rows["slic"]["co"]
     assert rows["scalp"]["sp_boundary"] < rows["slic"]["sp_boundary"]
+
+
+def test_reusable_metrics_call_matches():
+    """metrics.Metrics (workspace allocated once, result left on the device)
+    gives what metrics() gives, on repeated calls."""
+    from paper_1903_07149_amd.metrics import Metrics, metrics
+    rng = np.random.default_rng(11)
+    H, W, K, R = 70, 90, 12, 5
+    sp = np.kron(rng.integers(0, K, (H // 5 + 1, W // 5 + 1)), np.ones((5, 5)))[:H, :W].astype(np.int32)
+    gt = np.kron(rng.integers(0, R, (H // 7 + 1, W // 7 + 1)), np.ones((7, 7)))[:H, :W].astype(np.int32)
+    ref = metrics(dev(sp), dev(gt), num_sp=K, num_regions=R, epsilon=2.0)
+    mk = Metrics(W, H, K, R, epsilon=2.0)
+    for _ in range(3):
+        v = host(mk.run(dev(sp), dev(gt))).tolist()
+        assert v[:4] == [ref["br"], ref["asa"], ref["ue"], ref["co"]]
+        assert int(v[4]) == ref["gt_boundary"] and int(v[5]) == ref["sp_boundary"]
