@@ -726,7 +726,7 @@ static bool metrics_args_ok(int32_t W, int32_t H, int32_t K, int32_t R) {
 size_t scalp_metrics_workspace_bytes(int32_t width, int32_t height, int32_t num_sp,
                                      int32_t num_regions) {
     if (!metrics_args_ok(width, height, num_sp, num_regions)) return 0;
-    return metrics_workspace_bytes((long long)width * height, num_sp, num_regions);
+    return metrics_workspace_bytes(width, height, num_sp, num_regions);
 }
 
 int scalp_metrics(int32_t width, int32_t height, const int32_t* labels, int32_t num_sp,
@@ -735,7 +735,7 @@ int scalp_metrics(int32_t width, int32_t height, const int32_t* labels, int32_t 
     if (!metrics_args_ok(width, height, num_sp, num_regions)) return SCALP_ERR_ARG;
     if (!labels || !gt || !out) return SCALP_ERR_ARG;
     if (!(epsilon > 0.0f) || epsilon > 64.0f) return SCALP_ERR_ARG;
-    if (!ws || ws_bytes < metrics_workspace_bytes((long long)width * height, num_sp, num_regions))
+    if (!ws || ws_bytes < metrics_workspace_bytes(width, height, num_sp, num_regions))
         return SCALP_ERR_WORKSPACE;
     CHECK_HIP(launch_metrics(width, height, labels, num_sp, gt, num_regions, epsilon, out, ws,
                              (hipStream_t)stream));

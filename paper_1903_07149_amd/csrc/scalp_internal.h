@@ -138,7 +138,7 @@ int launch_prepare_gradient(int W, int H, const float* lab, float sigma, float4*
                             unsigned long long* mx, hipStream_t s);
 
 // ---- quality metrics (scalp_metrics.hip)
-size_t metrics_workspace_bytes(long long N, int K, int R);
+size_t metrics_workspace_bytes(int W, int H, int K, int R);
 int launch_metrics(int W, int H, const int* S, int K, const int* G, int R, float eps, double* out,
                    void* ws, hipStream_t st);
 

@@ -29,6 +29,30 @@ def test_metrics_match_definitions(H, W, K, R, seed, eps):
     assert got["sp_boundary"] == int(M.boundary(sp).sum())
 
 
+@pytest.mark.parametrize("eps", [17.5, 40.25, 63.9, 64.0])
+def test_boundary_recall_far_and_across_words(eps):
+    """Sparse superpixel boundaries (two vertical cuts, one short horizontal
+    one) and ground-truth boundaries at many distances: recall then hinges on
+    the search reaching across 64-pixel words and many rows."""
+    from paper_1903_07149_amd.metrics import metrics
+    H, W = 90, 333
+    sp = np.zeros((H, W), np.int32)
+    sp[:, 150:] = 1
+    sp[:, 290:] = 2
+    sp[70:, 20:60] = 3
+    rng = np.random.default_rng(7)
+    gt = np.zeros((H, W), np.int32)
+    for v, c in enumerate(sorted(rng.choice(np.arange(1, W), 9, replace=False)), start=1):
+        gt[:, c:] = v
+    gt[rng.integers(0, H):, :40] += 10
+    say("metrics far", H, W, eps)
+    got = metrics(dev(sp), dev(gt), num_sp=4, num_regions=int(gt.max()) + 1, epsilon=eps)
+    ref = M.all_metrics(sp, gt, eps)
+    assert got["br"] == ref["br"]
+    assert got["gt_boundary"] == int(M.boundary(gt).sum())
+    assert got["sp_boundary"] == int(M.boundary(sp).sum())
+
+
 def test_boundary_recall_at_the_tolerance():
     """Offsets at exactly epsilon do not count (the oracle's closed-form case)."""
     from paper_1903_07149_amd.metrics import metrics
