@@ -313,7 +313,8 @@ int scalp_boundary_map(int32_t width, int32_t height, const int32_t* labels, int
  * g = (f(+1) - f(-1)) / 2) divided by its maximum over the image, in FP64
  * and rounded once to FP32; all zeros for a constant image.  A detector-free
  * stand-in for the learned detectors of Sec. II-E.  workspace: at least
- * 8 bytes of device memory.  out: float32 [H][W]. */
+ * 4096 bytes of device memory (8-byte aligned), else SCALP_ERR_WORKSPACE.
+ * out: float32 [H][W]. */
 int scalp_contour_from_lab(int32_t width, int32_t height, const float* lab, float* out,
                            void* workspace, size_t workspace_bytes, void* stream);
 

@@ -756,7 +756,7 @@ int scalp_contour_from_lab(int32_t width, int32_t height, const float* lab, floa
                            size_t ws_bytes, void* stream) {
     if (width < 1 || height < 1 || !lab || !out) return SCALP_ERR_ARG;
     if ((long long)width * height >= (1LL << 31)) return SCALP_ERR_ARG;
-    if (!ws || ws_bytes < 8) return SCALP_ERR_WORKSPACE;
+    if (!ws || ws_bytes < (size_t)kGradBytes) return SCALP_ERR_WORKSPACE;
     CHECK_HIP(launch_contour_from_lab(width, height, lab, out, ws, (hipStream_t)stream));
     return SCALP_OK;
 }

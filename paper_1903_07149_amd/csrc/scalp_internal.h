@@ -21,9 +21,17 @@ constexpr int kAccStride = 8;
 enum Ctrl : int {
     kCtrlProjCount = 0,   // entries in the projection list
     kCtrlQueue = 1,       // persistent work-queue head
-    kCtrlGradMax = 2,     // words 2-3: FP64 bits of the largest gradient magnitude
-    kCtrlWords = 64
+    kCtrlGradMax = 64,    // words 64-1087: kGradSlots partial maxima of the squared
+                          // gradient magnitude (FP64 bits), one per 128-byte line
+    kCtrlWords = 1088
 };
+
+// The gradient maximum is kept in kGradSlots 64-bit slots kGradStride words
+// apart (one per 128-byte cache line; block b of the maximum pass updates
+// slot b mod kGradSlots), so that the atomics of thousands of blocks do not
+// queue on one line; readers take the largest.
+constexpr int kGradSlots = 32, kGradStride = 16;
+constexpr int kGradBytes = kGradSlots * kGradStride * 8;
 
 // One image as the kernels see it.
 struct Img {

@@ -45,9 +45,9 @@ __global__ __launch_bounds__(256) void k_boundary_frequency(int W, int H, int n,
     }
 }
 
-// Gradient magnitude of pixel p in FP64 (central differences, replicated
-// borders), channels summed in order.
-__device__ __forceinline__ double grad_mag(const float* __restrict__ lab, int W, int H, int x, int y) {
+// Squared gradient magnitude of pixel p in FP64 (central differences,
+// replicated borders), channels summed in order.
+__device__ __forceinline__ double grad_sq(const float* __restrict__ lab, int W, int H, int x, int y) {
     const int xl = x > 0 ? x - 1 : 0, xr = x + 1 < W ? x + 1 : W - 1;
     const int yu = y > 0 ? y - 1 : 0, yd = y + 1 < H ? y + 1 : H - 1;
     const long long r = 3LL * ((long long)y * W + xr), l = 3LL * ((long long)y * W + xl);
@@ -58,7 +58,11 @@ __device__ __forceinline__ double grad_mag(const float* __restrict__ lab, int W,
         const double gy = 0.5 * ((double)lab[d + c] - (double)lab[u + c]);
         s = s + (gx * gx + gy * gy);
     }
-    return sqrt(s);
+    return s;
+}
+
+__device__ __forceinline__ double grad_mag(const float* __restrict__ lab, int W, int H, int x, int y) {
+    return sqrt(grad_sq(lab, W, H, x, y));
 }
 
 __global__ __launch_bounds__(256) void k_gradient_max(const float* __restrict__ lab, int W, int H,
@@ -66,8 +70,10 @@ __global__ __launch_bounds__(256) void k_gradient_max(const float* __restrict__ 
     __shared__ unsigned long long red[256];
     unsigned long long m = 0;
     FOR_PIXELS(W, H) {
-        // magnitudes are >= 0, so their FP64 bit patterns order like the values
-        const unsigned long long b = (unsigned long long)__double_as_longlong(grad_mag(lab, W, H, x, y));
+        // squared magnitudes are >= 0, so their FP64 bit patterns order like
+        // the values; the correctly rounded square root is monotone, so the
+        // root of the largest square is the largest magnitude
+        const unsigned long long b = (unsigned long long)__double_as_longlong(grad_sq(lab, W, H, x, y));
         m = b > m ? b : m;
     }
     red[threadIdx.x] = m;
@@ -78,11 +84,24 @@ __global__ __launch_bounds__(256) void k_gradient_max(const float* __restrict__ 
                                                                        : red[threadIdx.x + h];
         __syncthreads();
     }
-    // most blocks find a maximum below what an earlier block has stored:
-    // only a larger value goes to the atomic (a stale read only costs an
-    // atomic that changes nothing)
-    if (threadIdx.x == 0 && red[0] > *reinterpret_cast<volatile unsigned long long*>(mx))
-        atomicMax(mx, red[0]);
+    // one of kGradSlots words per block; only a value above what the slot
+    // holds goes to the atomic (a stale read only costs an atomic that
+    // changes nothing)
+    unsigned long long* slot = mx + (blockIdx.y * gridDim.x + blockIdx.x) % kGradSlots * kGradStride;
+    if (threadIdx.x == 0 && red[0] > *reinterpret_cast<volatile unsigned long long*>(slot))
+        atomicMax(slot, red[0]);
+}
+
+// Largest of the kGradSlots partial maxima, reduced within each wave (every
+// wave of the reader computes the same value).
+__device__ __forceinline__ double grad_max_of(const unsigned long long* __restrict__ mx) {
+    const int lane = threadIdx.x & 63;
+    unsigned long long v = lane < kGradSlots ? mx[lane * kGradStride] : 0ULL;
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long w = __shfl_xor(v, o, 64);
+        v = w > v ? w : v;
+    }
+    return sqrt(__longlong_as_double((long long)v));
 }
 
 // Contour value of pixel p as the standalone map stores it (FP32).
@@ -95,7 +114,7 @@ __global__ __launch_bounds__(256) void k_gradient_normalise(const float* __restr
                                                             int H,
                                                             const unsigned long long* __restrict__ mx,
                                                             float* __restrict__ out) {
-    const double m = __longlong_as_double((long long)*mx);
+    const double m = grad_max_of(mx);
     FOR_PIXELS(W, H) out[(long long)y * W + x] = contour_at(lab, W, H, x, y, m);
 }
 
@@ -103,7 +122,7 @@ __global__ __launch_bounds__(256) void k_prepare_gradient(const float* __restric
                                                           int H, float sigma,
                                                           const unsigned long long* __restrict__ mx,
                                                           float4* __restrict__ packed) {
-    const double m = __longlong_as_double((long long)*mx);
+    const double m = grad_max_of(mx);
     const double s2 = (double)sigma * (double)sigma;
     FOR_PIXELS(W, H) {
         const long long p = (long long)y * W + x;
@@ -113,7 +132,9 @@ __global__ __launch_bounds__(256) void k_prepare_gradient(const float* __restric
     }
 }
 
-__global__ void k_zero_u64(unsigned long long* p) { *p = 0ULL; }
+__global__ void k_zero_slots(unsigned long long* p) {
+    if (threadIdx.x < kGradSlots) p[threadIdx.x * kGradStride] = 0ULL;
+}
 
 // About 2048 blocks of 256 threads: whole rows, the row stride set by the grid height.
 dim3 grid_for(int W, int H) {
@@ -131,7 +152,7 @@ int launch_boundary_frequency(int W, int H, int n, const int* labels, float* out
 
 int launch_contour_from_lab(int W, int H, const float* lab, float* out, void* ws, hipStream_t s) {
     unsigned long long* mx = static_cast<unsigned long long*>(ws);
-    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, mx);
+    hipLaunchKernelGGL(k_zero_slots, dim3(1), dim3(64), 0, s, mx);
     const dim3 b = grid_for(W, H);
     hipLaunchKernelGGL(k_gradient_max, dim3(b), dim3(256), 0, s, lab, W, H, mx);
     hipLaunchKernelGGL(k_gradient_normalise, dim3(b), dim3(256), 0, s, lab, W, H, mx, out);
@@ -140,7 +161,7 @@ int launch_contour_from_lab(int W, int H, const float* lab, float* out, void* ws
 
 int launch_prepare_gradient(int W, int H, const float* lab, float sigma, float4* packed,
                             unsigned long long* mx, hipStream_t s) {
-    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, mx);
+    hipLaunchKernelGGL(k_zero_slots, dim3(1), dim3(64), 0, s, mx);
     const dim3 b = grid_for(W, H);
     hipLaunchKernelGGL(k_gradient_max, dim3(b), dim3(256), 0, s, lab, W, H, mx);
     hipLaunchKernelGGL(k_prepare_gradient, dim3(b), dim3(256), 0, s, lab, W, H, sigma, mx, packed);

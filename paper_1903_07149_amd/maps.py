@@ -29,8 +29,8 @@ def contour_from_lab(lab: torch.Tensor, stream=None) -> torch.Tensor:
     lab = lab.contiguous()
     H, W, _ = lab.shape
     out = torch.empty((H, W), dtype=torch.float32, device=lab.device)
-    ws = torch.empty(256, dtype=torch.uint8, device=lab.device)
-    L.check(L.lib().scalp_contour_from_lab(W, H, _p(lab), _p(out), _p(ws), ctypes.c_size_t(256),
+    ws = torch.empty(4096, dtype=torch.uint8, device=lab.device)
+    L.check(L.lib().scalp_contour_from_lab(W, H, _p(lab), _p(out), _p(ws), ctypes.c_size_t(4096),
                                            _s(stream)), "scalp_contour_from_lab")
     return out
 

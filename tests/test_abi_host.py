@@ -149,5 +149,6 @@ def test_metrics_and_maps_validate_on_host():
     assert lib.scalp_boundary_map(5, 5, fake, 0, out, None) == L.SCALP_ERR_ARG
     assert lib.scalp_boundary_map(5, 5, None, 2, out, None) == L.SCALP_ERR_ARG
     assert lib.scalp_contour_from_lab(5, 5, fake, out, fake, 4, None) == L.SCALP_ERR_WORKSPACE
+    assert lib.scalp_contour_from_lab(5, 5, fake, out, fake, 4095, None) == L.SCALP_ERR_WORKSPACE
     assert lib.scalp_contour_from_lab(5, 0, fake, out, fake, 8, None) == L.SCALP_ERR_ARG
     assert lib.scalp_contour_from_lab(5, 5, None, out, fake, 8, None) == L.SCALP_ERR_ARG
