@@ -12,7 +12,10 @@
 //                     discrete line (Sec. II-B) from its pixel to the endpoint
 //                     over the table, accumulating Eq. (1)'s colour term and
 //                     Eq. (2)'s contour term in a fixed FP32 order, forms D of
-//                     Eq. (3) and keeps the first strict minimum.  With ACCUM
+//                     Eq. (3) and keeps the first strict minimum.  A lane
+//                     skips the walk of a candidate whose exact lower bound
+//                     on D (colour at the pixel and spatial term only) cannot
+//                     win, which leaves the labels unchanged.  With ACCUM
 //                     the update's sums are fused in: each pixel can only
 //                     choose among the cell's 9 candidates, so they reduce
 //                     into 9 LDS bins and leave the workgroup as at most 54
@@ -61,7 +64,17 @@ struct CellShared {
 // over its spl slices (spl is chosen on the host so that no slice has more
 // than WG pixels), and every wave keeps an 8x8 block.
 //
-// Candidates are taken one at a time (ascending slot, hence ascending k).
+// Candidates are taken one at a time, the pixel's own cell first, then the
+// four edge neighbours, then the corners; the winner is the smallest
+// (D, slot) pair, which is the first strict minimum in ascending slot (hence
+// ascending k) whatever the visiting order.  A lane skips a candidate whose
+// lower bound fl(fl(lambda dcp) + fl(ds spw)) cannot beat the current best
+// pair: with lambda in [0, 1], gamma >= 0 and every colour distance and w
+// non-negative, A >= fl(lambda dcp) and B >= 1 in Eqs. (1)-(2), so
+// D = fl(fl(A B) + fl(ds spw)) is at least that bound (FP32 rounding is
+// monotone) and the skipped D could not have been chosen.  The labels are
+// those of evaluating every candidate; a wave skips the walk when all of its
+// lanes do (a NaN bound never skips).
 // For candidate j the workgroup first writes, for every texel q of the
 // rectangle spanned by the item's pixels and j's endpoint (every path to j
 // lies inside it), the pair (d_c(q, j), w_q) into an LDS table; lanes then
@@ -147,8 +160,12 @@ __device__ __forceinline__ void process_cell(const Img& im, int cell, int slice,
     float best = INFINITY;
     int bestj = -1;
     int buf = 0;
+    // the pixel's own texel, for the lower bounds
+    const float4 fown = mine ? img[(long long)y * W + x] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    constexpr unsigned long long kOrder = 0x862075314ULL;   // slots 4, 1, 3, 5, 7, 0, 2, 6, 8
 #pragma unroll 1
-    for (int j = 0; j < 9; ++j) {
+    for (int t = 0; t < 9; ++t) {
+        const int j = (int)((kOrder >> (4 * t)) & 15ULL);
         const int k = sh.cand[j].k;
         if (k < 0) continue;                       // uniform
         const float l = sh.cand[j].l, a = sh.cand[j].a, b = sh.cand[j].b;
@@ -162,7 +179,11 @@ __device__ __forceinline__ void process_cell(const Img& im, int cell, int slice,
         }
         const float ccx = sh.cand[j].x, ccy = sh.cand[j].y;
         const float dcc = sh.cand[j].dcc, wc = sh.cand[j].wc;
-        if (mine) {
+        const float ex = (float)x - ccx;
+        const float ey = (float)y - ccy;
+        const float ds = ex * ex + ey * ey;
+        const float lb = lambda * colour_dist(fown, l, a, b) + ds * spw;   // <= D
+        if (mine && !(lb > best || (lb == best && j > bestj))) {
             const int dx = cx - x, dy = cy - y;
             const int adx = dx < 0 ? -dx : dx, ady = dy < 0 ? -dy : dy;
             const int n = adx > ady ? adx : ady;
@@ -191,11 +212,8 @@ __device__ __forceinline__ void process_cell(const Img& im, int cell, int slice,
             div_path_len(sc, sw, n, inv, qc, qw);
             const float A = lambda * dcp + oml * qc;             // Eq. (1)
             const float B = 1.0f + gamma * qw;                   // Eq. (2)
-            const float ex = (float)x - ccx;
-            const float ey = (float)y - ccy;
-            const float ds = ex * ex + ey * ey;
             const float D = A * B + ds * spw;                    // Eq. (3)
-            if (D < best) {
+            if (D < best || (D == best && j < bestj)) {
                 best = D;
                 bestj = j;
             }
