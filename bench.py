@@ -49,6 +49,7 @@ LDS_PEAK_TBPS = 107.5
 
 EXTENSIONS = ("batched", "soft", "window_form", "multiscale", "contour_prior", "quality")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "assign_hd_traffic.json")
+ISSUE_FILE = os.path.join(ROOT, "profiles", "assign_hd_sq.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1903_07149_amd", "csrc", f)
                   for f in ("scalp_kernels.hip", "scalp_device.h")]
 
@@ -95,6 +96,20 @@ def traffic_for(digest: str):
     if t.get("kernel_source_sha256_16") != digest:
         return None
     return t.get("bytes_per_launch")
+
+
+def issue_for(digest: str):
+    """VALU and LDS wave instructions per launch of the assignment kernel
+    from the committed SQ counter record, if it was taken on the current
+    kernel source."""
+    try:
+        with open(ISSUE_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256_16") != digest:
+        return None
+    return t
 
 
 def bench_hard(torch, args):
@@ -202,6 +217,15 @@ def bench_hard(torch, args):
         "lds_peak_TBps": round(LDS_PEAK_TBPS, 1),
         "kernel_source_sha256_16": digest,
     }
+    # achieved/frac count the work the method defines (every candidate's
+    # path); the kernel walks only the candidates whose exact lower bound can
+    # still win, so the work it executes comes from the SQ counters
+    issue = issue_for(digest)
+    if issue is not None:
+        ops = 64 * issue["valu_insts_per_dispatch"]
+        roofline["executed_valu_lane_ops_per_launch"] = int(ops)
+        roofline["executed_TOPs"] = round(ops / (kern_s / iters) / 1e12, 3)
+        roofline["executed_frac"] = round(ops / (kern_s / iters) / 1e12 / VALU_FP32_PEAK_TFLOPS, 4)
     log(f"hard: {ms_step:.3f} ms/step graph, {eager_ms:.3f} ms/step eager with events, wall {wall:.2f}s")
     if args.copy_probe:
         src = torch.empty(512 * 2**20, dtype=torch.uint8, device="cuda")

@@ -151,6 +151,38 @@ def test_assign_parameters(orc, lam, gamma):
     assert (lbl == ol).all()
 
 
+@pytest.mark.parametrize("lam,gamma,m", [(0.5, 0.0, 10.0), (1.0, 0.0, 0.0), (0.5, 5.0, 0.0),
+                                         (0.0, 3.0, 10.0)])
+def test_assign_exact_ties(orc, lam, gamma, m):
+    """Two flat colours and centres at the cell middles, so that many pixels
+    tie exactly between candidates (equal colour distance and mirrored
+    spatial distance) and the colour-plus-spatial lower bound often equals D:
+    the first strict minimum in ascending k must come out whatever order the
+    kernel visits the candidates in and whichever it skips."""
+    W, H, k = 96, 64, 24                        # 6 x 4 cells of 16 x 16
+    g = orc.grid(W, H, k)
+    rng = np.random.default_rng(17)
+    pick = np.kron(rng.integers(0, 2, (H // 8, W // 8)), np.ones((8, 8), np.int64))
+    colours = np.array([[40.0, 10.0, -5.0], [60.0, -20.0, 15.0]], np.float32)
+    lab = np.ascontiguousarray(colours[pick], dtype=np.float32)
+    contour = np.zeros((H, W), np.float32)
+    contour[:, 40:42] = 0.5
+    c = np.zeros((g.num_sp, 5), np.float32)
+    e = np.zeros((g.num_sp, 2), np.int32)
+    for kk in range(g.num_sp):
+        i, j = divmod(kk, g.nx)
+        c[kk, :3] = colours[(i + j) % 2]
+        c[kk, 3] = 16 * j + 7.5
+        c[kk, 4] = 16 * i + 7.5
+        e[kk] = (16 * j + 8, 16 * i + 8)
+    s = _scalp(W, H, k, lam=lam, gamma=gamma, m=m)
+    say("assign exact ties", lam, gamma, m)
+    lbl = host(s.assign(dev(lab), dev(contour), dev(c), dev(e)))
+    ol, _, _ = orc.assign(g, lab, orc.wmap(contour), c, e, lam=lam, gamma=gamma,
+                          spw=orc.spatial_weight(g, m))
+    assert (lbl == ol).all(), f"{int((lbl != ol).sum())} labels differ"
+
+
 @pytest.mark.parametrize("W,H,k", [(97, 61, 30), (481, 321, 250), (64, 64, 4096), (300, 200, 2)])
 def test_update_bit_exact(orc, W, H, k):
     img = _image(W, H, 5)
