@@ -13,6 +13,11 @@ Also reported on the same JSON line:
                 HIP events around every launch in a second loop of the same
                 steps launched kernel by kernel (eager_ms_per_step), against
                 the FP32 VALU issue peak for non-fused, non-packed operations;
+                with the executed VALU work from the committed SQ counter
+                record while the kernel source matches it;
+  without_pruning  the same step with every candidate's path walked
+                (exact_pruning = 0, same labels): its rate, the kernel's
+                average launch time and that roofline fraction;
   cpu_baseline  the plain C oracle timed on this host's cores on the same
                 workload;
   extensions    the ragged 64-image batch in one persistent launch per
@@ -193,6 +198,38 @@ def bench_hard(torch, args):
     per_it = [sum(evs[k][it][0].elapsed_time(evs[k][it][1]) for k in range(args.steps)) / args.steps
               for it in range(iters)]
 
+    # the same step with every candidate's path walked (exact_pruning = 0;
+    # the labels are the same): graph replays, then HIP events around each
+    # assignment launch
+    gr0 = s.graph(c, e, l, n, exact_pruning=0)
+    for _ in range(args.warmup):
+        s.init_grid(lab, con, out=(c, e, l))
+        gr0.launch()
+    torch.cuda.synchronize()
+    u0 = torch.cuda.Event(enable_timing=True)
+    u1 = torch.cuda.Event(enable_timing=True)
+    u0.record()
+    for _ in range(args.steps):
+        s.init_grid(lab, con, out=(c, e, l))
+        gr0.launch()
+    u1.record()
+    torch.cuda.synchronize()
+    ms_step0 = u0.elapsed_time(u1) / args.steps
+    gr0.close()
+    passes0 = 3
+    ev0 = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)]
+            for _ in range(iters)] for _ in range(passes0)]
+    for q in range(passes0):
+        s.init_grid(lab, con, out=(c, e, l))
+        for it in range(iters):
+            ev0[q][it][0].record()
+            s.assign_accumulate(c, e, l, exact_pruning=0)
+            ev0[q][it][1].record()
+            s.finalize(l, c, e, n, exact_pruning=0)
+    torch.cuda.synchronize()
+    kern0_s = sum(ev0[q][it][0].elapsed_time(ev0[q][it][1]) for q in range(passes0)
+                  for it in range(iters)) / passes0 * 1e-3
+
     N = W * H
     value = N * iters / (ms_step * 1e-3) / 1e6
     flops = sum(w["flops"] for w in work)
@@ -226,7 +263,14 @@ def bench_hard(torch, args):
         roofline["executed_valu_lane_ops_per_launch"] = int(ops)
         roofline["executed_TOPs"] = round(ops / (kern_s / iters) / 1e12, 3)
         roofline["executed_frac"] = round(ops / (kern_s / iters) / 1e12 / VALU_FP32_PEAK_TFLOPS, 4)
-    log(f"hard: {ms_step:.3f} ms/step graph, {eager_ms:.3f} ms/step eager with events, wall {wall:.2f}s")
+    without_pruning = {
+        "value": round(N * iters / (ms_step0 * 1e-3) / 1e6, 1),
+        "ms_per_step": round(ms_step0, 4),
+        "avg_launch_ms": round(kern0_s * 1e3 / iters, 4),
+        "frac": round(flops / kern0_s / 1e12 / VALU_FP32_PEAK_TFLOPS, 4),
+    }
+    log(f"hard: {ms_step:.3f} ms/step graph, {eager_ms:.3f} ms/step eager with events, "
+        f"{ms_step0:.3f} ms/step without pruning, wall {wall:.2f}s")
     if args.copy_probe:
         src = torch.empty(512 * 2**20, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
@@ -237,6 +281,7 @@ def bench_hard(torch, args):
     return img, tuned, {
         "value": value, "ms_per_step": ms_step, "eager_ms_per_step": eager_ms,
         "eager_value": N * iters / (eager_ms * 1e-3) / 1e6, "roofline": roofline,
+        "without_pruning": without_pruning,
         "config": {"workload": wl.name, "width": W, "height": H, "k": wl.k,
                    "num_sp": s.grid.num_sp, "iterations": iters, "launch": tuned,
                    "step": "pack + grid init (eager) + 10 x (fused assign/update, finalize/projection) "
@@ -568,6 +613,7 @@ def main():
         "config": hard["config"], "roofline": hard["roofline"],
         "eager_ms_per_step": round(hard["eager_ms_per_step"], 4),
         "eager_value": round(hard["eager_value"], 1),
+        "without_pruning": hard["without_pruning"],
     }
     if not args.no_extensions:
         runs = [("batched", lambda: bench_batched(torch, args, tuned)),

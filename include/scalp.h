@@ -82,6 +82,13 @@ typedef struct {
                                 SCALP_ASSIGN_WINDOW, see below               */
     int32_t contour_source;  /* SCALP_CONTOUR_INPUT (default) or
                                 SCALP_CONTOUR_GRADIENT, see below            */
+    int32_t exact_pruning;   /* 1 (default): the 3x3 assignment skips the path
+                                walk of a candidate whose exact FP32 lower
+                                bound of D (lambda dcp + spatial term of
+                                Eq. (3)) cannot beat the best so far; 0:
+                                every candidate is walked.  The labels are
+                                the same either way; 0 or 1, else
+                                SCALP_ERR_ARG                                */
 } scalp_params_t;
 
 /* Candidate rule of the assignment.

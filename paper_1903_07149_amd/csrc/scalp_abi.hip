@@ -45,6 +45,7 @@ bool params_valid(const scalp_params_t* p) {
         return false;
     if (p->contour_source != SCALP_CONTOUR_INPUT && p->contour_source != SCALP_CONTOUR_GRADIENT)
         return false;
+    if (p->exact_pruning != 0 && p->exact_pruning != 1) return false;
     return true;
 }
 
@@ -82,7 +83,7 @@ Img img_of(const scalp_grid_t* g, const scalp_params_t* p, long long pix, int sp
     im.gamma = p->gamma < 0.0f ? (float)(2.0 * r) : p->gamma;           // Sec. III-A.3
     im.spl = slices_of(g, tuning_of(p).wg);
     im.rad = (int)std::floor(r + 0.5);
-    im.pad = 0;
+    im.prune = p->exact_pruning;
     return im;
 }
 
@@ -238,6 +239,7 @@ int scalp_default_params(scalp_params_t* out) {
     out->wg_size = 0;
     out->assign_mode = SCALP_ASSIGN_GRID3X3;
     out->contour_source = SCALP_CONTOUR_INPUT;
+    out->exact_pruning = 1;
     return SCALP_OK;
 }
 

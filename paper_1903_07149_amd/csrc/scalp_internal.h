@@ -42,7 +42,7 @@ struct Img {
     float gamma;      // gamma of Eq. (2)
     int spl;          // assignment work items per grid cell (at most WG pixels each)
     int rad;          // R = r rounded to whole pixels (the window form's half-width)
-    int pad;
+    int prune;        // 1: skip the walks that the exact lower bound of D rules out
 };
 
 // An assignment work item has at most as many pixels as its workgroup has

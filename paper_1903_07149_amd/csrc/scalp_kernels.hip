@@ -183,7 +183,7 @@ __device__ __forceinline__ void process_cell(const Img& im, int cell, int slice,
         const float ey = (float)y - ccy;
         const float ds = ex * ex + ey * ey;
         const float lb = lambda * colour_dist(fown, l, a, b) + ds * spw;   // <= D
-        if (mine && !(lb > best || (lb == best && j > bestj))) {
+        if (mine && !(im.prune && (lb > best || (lb == best && j > bestj)))) {
             const int dx = cx - x, dy = cy - y;
             const int adx = dx < 0 ? -dx : dx, ady = dy < 0 ? -dy : dy;
             const int n = adx > ady ? adx : ady;

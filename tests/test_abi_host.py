@@ -101,7 +101,7 @@ def test_mode_parameters_are_validated_on_host():
     args = lambda pr: (ctypes.byref(g), ctypes.byref(pr), fake, fake, fake, fake, fake, fake, ws,
                        None)
     for field, val in [("assign_mode", 2), ("assign_mode", -1), ("contour_source", 2),
-                       ("contour_source", -1)]:
+                       ("contour_source", -1), ("exact_pruning", 2), ("exact_pruning", -1)]:
         pp = L.default_params(**{field: val})
         assert lib.scalp_assign(*args(pp)) == L.SCALP_ERR_ARG, (field, val)
     # a computed contour prior makes the contour pointer optional, a given one does not

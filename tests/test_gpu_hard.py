@@ -276,6 +276,12 @@ def test_run_hd_workload(orc):
     _compare_runs(orc, synth.workload_image(synth.HD), synth.HD.k, synth.HD.iterations)
 
 
+def test_run_bsd_shape_without_pruning(orc):
+    """Every candidate walked (exact_pruning = 0): the same labels, centres and
+    endpoints as the oracle, like the pruned default."""
+    _compare_runs(orc, synth.workload_image(synth.BSD_SHAPE), 250, 10, exact_pruning=0)
+
+
 def test_run_uhd_workload(orc):
     _compare_runs(orc, synth.workload_image(synth.UHD), synth.UHD.k, synth.UHD.iterations)
 
