@@ -603,24 +603,29 @@ __global__ void k_finalize_batched(const Img* __restrict__ imgs, const int* __re
 
 // ---------------------------------------------------------------- projection
 
+// Minimum key and member count over the workgroup: shuffles within each
+// wave, then one LDS slot per wave (two barriers in all).
 template <int WG>
 __device__ __forceinline__ void block_min_sum(unsigned long long& key, int& cnt) {
-    __shared__ unsigned long long rk[WG];
-    __shared__ int rc[WG];
-    const int tid = threadIdx.x;
-    rk[tid] = key;
-    rc[tid] = cnt;
-    __syncthreads();
-    for (int h = WG / 2; h > 0; h >>= 1) {
-        if (tid < h) {
-            rk[tid] = rk[tid] < rk[tid + h] ? rk[tid] : rk[tid + h];
-            rc[tid] += rc[tid + h];
-        }
-        __syncthreads();
+    __shared__ unsigned long long rk[WG / 64];
+    __shared__ int rc[WG / 64];
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long k2 = __shfl_xor(key, o, 64);
+        key = k2 < key ? k2 : key;
+        cnt += __shfl_xor(cnt, o, 64);
     }
+    if ((threadIdx.x & 63) == 0) {
+        rk[threadIdx.x >> 6] = key;
+        rc[threadIdx.x >> 6] = cnt;
+    }
+    __syncthreads();
     key = rk[0];
     cnt = rc[0];
-    __syncthreads();
+    for (int q = 1; q < WG / 64; ++q) {
+        key = rk[q] < key ? rk[q] : key;
+        cnt += rc[q];
+    }
+    __syncthreads();   // the slots are reused by the next reduction
 }
 
 // Squared FP32 distance to (xk, yk) in the high word, raster index in the
