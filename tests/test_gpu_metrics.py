@@ -53,6 +53,23 @@ def test_boundary_recall_far_and_across_words(eps):
     assert got["sp_boundary"] == int(M.boundary(sp).sum())
 
 
+def test_metrics_with_more_pairs_than_the_lds_table():
+    """Per-pixel random labels and regions: a 256-column block of a few rows
+    meets far more than 512 distinct (superpixel, region) pairs, so most of
+    them overflow the workgroup's LDS pair table and go to global memory
+    directly."""
+    from paper_1903_07149_amd.metrics import metrics
+    rng = np.random.default_rng(23)
+    H, W, K, R = 1100, 2048, 5000, 300          # blocks of 256 columns x 8 rows
+    sp = rng.integers(0, K, (H, W)).astype(np.int32)
+    gt = rng.integers(0, R, (H, W)).astype(np.int32)
+    say("metrics overflow", H, W, K, R)
+    got = metrics(dev(sp), dev(gt), num_sp=K, num_regions=R, epsilon=2.0)
+    ref = M.all_metrics(sp, gt, 2.0)
+    assert got["br"] == ref["br"] and got["asa"] == ref["asa"] and got["ue"] == ref["ue"]
+    assert abs(got["co"] - ref["co"]) <= 1e-12 * max(1.0, ref["co"])
+
+
 def test_boundary_recall_at_the_tolerance():
     """Offsets at exactly epsilon do not count (the oracle's closed-form case)."""
     from paper_1903_07149_amd.metrics import metrics
