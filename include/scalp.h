@@ -85,8 +85,10 @@ typedef struct {
     int32_t exact_pruning;   /* 1 (default): the 3x3 assignment skips the path
                                 walk of a candidate whose exact FP32 lower
                                 bound of D (lambda dcp + spatial term of
-                                Eq. (3)) cannot beat the best so far; 0:
-                                every candidate is walked.  The labels are
+                                Eq. (3)) cannot beat the best so far, and the
+                                soft forward skips the walk of a slot whose
+                                softmax weight that bound proves to be 0; 0:
+                                every candidate is walked.  The results are
                                 the same either way; 0 or 1, else
                                 SCALP_ERR_ARG                                */
 } scalp_params_t;

@@ -642,7 +642,8 @@ int scalp_soft_forward(const scalp_grid_t* g, const scalp_params_t* p, float tem
     const int T = p->iterations;
     const Img im = img_of(g, p, 0, 0);
     const SoftGeom geo = soft_geom(g->width, g->height, g->nx, g->ny, batch, im.spw, im.gamma,
-                                   p->lambda, temperature, tuning_of(p).wg);
+                                   p->lambda, temperature, tuning_of(p).wg,
+                                   p->exact_pruning);
     const SoftSaved S = soft_saved_layout(g, B, T);
     char* wb = static_cast<char*>(ws);
     char* sb = static_cast<char*>(saved);
@@ -684,7 +685,8 @@ int scalp_soft_backward(const scalp_grid_t* g, const scalp_params_t* p, float te
     const int T = p->iterations;
     const Img im = img_of(g, p, 0, 0);
     const SoftGeom geo = soft_geom(g->width, g->height, g->nx, g->ny, batch, im.spw, im.gamma,
-                                   p->lambda, temperature, tuning_of(p).wg);
+                                   p->lambda, temperature, tuning_of(p).wg,
+                                   p->exact_pruning);
     const SoftSaved S = soft_saved_layout(g, B, T);
     char* wb = static_cast<char*>(ws);
     const char* sb = static_cast<const char*>(saved);

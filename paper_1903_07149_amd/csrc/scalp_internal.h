@@ -110,9 +110,10 @@ struct SoftGeom {
     int W, H, nx, ny, B;
     int wg;   // workgroup size of the path kernels (256, 512 or 1024)
     float spw, gamma, lambda, temperature;
+    int prune;  // 1: skip the walks of slots whose softmax weight is provably 0
 };
 SoftGeom soft_geom(int W, int H, int nx, int ny, int B, float spw, float gamma, float lambda,
-                   float temperature, int wg);
+                   float temperature, int wg, int prune);
 void lift_soft_lds_limits();
 // Work items per cell of the soft assignment at workgroup size wg: a cell
 // is cut into slices of whole 64-pixel chunks, at most wg pixels each.

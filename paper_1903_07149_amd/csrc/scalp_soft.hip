@@ -40,6 +40,7 @@ struct SoftImg {
     long long N;
     float spw, gamma, lambda, inv_t;
     double temp;
+    int prune;   // 1: skip the walks of slots whose softmax weight is provably 0
 };
 
 // A superpixel whose soft mass is below a millionth of a pixel counts as
@@ -206,8 +207,21 @@ __global__ __launch_bounds__(WG) void k_soft_assign(SoftImg s, const float4* __r
     const float lambda = s.lambda, oml = 1.0f - lambda;
     const long long base = 9LL * s.N * b + p;
     int buf = 0;
+    // Exact pruning: D >= LB = fl(fl(lambda dcp) + fl(ds spw)) (the hard
+    // kernel's bound), and the softmax gives a slot Q = 0 exactly when
+    // (D - Dmin) / T > 110 in FP64; Dmin <= best, the smallest D computed so
+    // far, and both FP64 steps are monotone, so a slot with
+    // (LB - best) / T > 110 gets Q = 0 whatever its walk would give: its D is
+    // written as +inf (the softmax maps it to 0) and its saved factors as 0
+    // (the backward reads them only where dL/dD, a multiple of Q, is not 0).
+    // The own cell is visited first, then the edge neighbours, then the
+    // corners; each slot is written separately, so the order changes nothing.
+    const float4 fown = mine ? img[p] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    float best = INFINITY;
+    constexpr unsigned long long kOrder = 0x862075314ULL;   // slots 4, 1, 3, 5, 7, 0, 2, 6, 8
 #pragma unroll 1
-    for (int j = 0; j < 9; ++j) {
+    for (int t = 0; t < 9; ++t) {
+        const int j = (int)((kOrder >> (4 * t)) & 15ULL);
         const int k = sh.cand[j].k;
         const long long o = base + (long long)j * s.N;
         if (k < 0) {                                            // uniform
@@ -230,6 +244,15 @@ __global__ __launch_bounds__(WG) void k_soft_assign(SoftImg s, const float4* __r
         if (!mine) continue;
         const float dcc = sh.cand[j].dcc, wc = sh.cand[j].wc;
         const float ccx = sh.cand[j].x, ccy = sh.cand[j].y;
+        const float ex = (float)x - ccx, ey = (float)y - ccy;
+        const float ds = ex * ex + ey * ey;
+        const float lb = lambda * colour_dist(fown, l, a, bb) + ds * s.spw;
+        if (s.prune && ((double)lb - (double)best) / s.temp > 110.0) {
+            q[o] = INFINITY;
+            fa[o] = 0.0f;
+            fb[o] = 0.0f;
+            continue;
+        }
         const int dx = cx - x, dy = cy - y;
         const int adx = dx < 0 ? -dx : dx, ady = dy < 0 ? -dy : dy;
         const int n = adx > ady ? adx : ady;
@@ -257,8 +280,8 @@ __global__ __launch_bounds__(WG) void k_soft_assign(SoftImg s, const float4* __r
         div_path_len(sc, sw, n, inv, qc, qw);
         const float A = lambda * dcp + oml * qc;
         const float Bw = 1.0f + s.gamma * qw;
-        const float ex = (float)x - ccx, ey = (float)y - ccy;
-        const float D = A * Bw + (ex * ex + ey * ey) * s.spw;
+        const float D = A * Bw + ds * s.spw;
+        best = fminf(best, D);
         // D goes to the Q buffer (k_soft_softmax turns it into Q); A and B
         // go straight to the saved factors
         q[o] = D;
@@ -829,10 +852,11 @@ unsigned grid_for(long long n) {
 }  // namespace
 
 SoftGeom soft_geom(int W, int H, int nx, int ny, int B, float spw, float gamma, float lambda,
-                   float temperature, int wg) {
+                   float temperature, int wg, int prune) {
     SoftGeom g;
     g.W = W; g.H = H; g.nx = nx; g.ny = ny; g.B = B; g.wg = wg;
     g.spw = spw; g.gamma = gamma; g.lambda = lambda; g.temperature = temperature;
+    g.prune = prune;
     return g;
 }
 
@@ -856,6 +880,7 @@ static SoftImg to_img(const SoftGeom& g) {
     s.spl = soft_slices(g.W, g.H, g.nx, g.ny, g.wg);
     s.spw = g.spw; s.gamma = g.gamma; s.lambda = g.lambda; s.inv_t = 1.0f / g.temperature;
     s.temp = (double)g.temperature;
+    s.prune = g.prune;
     return s;
 }
 

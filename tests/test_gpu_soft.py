@@ -87,6 +87,29 @@ def compare_forward(c_t, q_t, th_o, q_o, W, H):
     return T
 
 
+@pytest.mark.parametrize("T", [0.5, 0.05, 5.0])
+def test_soft_pruning_changes_no_bit(T):
+    """exact_pruning skips only slots whose softmax weight is provably 0: Q
+    and the centres are bit-identical with and without it; the gradients
+    agree to the rounding of the backward's float atomics."""
+    W, H, k, B, iters = 160, 120, 40, 2, 3
+    lab, con = _batch(B, (W, H), 8, 640)
+    outs = []
+    for prune in (1, 0):
+        eng = _engine(W, H, k, B, T, iters, exact_pruning=prune)
+        say("soft pruning", prune, T)
+        L, C = dev(lab), dev(con)
+        c_t, q_t, saved = eng.forward(L, C)
+        gq = torch.from_numpy(np.random.default_rng(5).standard_normal(tuple(q_t[-1].shape)).astype(np.float32)).cuda()
+        gth = torch.from_numpy(np.random.default_rng(6).standard_normal(tuple(c_t[-1].shape)).astype(np.float32)).cuda()
+        glab, gcon = eng.backward(L, C, c_t, q_t, saved, gq, gth)
+        outs.append([host(t) for t in (c_t, q_t, glab, gcon)])
+    for a, b in zip(outs[0][:2], outs[1][:2]):
+        assert np.array_equal(a, b)
+    for a, b in zip(outs[0][2:], outs[1][2:]):
+        assert np.allclose(a, b, rtol=1e-5, atol=1e-6 * max(1.0, float(np.abs(b).max())))
+
+
 @pytest.mark.parametrize("W,H,k,B,T,iters,seed", CASES)
 def test_soft_forward_matches_oracle(orc, W, H, k, B, T, iters, seed):
     lab, con = _batch(B, (W, H), 8, seed)
