@@ -151,6 +151,27 @@ def test_assign_parameters(orc, lam, gamma):
     assert (lbl == ol).all()
 
 
+def test_assign_non_finite_texels(orc):
+    """A few NaN texels: a pixel whose own colour is NaN has no finite D and
+    keeps its own cell; a path through a NaN texel gives a NaN D that never
+    wins; the bound that prunes is NaN exactly when the pixel's own colour is
+    (same labels as the oracle, pruning or not)."""
+    W, H, k = 97, 61, 30
+    img = _image(W, H, 12)
+    g = orc.grid(W, H, k)
+    c, e = perturbed_state(orc, g, img.lab, seed=8, jitter=3.0)
+    lab = img.lab.copy()
+    rng = np.random.default_rng(9)
+    for _ in range(6):
+        lab[rng.integers(0, H), rng.integers(0, W), rng.integers(0, 3)] = np.nan
+    ol, _, _ = orc.assign(g, lab, orc.wmap(img.contour), c, e)
+    for prune in (1, 0):
+        s = _scalp(W, H, k, exact_pruning=prune)
+        say("assign non-finite", prune)
+        lbl = host(s.assign(dev(lab), dev(img.contour), dev(c), dev(e)))
+        assert (lbl == ol).all(), f"{int((lbl != ol).sum())} labels differ"
+
+
 @pytest.mark.parametrize("lam,gamma,m", [(0.5, 0.0, 10.0), (1.0, 0.0, 0.0), (0.5, 5.0, 0.0),
                                          (0.0, 3.0, 10.0)])
 def test_assign_exact_ties(orc, lam, gamma, m):
