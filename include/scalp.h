@@ -97,12 +97,12 @@ typedef struct {
  *   SCALP_ASSIGN_GRID3X3: every pixel compares the superpixels of the 3x3 grid
  *     cells around its own cell (pixel-centric; labels are always grid
  *     neighbours).
- *   SCALP_ASSIGN_WINDOW: Algorithm 1 as written: every superpixel k compares
- *     itself with the pixels of a (2R+1) x (2R+1) window centred on its
- *     rounded barycenter, R = r rounded to a whole pixel; a pixel takes the
- *     first strict minimum in ascending k over the windows covering it and
- *     keeps its previous label where no window covers it (labels are then
- *     in/out for scalp_assign).  Single-image entry points only. */
+ *   SCALP_ASSIGN_WINDOW: the window rule of Algorithm 1: the candidates of a
+ *     pixel are the superpixels whose (2R+1) x (2R+1) window, centred on the
+ *     rounded barycenter with R = r rounded to a whole pixel, contains it; a
+ *     pixel takes the smallest D over them (the smallest k among equal D)
+ *     and keeps its previous label where no window contains it (labels are
+ *     then in/out for scalp_assign).  Single-image entry points only. */
 enum { SCALP_ASSIGN_GRID3X3 = 0, SCALP_ASSIGN_WINDOW = 1 };
 
 /* Where the contour prior C of Sec. II-D comes from when an entry point packs

@@ -235,42 +235,56 @@ int orc_window_radius(int W, int H, int k) {
     return (int)floor(orc_grid_r(W, H, k) + 0.5);
 }
 
-/* Algorithm 1 as written: d <- infinity; for each cluster k in ascending
- * order, for each pixel p of the window of half-width R centred on the
- * rounded barycenter of k, compute D(p, C_k) along the path to k's endpoint
- * and keep it if strictly smaller than d(p).  Pixels no window covers keep
- * the label they had (labels is in/out). */
+/* The window form of the candidate rule (Algorithm 1): cluster k is a
+ * candidate of pixel p when p lies in k's window, the square of half-width R
+ * centred on k's barycenter rounded to a pixel (clamped into the image).
+ * Each pixel takes the candidate with the smallest D(p, C_k) of Eq. (3)
+ * (path to k's endpoint), the smallest k among equal distances; a pixel that
+ * no window contains keeps the label it had (labels is in/out).  best_out
+ * receives that smallest D (+infinity where no window contains the pixel).
+ * Per image row, the clusters whose window spans the row are listed first in
+ * ascending k; each pixel of the row then tests the column range of each. */
 void orc_assign_window(int W, int H, int K, int R, const float *lab, const float *w,
                        const float *centres, const int *endpoints,
                        float lambda, float gamma, float spw, int *labels, float *best_out) {
     hard_ctx c = {W, H, lab, w, lambda, gamma, spw};
-    long N = (long)W * H;
-    float *d = malloc(sizeof(float) * (size_t)N);
-    for (long p = 0; p < N; p++) d[p] = INFINITY;
+    int *wx = malloc(sizeof(int) * (size_t)K), *wy = malloc(sizeof(int) * (size_t)K);
     for (int k = 0; k < K; k++) {
-        const float *ck = centres + 5 * (long)k;
-        int wx = (int)floorf(ck[3] + 0.5f), wy = (int)floorf(ck[4] + 0.5f);
-        if (wx < 0) wx = 0;
-        if (wx > W - 1) wx = W - 1;
-        if (wy < 0) wy = 0;
-        if (wy > H - 1) wy = H - 1;
-        for (int y = wy - R; y <= wy + R; y++) {
-            if (y < 0 || y >= H) continue;
-            for (int x = wx - R; x <= wx + R; x++) {
-                if (x < 0 || x >= W) continue;
-                float D = hard_distance(&c, x, y, ck, endpoints[2 * k], endpoints[2 * k + 1],
-                                        NULL, NULL, NULL);
-                long p = (long)y * W + x;
-                if (D < d[p]) {
-                    d[p] = D;
-                    labels[p] = k;
+        int ex = (int)floorf(centres[5 * (long)k + 3] + 0.5f);
+        int ey = (int)floorf(centres[5 * (long)k + 4] + 0.5f);
+        wx[k] = ex < 0 ? 0 : (ex > W - 1 ? W - 1 : ex);
+        wy[k] = ey < 0 ? 0 : (ey > H - 1 ? H - 1 : ey);
+    }
+    #pragma omp parallel
+    {
+        int *rowk = malloc(sizeof(int) * (size_t)K);
+        #pragma omp for schedule(dynamic, 1)
+        for (int y = 0; y < H; y++) {
+            int nk = 0;
+            for (int k = 0; k < K; k++)
+                if (abs(y - wy[k]) <= R) rowk[nk++] = k;
+            for (int x = 0; x < W; x++) {
+                float best = INFINITY;
+                int bestk = -1;
+                for (int i = 0; i < nk; i++) {
+                    int k = rowk[i];
+                    if (abs(x - wx[k]) > R) continue;
+                    float D = hard_distance(&c, x, y, centres + 5 * (long)k, endpoints[2 * k],
+                                            endpoints[2 * k + 1], NULL, NULL, NULL);
+                    if (D < best) {       /* ascending k: an equal D keeps the first */
+                        best = D;
+                        bestk = k;
+                    }
                 }
+                long p = (long)y * W + x;
+                if (bestk >= 0) labels[p] = bestk;
+                if (best_out) best_out[p] = best;
             }
         }
+        free(rowk);
     }
-    if (best_out)
-        for (long p = 0; p < N; p++) best_out[p] = d[p];
-    free(d);
+    free(wx);
+    free(wy);
 }
 
 /* ------------------------------------------------------------------ */

@@ -77,7 +77,7 @@ int launch_assign(const Img& im, const float4* packed, const float* centres,
                   bool accumulate, const Tuning& t, hipStream_t s);
 int launch_accumulate(const Img& im, const float* lab, const int* labels, long long* acc,
                       hipStream_t s);
-// Window form of the assignment (Algorithm 1 as written); labels in/out.
+// Window form of the assignment (candidate rule of Algorithm 1); labels in/out.
 int launch_assign_window(const Img& im, const float4* packed, const float* centres,
                          const int* endpoints, int* labels, unsigned long long* keys, int R,
                          float lambda, const Tuning& t, hipStream_t s);

@@ -304,12 +304,13 @@ void k_assign_persistent(const Img* __restrict__ imgs,
 
 // ---------------------------------------------------------------- window form
 
-// Algorithm 1 as written: one workgroup per cluster k scans the window of
-// half-width R around k's rounded barycenter, computes D for every pixel of
-// it along the path to k's endpoint, and offers (D, k) to the pixel with a
-// 64-bit atomic minimum of (FP32 bits of D, k): D >= 0, so the minimum is the
-// smallest D and, among equal D, the smallest k, which is exactly the result
-// of visiting clusters in ascending order with a strict "<".
+// Window candidate rule of Algorithm 1: a pixel's candidates are the
+// clusters whose window (half-width R around the rounded barycenter)
+// contains it, and it takes the smallest D of Eq. (3), the smallest k among
+// equal distances.  One workgroup per cluster k scans k's window, computes D
+// for every pixel of it along the path to k's endpoint, and offers (D, k) to
+// the pixel with a 64-bit atomic minimum of (FP32 bits of D, k): D >= 0, so
+// the minimum is the smallest D and, among equal D, the smallest k.
 template <int WG>
 __global__ __launch_bounds__(WG) void k_assign_window(Img im, const float4* __restrict__ packed,
                                                       const float* __restrict__ centres,

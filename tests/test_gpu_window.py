@@ -1,4 +1,4 @@
-"""Window form of the assignment (Algorithm 1 as written) on the GPU against
+"""Window form of the assignment (the candidate rule of Algorithm 1) on the GPU against
 the oracle: one pass bit-exact (labels, with uncovered pixels keeping theirs),
 whole runs bit-exact against the fixed-point-mean oracle and >= 99.9 % label
 agreement against the FP64-mean oracle.  Also reports how far the window form

@@ -32,9 +32,11 @@ MUTATIONS = {
     "projection_ties": (H, "if (d < best) { best = d; bestp = p; }", "if (d <= best) { best = d; bestp = p; }"),
     "cell_rounding": (H, "static int cell_col(int x, int W, int nx) { return (int)(((long)x * nx) / W); }",
                       "static int cell_col(int x, int W, int nx) { return (int)(((long)x * nx + W / 2) / W); }"),
-    "window_off_by_one": (H, "for (int x = wx - R; x <= wx + R; x++) {",
-                          "for (int x = wx - R; x < wx + R; x++) {"),
-    "window_ties_to_last": (H, "                if (D < d[p]) {", "                if (D <= d[p]) {"),
+    "window_off_by_one": (H, "if (abs(x - wx[k]) > R) continue;",
+                          "if (abs(x - wx[k]) >= R) continue;"),
+    "window_rows_off_by_one": (H, "if (abs(y - wy[k]) <= R) rowk[nk++] = k;",
+                               "if (abs(y - wy[k]) < R) rowk[nk++] = k;"),
+    "window_ties_to_last": (H, "if (D < best) {       /* ascending k", "if (D <= best) {       /* ascending k"),
     "soft_bwd_drop_lambda": (S, "gf[3 * p + e] += g * Bw * lambda * dpe;", "gf[3 * p + e] += 0.0 * dpe;"),
     "soft_bwd_drop_gamma": (S, "gw[qix] += g * A * c.gamma / np;", "gw[qix] += g * A / np;"),
     "soft_bwd_softmax_sign": (S, "double g = -(1.0 / T) * Q[9 * p + j] * (gQ[9 * p + j] - dot);",
@@ -52,6 +54,7 @@ WHERE = {
     "projection_ties": ["tests/test_oracle_update.py"],
     "wmap_not_squared": ["tests/test_oracle_wmap.py"],
     "window_off_by_one": ["tests/test_oracle_window.py"],
+    "window_rows_off_by_one": ["tests/test_oracle_window.py"],
     "window_ties_to_last": ["tests/test_oracle_window.py"],
 }
 

@@ -1,6 +1,7 @@
-"""Pins for the oracle's cluster-centric assignment (Algorithm 1 as written:
-every cluster scans a (2r+1) x (2r+1) window around its barycenter, keeps
-strictly smaller distances, and pixels no window covers keep their label)."""
+"""Pins for the oracle's window form of the assignment (the candidate rule of
+Algorithm 1: the candidates of a pixel are the clusters whose (2r+1) x (2r+1)
+window around the barycenter contains it; the smallest D wins, the smallest k
+among equal D, and pixels no window contains keep their label)."""
 import numpy as np
 import pytest
 
