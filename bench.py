@@ -8,13 +8,14 @@ from inputs resident in HBM: pack (l, a, b, w) and grid initialisation
 projection) as one hipGraph replay.
 
 Also reported on the same JSON line:
-  roofline      the fused assignment kernel (the dominant kernel): algorithmic
-                FP32 operations per launch / its average duration, measured with
-                HIP events around every launch in a second loop of the same
-                steps launched kernel by kernel (eager_ms_per_step), against
-                the FP32 VALU issue peak for non-fused, non-packed operations;
-                with the executed VALU work from the committed SQ counter
-                record while the kernel source matches it;
+  roofline      the fused assignment kernel (the dominant kernel): the method's
+                algorithmic FP32 operations per launch / its average duration,
+                measured with HIP events around every launch in a second loop
+                of the same steps launched kernel by kernel
+                (eager_ms_per_step), against the published FP32 peak; beside
+                it, under "binding", what the kernel executes against the
+                resource that binds it (VALU issue, from the committed SQ
+                counter record while the kernel source matches it);
   without_pruning  the same step with every candidate's path walked
                 (exact_pruning = 0, same labels): its rate, the kernel's
                 average launch time and that roofline fraction;
@@ -42,15 +43,21 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Mpixel-iter/s (assign+update) 1080p K=2000; batched and soft fwd+bwd MP/s"
 
-# MI355X: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz issue 39.3 T non-fused,
-# non-packed FP32 operations per second (the published 157.3 TFLOP/s counts a
-# packed FMA as 4 operations per lane slot).
-VALU_FP32_PEAK_TFLOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# MI355X published peaks.  FP32 vector: 157.3 TFLOP/s (256 CUs x 2.4 GHz x
+# 256 FLOP per CU-clock, i.e. 4 SIMDs x 16 lanes issuing a packed FMA that
+# counts as 4 operations); HBM3E: 8 TB/s.
+FP32_PEAK_TFLOPS = 157.3
 HBM_PEAK_GBPS = 8000.0
-# LDS: the conflict-free ds_read_b128 ceiling measured by peaks_probe,
-# 107.5 TB/s (175 B per CU-clock), is the figure the path's LDS rate is set
-# against (it is never the bound: the kernel issues 16 B per ~17 VALU ops).
-LDS_PEAK_TBPS = 107.5
+# VALU issue ceiling derived from the unit counts: each of a CU's 4 SIMDs
+# retires a wave64 VALU instruction every 4 clocks, so one wave64 instruction
+# per CU-clock, 256 x 2.4e9 = 614.4 G instructions/s (39.3 T lane-ops/s).
+# Integer-heavy streams were measured slightly above it (1.19 per CU-clock,
+# profiles/peaks_mi355x.md), so it is a ceiling for FP32 work.
+VALU_ISSUE_PEAK_GINSTS = 256 * 2.4
+# LDS: 256 B per CU-clock on CDNA4 = 157.3 TB/s spec; the conflict-free
+# ds_read_b128 rate measured by peaks_probe is 107.5 TB/s.
+LDS_SPEC_TBPS = 256 * 256 * 2.4e9 / 1e12
+LDS_MEASURED_TBPS = 107.5
 
 EXTENSIONS = ("batched", "soft", "window_form", "multiscale", "contour_prior", "quality")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "assign_hd_traffic.json")
@@ -115,6 +122,31 @@ def issue_for(digest: str):
     if t.get("kernel_source_sha256_16") != digest:
         return None
     return t
+
+
+def binding_resource(issue, launch_s):
+    """What the fused assignment kernel actually executes, against the resource
+    that binds it (VALU issue): wave64 VALU instructions per launch from the
+    committed SQ counter record over the launch time measured in this run,
+    against one instruction per CU-clock; LDS bytes from the LDS instruction
+    count (8 bytes per lane: table reads and writes, bin atomics) against the
+    measured ds_read ceiling.  Marked stale, with no fractions, when the
+    record was taken on other kernel sources."""
+    if issue is None:
+        return {"resource": "VALU issue", "stale": True, "frac": None,
+                "note": "no SQ counter record for the current kernel sources"}
+    insts = issue["valu_insts_per_dispatch"]
+    g_insts = insts / launch_s / 1e9
+    lds_b = 64 * 8 * issue["lds_insts_per_dispatch"]
+    return {"resource": "VALU issue", "stale": False,
+            "valu_insts_per_launch": int(insts),
+            "achieved": round(g_insts, 1), "peak": VALU_ISSUE_PEAK_GINSTS,
+            "unit": "G wave64 VALU instructions/s",
+            "frac": round(g_insts / VALU_ISSUE_PEAK_GINSTS, 4),
+            "lds_bytes_per_launch": int(lds_b),
+            "lds_TBps": round(lds_b / launch_s / 1e12, 2),
+            "lds_frac_of_measured": round(lds_b / launch_s / 1e12 / LDS_MEASURED_TBPS, 4),
+            "counter_record": os.path.relpath(ISSUE_FILE, ROOT)}
 
 
 def bench_hard(torch, args):
@@ -235,39 +267,37 @@ def bench_hard(torch, args):
     flops = sum(w["flops"] for w in work)
     samples = sum(w["samples"] for w in work)
     kern_s = sum(per_it) * 1e-3
+    launch_s = kern_s / iters
     achieved = flops / kern_s / 1e12
     digest = source_digest()
     traffic = traffic_for(digest)
+    # achieved: the method's algorithmic FP32 operations (Eqs. (1)-(3) over
+    # every candidate's path, counted from the endpoints) per launch over the
+    # kernel's measured launch time, against the published FP32 peak
     roofline = {
         "bound": "alu",
         "kernel": f"k_assign<{s.params.wg_size},true> (fused assignment + update sums)",
         "achieved": round(achieved, 3),
-        "peak": round(VALU_FP32_PEAK_TFLOPS, 2),
+        "peak": FP32_PEAK_TFLOPS,
         "unit": "TFLOP/s",
-        "frac": round(achieved / VALU_FP32_PEAK_TFLOPS, 4),
+        "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
         "traffic": traffic,
-        "avg_launch_ms": round(kern_s * 1e3 / iters, 4),
+        "avg_launch_ms": round(launch_s * 1e3, 4),
         "flops_per_launch": flops // iters,
         "samples_per_launch": samples // iters,
         "samples_per_px_iter": round(samples / (N * iters), 2),
         "lds_algorithmic_TBps": round(16 * samples / kern_s / 1e12, 3),
-        "lds_peak_TBps": round(LDS_PEAK_TBPS, 1),
+        "lds_algorithmic_frac": round(16 * samples / kern_s / 1e12 / LDS_SPEC_TBPS, 4),
         "kernel_source_sha256_16": digest,
     }
-    # achieved/frac count the work the method defines (every candidate's
-    # path); the kernel walks only the candidates whose exact lower bound can
-    # still win, so the work it executes comes from the SQ counters
-    issue = issue_for(digest)
-    if issue is not None:
-        ops = 64 * issue["valu_insts_per_dispatch"]
-        roofline["executed_valu_lane_ops_per_launch"] = int(ops)
-        roofline["executed_TOPs"] = round(ops / (kern_s / iters) / 1e12, 3)
-        roofline["executed_frac"] = round(ops / (kern_s / iters) / 1e12 / VALU_FP32_PEAK_TFLOPS, 4)
+    if traffic is not None:
+        roofline["hbm_frac"] = round(traffic / launch_s / 1e9 / HBM_PEAK_GBPS, 4)
+    roofline["binding"] = binding_resource(issue_for(digest), launch_s)
     without_pruning = {
         "value": round(N * iters / (ms_step0 * 1e-3) / 1e6, 1),
         "ms_per_step": round(ms_step0, 4),
         "avg_launch_ms": round(kern0_s * 1e3 / iters, 4),
-        "frac": round(flops / kern0_s / 1e12 / VALU_FP32_PEAK_TFLOPS, 4),
+        "frac": round(flops / kern0_s / 1e12 / FP32_PEAK_TFLOPS, 4),
     }
     log(f"hard: {ms_step:.3f} ms/step graph, {eager_ms:.3f} ms/step eager with events, "
         f"{ms_step0:.3f} ms/step without pruning, wall {wall:.2f}s")

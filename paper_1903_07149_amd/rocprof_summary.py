@@ -4,13 +4,21 @@
   python -m paper_1903_07149_amd.rocprof_summary counters <counter_collection.csv> "<command>"
   python -m paper_1903_07149_amd.rocprof_summary traffic <fetch.csv> <write.csv> <kernel>
          <algorithmic bytes per launch> <source digest> <workload> "<fetch cmd>" "<write cmd>"
+  python -m paper_1903_07149_amd.rocprof_summary derived <sq1.csv> <sq2.csv> <fetch.csv>
+         <write.csv> <kernel substring>[,<kernel substring>...] [first=N] [grid=G]
 
 `stats` lists per-kernel call counts and durations; `counters` lists, per
 kernel, the mean per-dispatch value of every collected counter; `traffic`
 turns one FETCH_SIZE and one WRITE_SIZE run (KiB per dispatch) into HBM bytes
 per launch of <kernel>, each counter scaled by what it reads for the
 512 MiB device copy (`__amd_rocclr_copyBuffer`) of the same run, and prints
-the JSON record the benchmark reads.
+the JSON record the benchmark reads.  `derived` turns two SQ counter passes
+(instruction counts, then wait cycles) and one FETCH_SIZE and one WRITE_SIZE
+pass into per-kernel rates: VALU wave instructions per CU-clock (the issue
+ceiling is one), VALU lane utilisation, LDS instructions and LDS-busy cycles
+per CU-clock, the share of wave cycles spent waiting, and calibrated HBM
+bytes per dispatch (optionally only the first N dispatches, or only the
+dispatches of grid size G).
 """
 from __future__ import annotations
 
@@ -111,9 +119,83 @@ def traffic(fetch_csv: str, write_csv: str, kernel: str, algorithmic: int, diges
             "kernel_source_sha256_16": digest, "commands": [fetch_cmd, write_cmd]}
 
 
+def _per_dispatch_all(path: str, grid: int | None = None) -> dict:
+    """kernel -> counter -> {dispatch: value} (values of one dispatch summed)."""
+    per = defaultdict(lambda: defaultdict(lambda: defaultdict(float)))
+    for r in csv.DictReader(open(path)):
+        cname = r.get("Counter_Name") or r.get("Counter-Name")
+        if cname is None:
+            continue
+        if grid is not None and int(r.get("Grid_Size") or r.get("Grid-Size") or 0) != grid:
+            continue
+        name = _short(r.get("Kernel_Name") or r.get("Kernel-Name") or "")
+        disp = int(r.get("Dispatch_Id") or r.get("Dispatch-Id"))
+        per[name][cname][disp] += float(r.get("Counter_Value") or r.get("Counter-Value"))
+    return per
+
+
+def derived(paths: list[str], kernels: list[str], first: int | None = None,
+            grid: int | None = None) -> tuple[str, dict]:
+    """Mean per-dispatch counters of each kernel matching one of `kernels` and
+    the rates derived from them (see the module docstring)."""
+    merged = defaultdict(dict)
+    copy = {}
+    for path in paths:
+        for name, cs in _per_dispatch_all(path).items():
+            if COPY_KERNEL in name:
+                for c, d in cs.items():
+                    copy[c] = max(d.values())
+        for name, cs in _per_dispatch_all(path, grid).items():
+            key = next((k for k in kernels if k in name), None)
+            if key is None:
+                continue
+            for c, d in cs.items():
+                vals = [d[i] for i in sorted(d)]
+                if first:
+                    vals = vals[:first]
+                merged[key][c] = (sum(vals) / len(vals), len(vals))
+    rows = ["| kernel | dispatches | us (GRBM) | VALU instr | VALU / CU-clk | lane util | "
+            "LDS instr | LDS busy / CU-clk | wait / wave-cycles | VMEM instr | HBM read MB | "
+            "HBM write MB |", "|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    out = {}
+    for k in kernels:
+        cs = merged.get(k)
+        if not cs:
+            continue
+        g = lambda c: cs[c][0] if c in cs else float("nan")
+        cyc = g("GRBM_GUI_ACTIVE") / 8          # summed over the 8 XCDs
+        rd = g("FETCH_SIZE") * 1024 * (COPY_BYTES / 1024 / copy["FETCH_SIZE"]) \
+            if "FETCH_SIZE" in cs and "FETCH_SIZE" in copy else float("nan")
+        wr = g("WRITE_SIZE") * 1024 * (COPY_BYTES / 1024 / copy["WRITE_SIZE"]) \
+            if "WRITE_SIZE" in cs and "WRITE_SIZE" in copy else float("nan")
+        d = {"dispatches": cs.get("SQ_INSTS_VALU", (0, 0))[1],
+             "us": cyc / 2400.0,
+             "valu_insts": g("SQ_INSTS_VALU"),
+             "valu_per_cu_clk": g("SQ_INSTS_VALU") / 256 / cyc,
+             "lane_util": g("SQ_THREAD_CYCLES_VALU") / 64 / g("SQ_ACTIVE_INST_VALU"),
+             "lds_insts": g("SQ_INSTS_LDS"),
+             "lds_busy_per_cu_clk": g("SQ_LDS_IDX_ACTIVE") / 256 / cyc,
+             "wait_frac": g("SQ_WAIT_ANY") / g("SQ_WAVE_CYCLES"),
+             "wait_inst_frac": g("SQ_WAIT_INST_ANY") / g("SQ_WAVE_CYCLES"),
+             "lds_wait_frac": g("SQ_WAIT_INST_LDS") / g("SQ_WAVE_CYCLES"),
+             "vmem_insts": g("SQ_INSTS_VMEM"),
+             "hbm_read_bytes": rd, "hbm_write_bytes": wr}
+        out[k] = d
+        rows.append(f"| `{k}` | {d['dispatches']} | {d['us']:.1f} | {d['valu_insts']:.3e} | "
+                    f"{d['valu_per_cu_clk']:.3f} | {d['lane_util']:.3f} | {d['lds_insts']:.3e} | "
+                    f"{d['lds_busy_per_cu_clk']:.3f} | {d['wait_frac']:.3f} | "
+                    f"{d['vmem_insts']:.3e} | {rd / 1e6:.2f} | {wr / 1e6:.2f} |")
+    return "\n".join(rows) + "\n", out
+
+
 if __name__ == "__main__":
     kind = sys.argv[1]
-    if kind == "traffic":
+    if kind == "derived":
+        a = sys.argv[2:]
+        opts = dict(x.split("=", 1) for x in a[5:])
+        sys.stdout.write(derived(a[:4], a[4].split(","), int(opts["first"]) if "first" in opts
+                                 else None, int(opts["grid"]) if "grid" in opts else None)[0])
+    elif kind == "traffic":
         import json
         a = sys.argv[2:]
         print(json.dumps(traffic(a[0], a[1], a[2], int(a[3]), a[4], a[5], a[6], a[7]), indent=1))
