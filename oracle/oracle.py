@@ -97,6 +97,9 @@ def _declare(L):
     L.orc_soft_backward.argtypes = [_i, _i, _i, _i, _p, _p, _d, _d, _d, _d, _d, _i, _i, _p,
                                     _p, _p, _p]
     L.orc_soft_backward.restype = _i
+    L.orc_soft_backward_ex.argtypes = [_i, _i, _i, _i, _p, _p, _d, _d, _d, _d, _d, _i, _i, _p,
+                                       _p, _p, _p, _i, _i, _p]
+    L.orc_soft_backward_ex.restype = _i
 
 
 def _ptr(a: np.ndarray) -> int:
@@ -340,9 +343,14 @@ def soft_forward(lab, contour, k: int, iterations: int = 5, m: float = 10.0,
 
 def soft_backward(lab, contour, k: int, gq, gtheta, iterations: int = 5, m: float = 10.0,
                   lam: float = 0.5, sigma: float = 0.25, gamma: float = -1.0, T: float = 0.5,
-                  d32: bool = False):
+                  d32: bool = False, qcut: bool = False, r32: bool = False, bound: bool = False):
     """Gradient of <gq, Q_T> + <gtheta, Theta_T>.  Returns (glab f64[B][H][W][3],
-    gcontour f64[B][H][W])."""
+    gcontour f64[B][H][W]), plus, with bound=True, a dict of the error bound of
+    an FP32 evaluation (see scalp_soft_oracle.c): for "lab" and "contour" each,
+    (E, Md); an FP32 evaluation errs by at most 2^-24 E + Md per element (first
+    order), Md being what leaving out the slots with Q < 2^-24 can change.
+    qcut: leave out the slots whose Q is below 2^-24; r32: round every
+    intermediate result to FP32 (both test infrastructure for the bound)."""
     lab = _f32(lab)
     contour = _f32(contour)
     B, H, W = contour.shape
@@ -350,9 +358,17 @@ def soft_backward(lab, contour, k: int, gq, gtheta, iterations: int = 5, m: floa
     gtheta = _f64(gtheta)
     glab = np.zeros((B, H, W, 3))
     gc = np.zeros((B, H, W))
-    rc = lib().orc_soft_backward(B, W, H, k, _ptr(lab), _ptr(contour), m, lam, sigma, gamma, T,
-                                 iterations, int(d32), _ptr(gq), _ptr(gtheta), _ptr(glab),
-                                 _ptr(gc))
+    arrays = None
+    bnd_ptr = None
+    if bound:
+        arrays = [np.zeros((B, H, W, 3)) for _ in range(2)] + [np.zeros((B, H, W)) for _ in range(2)]
+        table = (ctypes.c_void_p * 4)(*[_ptr(a) for a in arrays])
+        bnd_ptr = ctypes.cast(table, ctypes.c_void_p).value
+    rc = lib().orc_soft_backward_ex(B, W, H, k, _ptr(lab), _ptr(contour), m, lam, sigma, gamma, T,
+                                    iterations, int(d32), _ptr(gq), _ptr(gtheta), _ptr(glab),
+                                    _ptr(gc), int(qcut), int(r32), bnd_ptr)
     if rc != 0:
         raise ValueError("oracle soft backward rejected its arguments")
-    return glab, gc
+    if not bound:
+        return glab, gc
+    return glab, gc, {"lab": tuple(arrays[:2]), "contour": tuple(arrays[2:])}

@@ -37,10 +37,12 @@ MUTATIONS = {
     "window_rows_off_by_one": (H, "if (abs(y - wy[k]) <= R) rowk[nk++] = k;",
                                "if (abs(y - wy[k]) < R) rowk[nk++] = k;"),
     "window_ties_to_last": (H, "if (D < best) {       /* ascending k", "if (D <= best) {       /* ascending k"),
-    "soft_bwd_drop_lambda": (S, "gf[3 * p + e] += g * Bw * lambda * dpe;", "gf[3 * p + e] += 0.0 * dpe;"),
-    "soft_bwd_drop_gamma": (S, "gw[qix] += g * A * c.gamma / np;", "gw[qix] += g * A / np;"),
-    "soft_bwd_softmax_sign": (S, "double g = -(1.0 / T) * Q[9 * p + j] * (gQ[9 * p + j] - dot);",
-                              "double g = (1.0 / T) * Q[9 * p + j] * (gQ[9 * p + j] - dot);"),
+    "soft_bwd_drop_lambda": (S, "double cfp = R(r32, R(r32, g * Bw) * lambda);",
+                             "double cfp = 0.0 * R(r32, R(r32, g * Bw) * lambda);"),
+    "soft_bwd_drop_gamma": (S, "double cwq = R(r32, R(r32, R(r32, g * A) * c.gamma) / np);",
+                            "double cwq = R(r32, R(r32, g * A) / np);"),
+    "soft_bwd_softmax_sign": (S, "double g = R(r32, -R(r32, R(r32, 1.0 / T) * Q[9 * p + j]) *",
+                              "double g = R(r32, R(r32, R(r32, 1.0 / T) * Q[9 * p + j]) *"),
 }
 
 
