@@ -277,7 +277,8 @@ static double R(int r32, double v) { return r32 ? (double)(float)v : v; }
  * Separately, Md bounds (absolutely) what leaving out every slot with
  * Q < 2^-24 changes: such a slot's dL/dD enters Md whole and propagates
  * linearly through the full chain (a slot within one ulp of the cut counts
- * as left out).  An FP32 evaluation then errs by at most u E + Md per
+ * as left out; with the qcut option, which leaves those slots out here too,
+ * only the slots within one ulp of the cut enter Md).  An FP32 evaluation then errs by at most u E + Md per
  * element, to first order.
  * Per accumulated element: se = sum of term bounds, sa = sum of |terms|,
  * n = number of terms, md = sum of term Md. */
@@ -461,8 +462,12 @@ int orc_soft_backward_ex(int Bn, int W, int H, int k, const float *lab, const fl
                             double edl = bacc_e(&bq, 9 * p + j) + edot + fabs(dl);
                             ge[j] = (qj * edl + fabs(dl) * B_DQ * qj) / T + 3.0 * fabs(gv);
                             gmd[j] = qj * (bq.md[9 * p + j] + mddot) / T;
-                            /* left out by the FP32 path if its Q is below the cut */
-                            if (qj <= B_QCUT * (1.0 + 0x1p-22)) gmd[j] += fabs(gv);
+                            /* left out by one side only: below the cut (with qcut,
+                             * only within one ulp of it, where the two sides'
+                             * Q may fall on different sides) */
+                            if (qj <= B_QCUT * (1.0 + 0x1p-22) &&
+                                (!qcut || qj >= B_QCUT * (1.0 - 0x1p-22)))
+                                gmd[j] += fabs(gv);
                         }
                     }
                     for (int j = 0; j < 9; j++) {

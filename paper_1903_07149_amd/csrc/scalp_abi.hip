@@ -573,10 +573,10 @@ SoftSaved soft_saved_layout(const scalp_grid_t* g, long long B, long long T) {
     return s;
 }
 
-// workspace: [packed B*N float4][gd B*9*N][gf B*N float4][gth 2 x B*K*5]
-// [cand B*K*2 float4]
+// workspace: [packed B*N float4][gd B*9*N][gf B*N float4][gth 2 x B*K*5 double]
+// [cand B*K*2 float4][gmask B*N uint16]
 struct SoftWs {
-    size_t packed, gd, gf, gth0, gth1, cand, total;
+    size_t packed, gd, gf, gth0, gth1, cand, gmask, total;
 };
 
 SoftWs soft_ws_layout(const scalp_grid_t* g, long long B) {
@@ -586,9 +586,10 @@ SoftWs soft_ws_layout(const scalp_grid_t* g, long long B) {
     w.gd = align_up((size_t)(B * N) * 16);
     w.gf = w.gd + align_up((size_t)(B * 9 * N) * 4);
     w.gth0 = w.gf + align_up((size_t)(B * N) * 16);
-    w.gth1 = w.gth0 + align_up((size_t)(B * K * 5) * 4);
-    w.cand = w.gth1 + align_up((size_t)(B * K * 5) * 4);
-    w.total = w.cand + align_up((size_t)(B * K * 2) * 16);
+    w.gth1 = w.gth0 + align_up((size_t)(B * K * 5) * 8);
+    w.cand = w.gth1 + align_up((size_t)(B * K * 5) * 8);
+    w.gmask = w.cand + align_up((size_t)(B * K * 2) * 16);
+    w.total = w.gmask + align_up((size_t)(B * N) * 2);
     return w;
 }
 
@@ -693,25 +694,27 @@ int scalp_soft_backward(const scalp_grid_t* g, const scalp_params_t* p, float te
     float4* packed = reinterpret_cast<float4*>(wb + W.packed);
     float* gd = reinterpret_cast<float*>(wb + W.gd);
     float4* gf = reinterpret_cast<float4*>(wb + W.gf);
-    float* gth[2] = {reinterpret_cast<float*>(wb + W.gth0), reinterpret_cast<float*>(wb + W.gth1)};
+    double* gth[2] = {reinterpret_cast<double*>(wb + W.gth0),
+                      reinterpret_cast<double*>(wb + W.gth1)};
     float4* cand = reinterpret_cast<float4*>(wb + W.cand);
+    unsigned short* gmask = reinterpret_cast<unsigned short*>(wb + W.gmask);
     const float* fa = reinterpret_cast<const float*>(sb + S.a);
     const float* fb = reinterpret_cast<const float*>(sb + S.bf);
     const double* z = reinterpret_cast<const double*>(sb + S.z);
-    const int cap = soft_cap_bytes(p) / 16;   // four gradient floats per texel
+    const int cap = soft_cap_bytes(p);
     if (!p->reuse_prepared) CHECK_HIP(launch_prepare(B * N, lab, contour, p->sigma, packed, s));
     CHECK_HIP(launch_clear(reinterpret_cast<long long*>(gf), B * N * 2, s));
-    CHECK_HIP(launch_copy_f32(grad_centers, gth[0], B * K * 5, s));
+    CHECK_HIP(launch_widen_f32(grad_centers, gth[0], B * K * 5, s));
     int cur = 0;
     for (int t = T - 1; t >= 0; --t) {
         const long long qo = (long long)t * B * 9 * N;
         const double* zt = z + (long long)t * B * K;
         CHECK_HIP(launch_soft_bwd_update(geo, t == T - 1, q_t + qo, zt,
                                          centers_t + (long long)(t + 1) * B * K * 5, packed,
-                                         gth[cur], grad_q, gd, gf, cand, s));
+                                         gth[cur], grad_q, gd, gmask, gf, cand, s));
         CHECK_HIP(launch_soft_bwd_pass(geo, zt, gth[cur], gth[1 - cur], s));
         CHECK_HIP(launch_soft_bwd_path(geo, packed, centers_t + (long long)t * B * K * 5, fa + qo,
-                                       fb + qo, gd, gf, gth[1 - cur], cap, s));
+                                       fb + qo, gd, gmask, gf, gth[1 - cur], cap, s));
         cur = 1 - cur;
     }
     CHECK_HIP(launch_soft_bwd_finish(geo, gf, gth[cur], contour, p->sigma, grad_lab, grad_contour,

@@ -123,20 +123,23 @@ int launch_soft_assign(const SoftGeom& g, const float4* packed, const float* the
                        float* fa, float* fb, int cap, hipStream_t st);
 int launch_soft_update(const SoftGeom& g, const float* q, const float4* packed,
                        const float* theta_prev, float* theta_next, double* z, hipStream_t st);
-// cand: scratch of 2 * B * K float4 (per-superpixel terms of the update backward)
+// cand: scratch of 2 * B * K float4 (per-superpixel terms of the update backward);
+// gd receives the nonzero dL/dD only, gmask ([B][N]) which of the 9 slots they are
 int launch_soft_bwd_update(const SoftGeom& g, int first, const float* q, const double* z,
-                           const float* theta, const float4* packed, const float* gth,
-                           const float* gq_in, float* gd, float4* gf, float4* cand,
-                           hipStream_t st);
-int launch_soft_bwd_pass(const SoftGeom& g, const double* z, const float* gth, float* gth_prev,
+                           const float* theta, const float4* packed, const double* gth,
+                           const float* gq_in, float* gd, unsigned short* gmask, float4* gf,
+                           float4* cand, hipStream_t st);
+int launch_soft_bwd_pass(const SoftGeom& g, const double* z, const double* gth, double* gth_prev,
                          hipStream_t st);
+// dL/dTheta (gth, gth_prev, gth0) is FP64; cap_bytes: LDS tile budget of the path pass
 int launch_soft_bwd_path(const SoftGeom& g, const float4* packed, const float* theta_prev,
-                         const float* fa, const float* fb, const float* gd, float4* gf,
-                         float* gth_prev, int cap, hipStream_t st);
-int launch_soft_bwd_finish(const SoftGeom& g, const float4* gf, const float* gth0,
+                         const float* fa, const float* fb, const float* gd,
+                         const unsigned short* gmask, float4* gf, double* gth_prev,
+                         int cap_bytes, hipStream_t st);
+int launch_soft_bwd_finish(const SoftGeom& g, const float4* gf, const double* gth0,
                            const float* contour, float sigma, float* glab, float* gcon,
                            hipStream_t st);
-int launch_copy_f32(const float* src, float* dst, long long n, hipStream_t st);
+int launch_widen_f32(const float* src, double* dst, long long n, hipStream_t st);
 
 // ---- per-pixel maps (scalp_maps.hip)
 int launch_boundary_frequency(int W, int H, int n, const int* labels, float* out, hipStream_t s);

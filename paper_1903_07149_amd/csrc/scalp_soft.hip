@@ -19,12 +19,12 @@
 // Backward, per iteration in reverse:
 //   k_soft_bwd_update  thread per pixel: soft-update and softmax backward,
 //                      giving dL/dD for the 9 slots.
-//   k_soft_bwd_path    workgroup per (image, cell), one pass: every lane
-//                      re-walks the paths of its pixel's slots with a nonzero
-//                      dL/dD (samples are recomputed, never stored) and
-//                      scatters dL/df_q and dL/dw_q into LDS tiles and the
-//                      candidate's centre gradient into LDS bins; both leave
-//                      the workgroup as float atomics (not bit-reproducible).
+//   k_soft_bwd_path    workgroup per (image, cell): every (pixel, slot) with a
+//                      nonzero dL/dD re-walks its path (samples are recomputed,
+//                      never stored), adding the path's two per-sample weights
+//                      into LDS tiles; a fold over the tiles then forms dL/df,
+//                      dL/dw and the candidates' centre gradients (FP64), which
+//                      leave the workgroup as atomics (not bit-reproducible).
 #include <algorithm>
 
 #include "scalp_device.h"
@@ -55,13 +55,11 @@ struct SoftCand {
     float l, a, b, x, y;
     int cx, cy;
     float dcc, wc;
-    int staged;                 // backward: endpoint inside the tile rectangle
     int tx0, ty0, tw, th;       // forward: table origin, row pitch, rows; tw == 0: not staged
 };
 
 struct SoftShared {
     SoftCand cand[9];
-    int rx0, ry0, rw, rh;
 };
 
 // Candidates of cell (ci, cj) from theta [K][5]; endpoint = rounded barycenter.
@@ -72,7 +70,6 @@ __device__ __forceinline__ void load_candidates(const SoftImg& s, int ci, int cj
     if (tid < 9) {
         SoftCand c;
         const int ii = ci + tid / 3 - 1, jj = cj + tid % 3 - 1;
-        c.staged = 0;
         if (ii >= 0 && ii < s.ny && jj >= 0 && jj < s.nx) {
             const int k = ii * s.nx + jj;
             const float* ck = theta + 5LL * k;
@@ -90,28 +87,6 @@ __device__ __forceinline__ void load_candidates(const SoftImg& s, int ci, int cj
             c.dcc = c.wc = 0.0f;
         }
         sh.cand[tid] = c;
-    }
-}
-
-// Greedy LDS rectangle (cell grown by candidate endpoints within `cap`).
-__device__ __forceinline__ void plan_rect(int x0, int x1, int y0, int y1, int cap, SoftShared& sh) {
-    if (threadIdx.x == 0) {
-        int rx0 = x0, rx1 = x1, ry0 = y0, ry1 = y1;
-        if ((long long)(x1 - x0) * (y1 - y0) <= cap) {
-            for (int j = 0; j < 9; ++j) {
-                if (sh.cand[j].k < 0) continue;
-                const int cx = sh.cand[j].cx, cy = sh.cand[j].cy;
-                const int ax0 = min(rx0, cx), ax1 = max(rx1, cx + 1);
-                const int ay0 = min(ry0, cy), ay1 = max(ry1, cy + 1);
-                if ((long long)(ax1 - ax0) * (ay1 - ay0) <= cap) {
-                    rx0 = ax0; rx1 = ax1; ry0 = ay0; ry1 = ay1;
-                    sh.cand[j].staged = 1;
-                }
-            }
-            sh.rx0 = rx0; sh.ry0 = ry0; sh.rw = rx1 - rx0; sh.rh = ry1 - ry0;
-        } else {
-            sh.rx0 = x0; sh.ry0 = y0; sh.rw = 0; sh.rh = 0;
-        }
     }
 }
 
@@ -424,7 +399,7 @@ __global__ __launch_bounds__(WG) void k_soft_update(SoftImg s, const float* __re
 // below kZMin (such a superpixel kept its centre and passes no gradient to
 // Q or f).
 __global__ void k_soft_bwd_cand(SoftImg s, const double* __restrict__ z,
-                                const float* __restrict__ theta, const float* __restrict__ gth,
+                                const float* __restrict__ theta, const double* __restrict__ gth,
                                 float4* __restrict__ cand) {
     const long long total = (long long)s.B * s.K;
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
@@ -433,9 +408,8 @@ __global__ void k_soft_bwd_cand(SoftImg s, const double* __restrict__ z,
         float v = 0.0f;
         const double Zd = z[i];
         if (Zd >= kZMin) {
-            const float Z = (float)Zd;
             for (int c = 0; c < 5; ++c) {
-                u[c] = gth[5 * i + c] / Z;
+                u[c] = (float)(gth[5 * i + c] / Zd);
                 v += u[c] * theta[5 * i + c];
             }
         }
@@ -454,6 +428,7 @@ __global__ __launch_bounds__(256) void k_soft_bwd_update(SoftImg s, int first,
                                                          const float4* __restrict__ packed,
                                                          const float* __restrict__ gq_in,
                                                          float* __restrict__ gd,
+                                                         unsigned short* __restrict__ gmask,
                                                          float4* __restrict__ gf) {
     SOFT_FOR_PIXELS(s) {
         const long long p = (long long)y * s.W + x;
@@ -481,10 +456,18 @@ __global__ __launch_bounds__(256) void k_soft_bwd_update(SoftImg s, int first,
         }
         // A slot's whole path contribution is proportional to Q_pj; below
         // FP32's unit roundoff (2^-24) it is dropped, and the path pass skips
-        // the slot (at low T most pixels have one slot above it).
+        // the slot (at low T most pixels have one slot above it).  Only the
+        // nonzero dL/dD are stored; bit j of the pixel's mask says which.
+        unsigned m = 0;
 #pragma unroll
-        for (int j = 0; j < 9; ++j)
-            gd[qb + (long long)j * s.N] = Q[j] < kQMin ? 0.0f : -s.inv_t * Q[j] * (G[j] - dot);
+        for (int j = 0; j < 9; ++j) {
+            const float g = Q[j] < kQMin ? 0.0f : -s.inv_t * Q[j] * (G[j] - dot);
+            if (g != 0.0f) {
+                gd[qb + (long long)j * s.N] = g;
+                m |= 1u << j;
+            }
+        }
+        gmask[i] = (unsigned short)m;
         float4 o = gf[i];
         o.x += gfl;
         o.y += gfa;
@@ -496,55 +479,73 @@ __global__ __launch_bounds__(256) void k_soft_bwd_update(SoftImg s, int first,
 // dL/dTheta_{t-1} starts as the pass-through of superpixels whose soft mass
 // was zero (they kept their previous centre) and receives the path terms.
 __global__ void k_soft_bwd_pass(SoftImg s, const double* __restrict__ z,
-                                const float* __restrict__ gth, float* __restrict__ gth_prev) {
+                                const double* __restrict__ gth, double* __restrict__ gth_prev) {
     const long long total = 5LL * s.B * s.K;
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
          i += (long long)gridDim.x * blockDim.x)
-        gth_prev[i] = z[i / 5] >= kZMin ? 0.0f : gth[i];
+        gth_prev[i] = z[i / 5] >= kZMin ? 0.0 : gth[i];
 }
 
 // Per wave, a list of (pixel, slot) pairs whose dL/dD is not zero, listed
 // chunk by chunk and slot by slot, walked in whole rounds of 64 whenever the
 // next slot would overflow its kBwdBatch entries (the rest carried over);
-// per slot, the 5 centre-gradient sums and the 2 endpoint sums in
-// kBwdCopies copies.
+// per slot, seven FP64 sums (the centre gradient's five components, the
+// endpoint's two weights) in kBwdCopies copies.
 constexpr int kBwdBatch = 192;
 constexpr int kBwdCopies = 8;
+// Texels per thread and trip of the fold.
+constexpr int kFold = 4;
 
-// One workgroup per (image, cell), one pass: every (pixel, slot) whose dL/dD
-// is not zero (at low T about one per pixel) re-walks its path, scattering
-// per sample
+// Where the backward path pass of one work item keeps its tiles: per slot,
+// the box [bx0, bx1) x [by0, by1) of the pixels whose path to the slot it
+// walks, grown to contain the slot's endpoint, and the offset (in doubles)
+// of the slot's FP64 weight tile over that box (-1: the slot's paths scatter
+// to global memory instead); one FP32 tile of dL/dw over the union of the
+// staged boxes follows the weight tiles.
+struct BwdLayout {
+    int bx0[9], bx1[9], by0[9], by1[9];
+    int has[9];
+    int soff[9];
+    int ux0, uy0, uw, uh;
+    int woff;      // in floats
+};
+
+// One workgroup per (image, cell).  Every (pixel, slot) whose dL/dD is not
+// zero (at low T about one per pixel) re-walks its path.  Along a path to
+// candidate k every sample q receives the same two weights,
 //   dL/df_q += cf (f_q - f_k)   with cf = dL/dD * B (1 - lambda) 2 / |P|
-//   dL/dw_q += dL/dD * A gamma / |P|
-// into LDS tiles over the rectangle of the cell and its candidates'
-// endpoints (texel colours come through the cache); the candidate's centre
-// gradient takes the opposite colour terms and the spatial and lambda terms.
-// Each wave lists its nonzero pairs in LDS and walks them 64 at a time, one
-// per lane, so no lane idles on a zero slot (with one lane per pixel and
-// slot, most lanes of a wave had nothing to walk for the neighbouring
-// slots), and only the wave's last round is partial.  The endpoint sample, shared by every path to a
-// slot, is summed per slot and added once at the end.  Tiles leave the
-// workgroup as float atomics (not bit-reproducible).  Candidates whose
-// endpoint lies outside the rectangle scatter straight to global memory.
+//   dL/dw_q += cw               with cw = dL/dD * A gamma / |P|
+// (and p itself dL/dD * B lambda 2 (f_p - f_k)), so the walk only adds cf
+// into an FP64 tile S_k(q) of the slot (p's lambda term included) and cw
+// into the FP32 tile of dL/dw: two LDS atomics per sample and no texel read.
+// A fold over the union of the slots' boxes then forms, per texel,
+// dL/df_q = sum_k S_k(q) (f_q - f_k) from one texel load, and the centre
+// gradient of each candidate, -sum_q S_k(q) (f_q - f_k), in FP64.  The
+// spatial part of the centre gradient and the endpoint's weights (every path
+// to k ends there) are summed per slot and added once.  A first pass over
+// the slot masks of dL/dD sizes the boxes.  Slots whose tiles do not fit the
+// budget walk their paths from global memory instead, reading the texels and
+// scattering the four gradient floats with float atomics.  The centre
+// gradients are summed in FP64 (no FP32 partial sum longer than one path);
+// dL/dTheta leaves as FP64 atomics, dL/df and dL/dw as float atomics (not
+// bit-reproducible).  At least 4 waves per SIMD (at most 128 VGPRs): two 512-lane
+// workgroups per CU, as the LDS budget allows.
 template <int WG>
-__global__ __launch_bounds__(WG) void k_soft_bwd_path(SoftImg s, const float4* __restrict__ packed,
+__global__ __launch_bounds__(WG, 4) void k_soft_bwd_path(SoftImg s, const float4* __restrict__ packed,
                                                       const float* __restrict__ theta_prev,
                                                       const float* __restrict__ fa,
                                                       const float* __restrict__ fb,
                                                       const float* __restrict__ gd,
+                                                      const unsigned short* __restrict__ gmask,
                                                       float4* __restrict__ gf,
-                                                      float* __restrict__ gth_prev, int cap) {
-    extern __shared__ float4 lds_dyn[];
+                                                      double* __restrict__ gth_prev, int cap_bytes) {
+    extern __shared__ double bwd_dyn[];
     __shared__ SoftShared sh;
-    __shared__ int wl_t[WG / 64][kBwdBatch];              // pixel index in the cell
+    __shared__ BwdLayout bl;
+    __shared__ int wl_t[WG / 64][kBwdBatch];              // pixel (see wl_xy) in the cell
     __shared__ unsigned char wl_j[WG / 64][kBwdBatch];    // slot
     __shared__ float wl_g[WG / 64][kBwdBatch];            // dL/dD
-    __shared__ float slot_acc[9][7][kBwdCopies];
-    // four planar float tiles of cap texels: dL/dl, dL/da, dL/db, dL/dw
-    float* accx = reinterpret_cast<float*>(lds_dyn);
-    float* accy = accx + cap;
-    float* accz = accy + cap;
-    float* accw = accz + cap;
+    __shared__ double bins[9][7][kBwdCopies];
     const int item = xcd_remap(blockIdx.x, gridDim.x);
     const int b = item / s.K, cell = item - b * s.K;
     const int tid = threadIdx.x;
@@ -555,140 +556,183 @@ __global__ __launch_bounds__(WG) void k_soft_bwd_path(SoftImg s, const float4* _
     const float4* __restrict__ img = packed + (long long)b * s.N;
     float4* __restrict__ gimg = gf + (long long)b * s.N;
     load_candidates(s, ci, cj, theta_prev + 5LL * s.K * b, img, sh);
-    for (int t = tid; t < 9 * 7 * kBwdCopies; t += WG) (&slot_acc[0][0][0])[t] = 0.0f;
+    for (int t = tid; t < 9 * 7 * kBwdCopies; t += WG) (&bins[0][0][0])[t] = 0.0;
     __syncthreads();
-    plan_rect(x0, x1, y0, y1, cap, sh);
-    __syncthreads();
-    const int rx0 = sh.rx0, ry0 = sh.ry0, rw = sh.rw;
-    const int area = rw * sh.rh;
-    for (int e = tid; e < area; e += WG) {
-        accx[e] = 0.0f;
-        accy[e] = 0.0f;
-        accz[e] = 0.0f;
-        accw[e] = 0.0f;
+    if (tid < 9) {
+        bl.bx0[tid] = sh.cand[tid].cx;
+        bl.bx1[tid] = sh.cand[tid].cx + 1;
+        bl.by0[tid] = sh.cand[tid].cy;
+        bl.by1[tid] = sh.cand[tid].cy + 1;
+        bl.has[tid] = 0;
     }
     __syncthreads();
     const int cw = x1 - x0, ch = y1 - y0, P = cw * ch;
     const int lane = tid & 63, wave = tid >> 6;
     const int cp = lane & (kBwdCopies - 1);
-    const float lambda = s.lambda, oml = 1.0f - lambda;
     const long long base = 9LL * s.N * b;
+    // list entries hold the pixel's offsets in the cell as two 16-bit
+    // halves when they fit, else its index in the cell's pixel order
+    const bool wl_xy = cw < 65536 && ch < 65536;
+    // pass 1: the box of each slot's walked pixels (a chunk's box per chunk
+    // with any nonzero dL/dD in the slot)
+    for (int chunk = wave; chunk * 64 < P; chunk += WG / 64) {
+        const int t = chunk * 64 + lane;
+        const bool valid = t < P;
+        int px = 0, py = 0;
+        if (valid) {
+            cell_pixel(t, cw, ch, px, py);
+            px += x0;
+            py += y0;
+        }
+        int mnx = valid ? px : 0x7fffffff, mxx = valid ? px : -1;
+        int mny = valid ? py : 0x7fffffff, mxy = valid ? py : -1;
+        for (int o = 32; o > 0; o >>= 1) {
+            mnx = min(mnx, __shfl_xor(mnx, o, 64));
+            mxx = max(mxx, __shfl_xor(mxx, o, 64));
+            mny = min(mny, __shfl_xor(mny, o, 64));
+            mxy = max(mxy, __shfl_xor(mxy, o, 64));
+        }
+        const unsigned msk = valid ? gmask[(long long)b * s.N + (long long)py * W + px] : 0u;
+#pragma unroll
+        for (int j = 0; j < 9; ++j) {
+            if (__ballot((msk >> j) & 1u) != 0ULL && lane == 0) {
+                atomicMin(&bl.bx0[j], mnx);
+                atomicMax(&bl.bx1[j], mxx + 1);
+                atomicMin(&bl.by0[j], mny);
+                atomicMax(&bl.by1[j], mxy + 1);
+                bl.has[j] = 1;
+            }
+        }
+    }
+    __syncthreads();
+    // tile layout: slots in the order own cell, edges, corners, while they fit
+    if (tid == 0) {
+        constexpr unsigned long long kOrder = 0x862075314ULL;
+        int used = 0;                                           // bytes of weight tiles
+        int ux0 = 0x7fffffff, uy0 = 0x7fffffff, ux1 = -1, uy1 = -1;
+        for (int t = 0; t < 9; ++t) {
+            const int j = (int)((kOrder >> (4 * t)) & 15ULL);
+            bl.soff[j] = -1;
+            if (sh.cand[j].k < 0 || !bl.has[j]) continue;
+            const int bw = bl.bx1[j] - bl.bx0[j], bh = bl.by1[j] - bl.by0[j];
+            const long long sb = 8LL * bw * bh;
+            const int nx0 = min(ux0, bl.bx0[j]), nx1 = max(ux1, bl.bx1[j]);
+            const int ny0 = min(uy0, bl.by0[j]), ny1 = max(uy1, bl.by1[j]);
+            const long long ub = 4LL * (nx1 - nx0) * (ny1 - ny0);
+            if (used + sb + ub <= cap_bytes) {
+                bl.soff[j] = used / 8;
+                used += (int)sb;
+                ux0 = nx0; ux1 = nx1; uy0 = ny0; uy1 = ny1;
+            }
+        }
+        if (ux1 < 0) ux0 = ux1 = uy0 = uy1 = 0;
+        bl.ux0 = ux0; bl.uy0 = uy0; bl.uw = ux1 - ux0; bl.uh = uy1 - uy0;
+        bl.woff = used / 4;
+    }
+    __syncthreads();
+    float* wtile = reinterpret_cast<float*>(bwd_dyn) + bl.woff;
+    const int ux0 = bl.ux0, uy0 = bl.uy0, uw = bl.uw, uh = bl.uh;
+    {
+        const int words = bl.woff + uw * uh;
+        float* z = reinterpret_cast<float*>(bwd_dyn);
+        for (int e = tid; e < words; e += WG) z[e] = 0.0f;
+    }
+    __syncthreads();
+    const float lambda = s.lambda, oml = 1.0f - lambda;
     // walks listed pair i of this wave (the lanes of a wave call it together)
     auto walk_pair = [&](int i) {
         const int jj = wl_j[wave][i];
         const float gj = wl_g[wave][i];
         int x, y;
-        cell_pixel(wl_t[wave][i], cw, ch, x, y);
+        if (wl_xy) {
+            x = wl_t[wave][i] & 0xffff;
+            y = wl_t[wave][i] >> 16;
+        } else {
+            cell_pixel(wl_t[wave][i], cw, ch, x, y);
+        }
         x += x0;
         y += y0;
         const int p = y * W + x;
         const SoftCand c = sh.cand[jj];
-        float gk[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-        float cf_end = 0.0f, cw_end = 0.0f;
-        {
-            const long long o = base + (long long)jj * s.N + p;
-            const float A = fa[o], Bw = fb[o];
-            const int dx = c.cx - x, dy = c.cy - y;
-            const int adx = dx < 0 ? -dx : dx, ady = dy < 0 ? -dy : dy;
-            const int n = adx > ady ? adx : ady;
-            const float inv_np = 1.0f / (float)(n + 1);
-            const float cf = 2.0f * gj * Bw * oml * inv_np;  // per sample, times (f_q - f_k)
-            const float cw_ = gj * A * s.gamma * inv_np;     // per sample: dL/dw_q
-            const float lf = 2.0f * gj * Bw * lambda;        // lambda term of p
+        const long long o = base + (long long)jj * s.N + p;
+        const float A = fa[o], Bw = fb[o];
+        const int dx = c.cx - x, dy = c.cy - y;
+        const int adx = dx < 0 ? -dx : dx, ady = dy < 0 ? -dy : dy;
+        const int n = adx > ady ? adx : ady;
+        const float inv_np = 1.0f / (float)(n + 1);
+        const float cf = 2.0f * gj * Bw * oml * inv_np;  // per sample, times (f_q - f_k)
+        const float cw_ = gj * A * s.gamma * inv_np;     // per sample: dL/dw_q
+        const float lf = 2.0f * gj * Bw * lambda;        // lambda term of p
+        atomicAdd(&bins[jj][3][cp], (double)(-2.0f * gj * s.spw * ((float)x - c.x)));
+        atomicAdd(&bins[jj][4][cp], (double)(-2.0f * gj * s.spw * ((float)y - c.y)));
+        const bool xmaj = adx >= ady;
+        const int so = bl.soff[jj];
+        if (so >= 0) {                                   // staged
+            // samples i = 0 .. n-1 (p itself first); the endpoint i = n is
+            // added once per slot
+            const int sbx0 = bl.bx0[jj], sby0 = bl.by0[jj], sp = bl.bx1[jj] - sbx0;
+            double* st = bwd_dyn + so;
+            const int stx = dx < 0 ? -1 : 1;
+            const int sys = dy < 0 ? -sp : sp, syw = dy < 0 ? -uw : uw;
+            const int smaj_s = xmaj ? stx : sys, sdiag_s = smaj_s + (xmaj ? sys : stx);
+            const int smaj_w = xmaj ? stx : syw, sdiag_w = smaj_w + (xmaj ? syw : stx);
+            int ls = (y - sby0) * sp + (x - sbx0);
+            int lw = (y - uy0) * uw + (x - ux0);
+            const double cfd = (double)cf;
+            if (n > 0) {
+                atomicAdd(&st[ls], cfd + (double)lf);
+                atomicAdd(&wtile[lw], cw_);
+                const unsigned F = step_increment(xmaj ? ady : adx, n);
+                unsigned acc = 0x80000000u;
+                for (int i = 1; i < n; ++i) {
+                    const bool cr = __builtin_add_overflow(acc, F, &acc);
+                    ls += cr ? sdiag_s : smaj_s;
+                    lw += cr ? sdiag_w : smaj_w;
+                    atomicAdd(&st[ls], cfd);
+                    atomicAdd(&wtile[lw], cw_);
+                }
+            } else {
+                atomicAdd(&st[ls], (double)lf);
+            }
+            atomicAdd(&bins[jj][5][cp], cfd);
+            atomicAdd(&bins[jj][6][cp], (double)cw_);
+        } else {                                         // scatter to global memory
+            float gk[3] = {0.0f, 0.0f, 0.0f};
             const float4 fp = img[p];
             const float dl = fp.x - c.l, da = fp.y - c.a, db = fp.z - c.b;
             gk[0] -= lf * dl;
             gk[1] -= lf * da;
             gk[2] -= lf * db;
-            gk[3] -= 2.0f * gj * s.spw * ((float)x - c.x);
-            gk[4] -= 2.0f * gj * s.spw * ((float)y - c.y);
-            // samples i = 0 .. n-1 (p itself first); i = n is the endpoint
-            const bool xmaj = adx >= ady;
             const int am = xmaj ? ady : adx;
             const int two_n = 2 * n, inc = 2 * am;
             int rem = n;
-            if (c.staged) {
-                const int stx = dx < 0 ? -1 : 1, sty = dy < 0 ? -rw : rw;
-                const int smaj = xmaj ? stx : sty;
-                const int sdiag = smaj + (xmaj ? sty : stx);
-                const int gty = dy < 0 ? -W : W;                // the same steps in the image
-                const int gmaj = xmaj ? stx : gty;
-                const int gdiag = gmaj + (xmaj ? gty : stx);
-                int li = (y - ry0) * rw + (x - rx0);
-                int gi = p;
-                atomicAdd(&accx[li], lf * dl);
-                atomicAdd(&accy[li], lf * da);
-                atomicAdd(&accz[li], lf * db);
-                // four samples per trip: the texel loads of a trip are all
-                // issued before the first is used
-                for (int i0 = 0; i0 < n; i0 += 4) {
-                    int lis[4];
-                    float4 fq[4];
-    #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        if (i0 + u < n) {
-                            if (i0 + u > 0) {
-                                rem += inc;
-                                const bool st = rem >= two_n;
-                                rem -= st ? two_n : 0;
-                                li += st ? sdiag : smaj;
-                                gi += st ? gdiag : gmaj;
-                            }
-                            lis[u] = li;
-                            fq[u] = img[gi];
-                        }
-                    }
-    #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        if (i0 + u < n) {
-                            const float el = cf * (fq[u].x - c.l), ea = cf * (fq[u].y - c.a),
-                                        eb = cf * (fq[u].z - c.b);
-                            atomicAdd(&accx[lis[u]], el);
-                            atomicAdd(&accy[lis[u]], ea);
-                            atomicAdd(&accz[lis[u]], eb);
-                            atomicAdd(&accw[lis[u]], cw_);
-                            gk[0] -= el;
-                            gk[1] -= ea;
-                            gk[2] -= eb;
-                        }
-                    }
+            const int stx = dx < 0 ? -1 : 1, sty = dy < 0 ? -W : W;
+            const int smaj = xmaj ? stx : sty;
+            const int sdiag = smaj + (xmaj ? sty : stx);
+            int gi = p;
+            unsafeAtomicAdd(&gimg[gi].x, lf * dl);
+            unsafeAtomicAdd(&gimg[gi].y, lf * da);
+            unsafeAtomicAdd(&gimg[gi].z, lf * db);
+            for (int i = 0; i <= n; ++i) {
+                if (i > 0) {
+                    rem += inc;
+                    const bool st_ = rem >= two_n;
+                    rem -= st_ ? two_n : 0;
+                    gi += st_ ? sdiag : smaj;
                 }
-                cf_end = cf;
-                cw_end = cw_;
-            } else {
-                const int stx = dx < 0 ? -1 : 1, sty = dy < 0 ? -W : W;
-                const int smaj = xmaj ? stx : sty;
-                const int sdiag = smaj + (xmaj ? sty : stx);
-                int gi = p;
-                unsafeAtomicAdd(&gimg[gi].x, lf * dl);
-                unsafeAtomicAdd(&gimg[gi].y, lf * da);
-                unsafeAtomicAdd(&gimg[gi].z, lf * db);
-                for (int i = 0; i <= n; ++i) {
-                    if (i > 0) {
-                        rem += inc;
-                        const bool st = rem >= two_n;
-                        rem -= st ? two_n : 0;
-                        gi += st ? sdiag : smaj;
-                    }
-                    const float4 fq = img[gi];
-                    const float el = cf * (fq.x - c.l), ea = cf * (fq.y - c.a),
-                                eb = cf * (fq.z - c.b);
-                    unsafeAtomicAdd(&gimg[gi].x, el);
-                    unsafeAtomicAdd(&gimg[gi].y, ea);
-                    unsafeAtomicAdd(&gimg[gi].z, eb);
-                    unsafeAtomicAdd(&gimg[gi].w, cw_);
-                    gk[0] -= el;
-                    gk[1] -= ea;
-                    gk[2] -= eb;
-                }
+                const float4 fq = img[gi];
+                const float el = cf * (fq.x - c.l), ea = cf * (fq.y - c.a),
+                            eb = cf * (fq.z - c.b);
+                unsafeAtomicAdd(&gimg[gi].x, el);
+                unsafeAtomicAdd(&gimg[gi].y, ea);
+                unsafeAtomicAdd(&gimg[gi].z, eb);
+                unsafeAtomicAdd(&gimg[gi].w, cw_);
+                gk[0] -= el;
+                gk[1] -= ea;
+                gk[2] -= eb;
             }
-        }
 #pragma unroll
-        for (int v = 0; v < 5; ++v)
-            if (gk[v] != 0.0f) atomicAdd(&slot_acc[jj][v][cp], gk[v]);
-        if (c.staged) {
-            atomicAdd(&slot_acc[jj][5][cp], cf_end);
-            atomicAdd(&slot_acc[jj][6][cp], cw_end);
+            for (int v = 0; v < 3; ++v) atomicAdd(&bins[jj][v][cp], (double)gk[v]);
         }
     };
     // walks pairs [0, upto) of the list, 64 per round; then the list's LDS
@@ -704,6 +748,7 @@ __global__ __launch_bounds__(WG) void k_soft_bwd_path(SoftImg s, const float4* _
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     };
+    // pass 2: list the nonzero pairs and walk them
     int nb = 0;                        // pairs listed and not walked yet (uniform over the wave)
     for (int chunk = wave; chunk * 64 < P; chunk += WG / 64) {
         const int t = chunk * 64 + lane;
@@ -714,11 +759,12 @@ __global__ __launch_bounds__(WG) void k_soft_bwd_path(SoftImg s, const float4* _
             px += x0;
             py += y0;
         }
+        const unsigned msk = valid ? gmask[(long long)b * s.N + (long long)py * W + px] : 0u;
         float g[9];
 #pragma unroll
         for (int j = 0; j < 9; ++j)
-            g[j] = valid && sh.cand[j].k >= 0
-                       ? gd[base + (long long)j * s.N + (long long)py * W + px] : 0.0f;
+            g[j] = (msk >> j) & 1u ? gd[base + (long long)j * s.N + (long long)py * W + px] : 0.0f;
+        const int tag = wl_xy ? (px - x0) | ((py - y0) << 16) : t;
 #pragma unroll 1
         for (int jn = 0; jn < 9; ++jn) {                        // uniform
             float gj = 0.0f;
@@ -752,7 +798,7 @@ __global__ __launch_bounds__(WG) void k_soft_bwd_path(SoftImg s, const float4* _
                 const int at = nb + (int)__builtin_amdgcn_mbcnt_hi(
                                        (unsigned)(m >> 32),
                                        __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-                wl_t[wave][at] = t;
+                wl_t[wave][at] = tag;
                 wl_j[wave][at] = (unsigned char)jn;
                 wl_g[wave][at] = gj;
             }
@@ -761,47 +807,89 @@ __global__ __launch_bounds__(WG) void k_soft_bwd_path(SoftImg s, const float4* _
     }
     walk_list(nb);
     __syncthreads();
-    // per slot: the endpoint sample, (sum cf) (f_c - f_k) and sum dL/dw, then
-    // the centre gradient
-    if (tid < 9) {
+    // the endpoint's weights, once per staged slot (one writer per weight
+    // tile entry; two candidates may round to the same endpoint pixel, so
+    // the shared dL/dw tile takes an atomic)
+    if (tid < 9 && bl.soff[tid] >= 0) {
         const SoftCand c = sh.cand[tid];
-        if (c.k >= 0) {
-            float v[7];
+        double vc = 0.0, vw = 0.0;
+        for (int k = 0; k < kBwdCopies; ++k) {
+            vc += bins[tid][5][k];
+            vw += bins[tid][6][k];
+        }
+        const int sp = bl.bx1[tid] - bl.bx0[tid];
+        bwd_dyn[bl.soff[tid] + (c.cy - bl.by0[tid]) * sp + (c.cx - bl.bx0[tid])] += vc;
+        atomicAdd(&wtile[(c.cy - uy0) * uw + (c.cx - ux0)], (float)vw);
+    }
+    __syncthreads();
+    // fold over the union box, kFold texels per thread and trip with their
+    // texel loads issued first: dL/df_q = sum_k S_k(q) (f_q - f_k) (FP64, one
+    // rounding) and dL/dw_q; the centre gradients -sum_q S_k(q) (f_q - f_k)
+    // go to the FP64 slot sums term by term
+    {
+        const int area = uw * uh;
+        const int dr = uw > 0 ? WG / uw : 0, dc = uw > 0 ? WG - dr * uw : 0;
+        int r = uw > 0 ? tid / uw : 0, c = tid - r * uw;
+        for (int e0 = tid; e0 < area; e0 += kFold * WG) {
+            int xs[kFold], ys[kFold];
+            float4 fs[kFold];
 #pragma unroll
-            for (int q = 0; q < 7; ++q) {
-                float a = 0.0f;
-                for (int k = 0; k < kBwdCopies; ++k) a += slot_acc[tid][q][k];
-                v[q] = a;
+            for (int u = 0; u < kFold; ++u) {
+                xs[u] = ux0 + c;
+                ys[u] = uy0 + r;
+                if (e0 + u * WG < area) fs[u] = img[(long long)ys[u] * W + xs[u]];
+                c += dc;
+                const bool wrap = c >= uw;
+                c -= wrap ? uw : 0;
+                r += dr + (wrap ? 1 : 0);
             }
-            if (c.staged && (v[5] != 0.0f || v[6] != 0.0f)) {
-                const int lic = (c.cy - ry0) * rw + (c.cx - rx0);
-                const float4 fc = img[(long long)c.cy * W + c.cx];
-                const float el = v[5] * (fc.x - c.l), ea = v[5] * (fc.y - c.a),
-                            eb = v[5] * (fc.z - c.b);
-                atomicAdd(&accx[lic], el);
-                atomicAdd(&accy[lic], ea);
-                atomicAdd(&accz[lic], eb);
-                atomicAdd(&accw[lic], v[6]);
-                v[0] -= el;
-                v[1] -= ea;
-                v[2] -= eb;
+#pragma unroll
+            for (int u = 0; u < kFold; ++u) {
+                const int e = e0 + u * WG;
+                if (e >= area) break;
+                const int x = xs[u], y = ys[u];
+                const float4 f = fs[u];
+                const float wv = wtile[e];
+                double ax = 0.0, ay = 0.0, az = 0.0;
+#pragma unroll
+                for (int j = 0; j < 9; ++j) {
+                    const int so = bl.soff[j];
+                    if (so < 0) continue;
+                    if (x < bl.bx0[j] || x >= bl.bx1[j] || y < bl.by0[j] || y >= bl.by1[j])
+                        continue;
+                    const double sv = bwd_dyn[so + (y - bl.by0[j]) * (bl.bx1[j] - bl.bx0[j]) +
+                                              (x - bl.bx0[j])];
+                    if (sv == 0.0) continue;
+                    const double el = sv * (double)(f.x - sh.cand[j].l);
+                    const double ea = sv * (double)(f.y - sh.cand[j].a);
+                    const double eb = sv * (double)(f.z - sh.cand[j].b);
+                    ax += el;
+                    ay += ea;
+                    az += eb;
+                    atomicAdd(&bins[j][0][cp], -el);
+                    atomicAdd(&bins[j][1][cp], -ea);
+                    atomicAdd(&bins[j][2][cp], -eb);
+                }
+                if (ax != 0.0 || ay != 0.0 || az != 0.0 || wv != 0.0f) {
+                    float4* d = &gimg[(long long)y * W + x];
+                    unsafeAtomicAdd(&d->x, (float)ax);
+                    unsafeAtomicAdd(&d->y, (float)ay);
+                    unsafeAtomicAdd(&d->z, (float)az);
+                    unsafeAtomicAdd(&d->w, wv);
+                }
             }
-            for (int q = 0; q < 5; ++q)
-                if (v[q] != 0.0f)
-                    unsafeAtomicAdd(&gth_prev[5LL * s.K * b + 5LL * c.k + q], v[q]);
         }
     }
     __syncthreads();
-    // flush the workgroup's tiles
-    for (int e = tid; e < area; e += WG) {
-        const float vx = accx[e], vy = accy[e], vz = accz[e], vw = accw[e];
-        if (vx != 0.0f || vy != 0.0f || vz != 0.0f || vw != 0.0f) {
-            const int r = e / rw;
-            float4* d = &gimg[(long long)(ry0 + r) * W + rx0 + (e - r * rw)];
-            unsafeAtomicAdd(&d->x, vx);
-            unsafeAtomicAdd(&d->y, vy);
-            unsafeAtomicAdd(&d->z, vz);
-            unsafeAtomicAdd(&d->w, vw);
+    // the centre gradients
+    if (tid < 9) {
+        const SoftCand c = sh.cand[tid];
+        if (c.k >= 0) {
+            for (int q = 0; q < 5; ++q) {
+                double a = 0.0;
+                for (int k = 0; k < kBwdCopies; ++k) a += bins[tid][q][k];
+                if (a != 0.0) unsafeAtomicAdd(&gth_prev[5LL * s.K * b + 5LL * c.k + q], a);
+            }
         }
     }
 }
@@ -809,7 +897,7 @@ __global__ __launch_bounds__(WG) void k_soft_bwd_path(SoftImg s, const float4* _
 // Theta_0 = cell means: dL/df_p += dL/dTheta_0 / |cell|; then the outputs:
 // dL/dlab = dL/df and dL/dC = dL/dw * 2C/sigma^2 exp(-C^2/sigma^2).
 __global__ __launch_bounds__(256) void k_soft_bwd_finish(SoftImg s, const float4* __restrict__ gf,
-                                                         const float* __restrict__ gth0,
+                                                         const double* __restrict__ gth0,
                                                          const float* __restrict__ contour,
                                                          float sigma, float* __restrict__ glab,
                                                          float* __restrict__ gcon) {
@@ -820,30 +908,29 @@ __global__ __launch_bounds__(256) void k_soft_bwd_finish(SoftImg s, const float4
         const int ci = cell_of(y, s.ny, s.H), cj = cell_of(x, s.nx, s.W);
         const int cnt = (cell_lo(cj + 1, s.W, s.nx) - cell_lo(cj, s.W, s.nx)) *
                         (cell_lo(ci + 1, s.H, s.ny) - cell_lo(ci, s.H, s.ny));
-        const float* g0 = gth0 + 5LL * s.K * b + 5LL * (ci * s.nx + cj);
+        const double* g0 = gth0 + 5LL * s.K * b + 5LL * (ci * s.nx + cj);
         const float4 v = gf[i];
-        glab[3 * i] = v.x + g0[0] / (float)cnt;
-        glab[3 * i + 1] = v.y + g0[1] / (float)cnt;
-        glab[3 * i + 2] = v.z + g0[2] / (float)cnt;
+        glab[3 * i] = v.x + (float)(g0[0] / cnt);
+        glab[3 * i + 1] = v.y + (float)(g0[1] / cnt);
+        glab[3 * i + 2] = v.z + (float)(g0[2] / cnt);
         const double c = contour[i];
         gcon[i] = (float)((double)v.w * (2.0 * c / s2) * exp(-(c * c) / s2));
     }
 }
 
-__global__ void k_copy_f32(const float* __restrict__ src, float* __restrict__ dst, long long n) {
+__global__ void k_widen_f32(const float* __restrict__ src, double* __restrict__ dst, long long n) {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x)
-        dst[i] = src[i];
+        dst[i] = (double)src[i];
 }
 
 constexpr int kSoftWG = 256;
 constexpr int kSoftBwdWG = 512;
-// Tile budget of the backward path pass in texels (16 bytes each): with its
-// ~16 KiB of static LDS (the waves' pair lists, the slot sums, the
-// candidates) two 512-lane workgroups still fit in a CU's 160 KiB, with
-// room for allocation granularity.  A rectangle beyond it scatters to
-// global memory instead.
-constexpr int kBwdTileCap = 3968;
+// Tile budget of the backward path pass in bytes (FP64 weight tiles plus the
+// FP32 dL/dw tile): with its ~18 KiB of static LDS (the waves' pair lists,
+// the slot sums, the layout, the candidates) two 512-lane workgroups still
+// fit in a CU's 160 KiB.  Slots beyond it scatter to global memory instead.
+constexpr int kBwdLdsBytes = 60 * 1024;
 
 unsigned grid_for(long long n) {
     return (unsigned)std::max<long long>(1, std::min<long long>((n + 255) / 256, 65536));
@@ -895,7 +982,7 @@ void lift_soft_lds_limits() {
     }
     static_cast<void>(hipFuncSetAttribute(
         reinterpret_cast<const void*>(k_soft_bwd_path<kSoftBwdWG>),
-        hipFuncAttributeMaxDynamicSharedMemorySize, kBwdTileCap * 4 * (int)sizeof(float)));
+        hipFuncAttributeMaxDynamicSharedMemorySize, kBwdLdsBytes));
     static_cast<void>(hipGetLastError());
 }
 
@@ -935,18 +1022,18 @@ int launch_soft_update(const SoftGeom& g, const float* q, const float4* packed,
 }
 
 int launch_soft_bwd_update(const SoftGeom& g, int first, const float* q, const double* z,
-                           const float* theta, const float4* packed, const float* gth,
-                           const float* gq_in, float* gd, float4* gf, float4* cand,
-                           hipStream_t st) {
+                           const float* theta, const float4* packed, const double* gth,
+                           const float* gq_in, float* gd, unsigned short* gmask, float4* gf,
+                           float4* cand, hipStream_t st) {
     const SoftImg s = to_img(g);
     hipLaunchKernelGGL(k_soft_bwd_cand, dim3(grid_for((long long)s.B * s.K)), dim3(256), 0, st, s,
                        z, theta, gth, cand);
     hipLaunchKernelGGL(k_soft_bwd_update, pixel_grid(s), dim3(256), 0, st, s, first, q, cand,
-                       packed, gq_in, gd, gf);
+                       packed, gq_in, gd, gmask, gf);
     return hipGetLastError();
 }
 
-int launch_soft_bwd_pass(const SoftGeom& g, const double* z, const float* gth, float* gth_prev,
+int launch_soft_bwd_pass(const SoftGeom& g, const double* z, const double* gth, double* gth_prev,
                          hipStream_t st) {
     const SoftImg s = to_img(g);
     hipLaunchKernelGGL(k_soft_bwd_pass, dim3(grid_for(5LL * s.B * s.K)), dim3(256), 0, st, s, z,
@@ -956,24 +1043,25 @@ int launch_soft_bwd_pass(const SoftGeom& g, const double* z, const float* gth, f
 
 template <int WG>
 static int soft_bwd_path_t(const SoftImg& s, const float4* packed, const float* theta_prev,
-                           const float* fa, const float* fb, const float* gd, float4* gf,
-                           float* gth_prev, int cap, hipStream_t st) {
-    hipLaunchKernelGGL(k_soft_bwd_path<WG>, dim3(s.B * s.K), dim3(WG),
-                       (size_t)cap * 4 * sizeof(float), st, s, packed, theta_prev,
-                       fa, fb, gd, gf, gth_prev, cap);
+                           const float* fa, const float* fb, const float* gd,
+                           const unsigned short* gmask, float4* gf, double* gth_prev,
+                           int cap_bytes, hipStream_t st) {
+    hipLaunchKernelGGL(k_soft_bwd_path<WG>, dim3(s.B * s.K), dim3(WG), (size_t)cap_bytes, st, s,
+                       packed, theta_prev, fa, fb, gd, gmask, gf, gth_prev, cap_bytes);
     return hipGetLastError();
 }
 
 int launch_soft_bwd_path(const SoftGeom& g, const float4* packed, const float* theta_prev,
-                         const float* fa, const float* fb, const float* gd, float4* gf,
-                         float* gth_prev, int cap, hipStream_t st) {
-    // one shape for the backward pass whatever the assignment's (measured
-    // fastest on 16 x 512x512, k = 400: 512 lanes)
-    return soft_bwd_path_t<kSoftBwdWG>(to_img(g), packed, theta_prev, fa, fb, gd, gf, gth_prev,
-                                       std::min(cap, kBwdTileCap), st);
+                         const float* fa, const float* fb, const float* gd,
+                         const unsigned short* gmask, float4* gf, double* gth_prev,
+                         int cap_bytes, hipStream_t st) {
+    // one shape for the backward pass whatever the assignment's (512 lanes;
+    // a cell's work is split over its 64-pixel chunks, one wave each)
+    return soft_bwd_path_t<kSoftBwdWG>(to_img(g), packed, theta_prev, fa, fb, gd, gmask, gf,
+                                       gth_prev, std::min(cap_bytes, kBwdLdsBytes) & ~7, st);
 }
 
-int launch_soft_bwd_finish(const SoftGeom& g, const float4* gf, const float* gth0,
+int launch_soft_bwd_finish(const SoftGeom& g, const float4* gf, const double* gth0,
                            const float* contour, float sigma, float* glab, float* gcon,
                            hipStream_t st) {
     const SoftImg s = to_img(g);
@@ -982,8 +1070,8 @@ int launch_soft_bwd_finish(const SoftGeom& g, const float4* gf, const float* gth
     return hipGetLastError();
 }
 
-int launch_copy_f32(const float* src, float* dst, long long n, hipStream_t st) {
-    hipLaunchKernelGGL(k_copy_f32, dim3(grid_for(n)), dim3(256), 0, st, src, dst, n);
+int launch_widen_f32(const float* src, double* dst, long long n, hipStream_t st) {
+    hipLaunchKernelGGL(k_widen_f32, dim3(grid_for(n)), dim3(256), 0, st, src, dst, n);
     return hipGetLastError();
 }
 
