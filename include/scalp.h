@@ -192,6 +192,24 @@ int scalp_run(const scalp_grid_t* g, const scalp_params_t* p, const float* lab,
               const float* contour, float* centers, int32_t* endpoints, int32_t* labels,
               int32_t* counts, void* workspace, size_t workspace_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under hipGraph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): scalp_run
+ * without a workspace argument.  The same computation and outputs, with
+ * scalp_run's workspace replaced by a scratch array the library keeps in
+ * device memory: SCALP_STATIC_SCRATCH_BYTES (64 MiB), held on every GPU the
+ * library runs on until the process ends.  It allocates and frees nothing.
+ * Limits: scalp_workspace_bytes(g) must not exceed the scratch (1920x1080
+ * fits, 3840x2160 does not), else SCALP_ERR_WORKSPACE before anything is
+ * enqueued; p->reuse_prepared must be 0 (SCALP_ERR_ARG).  All calls on one
+ * GPU share that GPU's scratch, which keeps the last call's contents (each
+ * call clears what it needs on its own stream): calls on one GPU that
+ * overlap in time (other streams, other host threads) race, and their
+ * results are undefined.  Other arguments as for scalp_run. */
+#define SCALP_STATIC_SCRATCH_BYTES (64ull << 20)
+int scalp_run_static(const scalp_grid_t* g, const scalp_params_t* p, const float* lab,
+                     const float* contour, float* centers, int32_t* endpoints, int32_t* labels,
+                     int32_t* counts, void* stream);
+
 /* The iteration loop of scalp_run (assign, update, projection, repeated
  * p->iterations times) captured once into a hipGraph for fixed buffers, and
  * replayed with scalp_graph_launch.  The graph reads centers and endpoints

@@ -17,13 +17,15 @@ LIB_PATH = os.path.join(HERE, "libscalp.so")
 SCALP_OK = 0
 SCALP_ERR_ARG = -1
 SCALP_ERR_WORKSPACE = -2
+# SCALP_STATIC_SCRATCH_BYTES of include/scalp.h: the scratch of scalp_run_static
+STATIC_SCRATCH_BYTES = 64 << 20
 SCALP_ERR_HIP = -3
 SCALP_ERR_UNSUPPORTED = -4
 
 EXPORTED = [
     "scalp_default_params", "scalp_make_grid", "scalp_workspace_bytes", "scalp_prepare",
     "scalp_init_grid", "scalp_assign", "scalp_update", "scalp_assign_accumulate",
-    "scalp_finalize", "scalp_run", "scalp_graph_create",
+    "scalp_finalize", "scalp_run", "scalp_run_static", "scalp_graph_create",
     "scalp_graph_launch", "scalp_graph_destroy", "scalp_batch_workspace_bytes",
     "scalp_run_batched", "scalp_batched_graph_create", "scalp_soft_saved_bytes",
     "scalp_soft_workspace_bytes", "scalp_soft_forward", "scalp_soft_backward",
@@ -98,6 +100,7 @@ def lib() -> ctypes.CDLL:
             "scalp_assign_accumulate": ([gp, pp, _P, _P, _P, _P, _SZ, _P], ctypes.c_int),
             "scalp_finalize": ([gp, pp, _P, _P, _P, _P, _P, _SZ, _P], ctypes.c_int),
             "scalp_run": ([gp, pp, _P, _P, _P, _P, _P, _P, _P, _SZ, _P], ctypes.c_int),
+            "scalp_run_static": ([gp, pp, _P, _P, _P, _P, _P, _P, _P], ctypes.c_int),
             "scalp_graph_create": ([gp, pp, _P, _P, _P, _P, _P, _SZ, ctypes.POINTER(_P)],
                                    ctypes.c_int),
             "scalp_graph_launch": ([_P, _P], ctypes.c_int),

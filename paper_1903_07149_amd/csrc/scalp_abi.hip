@@ -13,6 +13,13 @@
 
 using namespace scalp;
 
+// The scratch of scalp_run_static: the workspace that scalp_run takes from
+// its caller, as a device array of this library (one per GPU).  In host code
+// `scratch` names a host-side stand-in, not a device address: every use goes
+// through the per-device address that hipGetSymbolAddress returns
+// (static_scratch below).
+static __device__ __align__(256) unsigned char scratch[SCALP_STATIC_SCRATCH_BYTES];
+
 namespace {
 
 constexpr size_t kAlign = 256;
@@ -125,6 +132,26 @@ int window_radius(const scalp_grid_t* g) {
 }
 
 long long clear_words(const Layout& L) { return (long long)((L.ctrl + kCtrlWords * 4 - L.acc) / 8); }
+
+// Device address of the current device's scratch, resolved once per device
+// with that device current.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+
+int static_scratch(void** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return SCALP_ERR_HIP;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr)
+            return SCALP_ERR_HIP;
+        g_scratch[dev] = ptr;
+    }
+    *out = g_scratch[dev];
+    return SCALP_OK;
+}
 
 #define CHECK_HIP(expr)                            \
     do {                                           \
@@ -386,6 +413,20 @@ int scalp_run(const scalp_grid_t* g, const scalp_params_t* p, const float* lab,
     CHECK_HIP(enq_iterations(im, p, v, centers, endpoints, labels, counts, s, window_radius(g),
                              clear_words(L)));
     return SCALP_OK;
+}
+
+int scalp_run_static(const scalp_grid_t* g, const scalp_params_t* p, const float* lab,
+                     const float* contour, float* centers, int32_t* endpoints, int32_t* labels,
+                     int32_t* counts, void* stream) {
+    if (!grid_valid(g) || !params_valid(p) || p->reuse_prepared) return SCALP_ERR_ARG;
+    if (scalp_workspace_bytes(g) > SCALP_STATIC_SCRATCH_BYTES) return SCALP_ERR_WORKSPACE;
+    if (!centers || !endpoints || !labels || !counts || !pack_inputs_ok(p, lab, contour))
+        return SCALP_ERR_ARG;
+    void* ws = nullptr;
+    const int rc = static_scratch(&ws);
+    if (rc != SCALP_OK) return rc;
+    return scalp_run(g, p, lab, contour, centers, endpoints, labels, counts, ws,
+                     SCALP_STATIC_SCRATCH_BYTES, stream);
 }
 
 int scalp_graph_create(const scalp_grid_t* g, const scalp_params_t* p, float* centers,

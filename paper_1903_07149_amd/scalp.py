@@ -162,6 +162,18 @@ class Scalp:
                                 *self._ws(), _s(stream)), "scalp_run")
         return RunResult(labels, centers, endpoints, counts)
 
+    def run_static(self, lab, contour, stream=None, out=None, **over) -> RunResult:
+        """run() through scalp_run_static: the library's device scratch instead of
+        a workspace.  The call itself allocates nothing when `out` holds the
+        four output tensors (new_state())."""
+        self._img(lab, contour)
+        centers, endpoints, labels, counts = out if out is not None else self.new_state()
+        p = self._params(**over)
+        check(L.lib().scalp_run_static(ctypes.byref(self.grid), ctypes.byref(p), _p(lab),
+                                       _p(contour), _p(centers), _p(endpoints), _p(labels),
+                                       _p(counts), _s(stream)), "scalp_run_static")
+        return RunResult(labels, centers, endpoints, counts)
+
     def graph(self, centers, endpoints, labels, counts, **over) -> "Graph":
         """hipGraph of the iteration loop on these buffers (the packed image must
         already be in the workspace)."""

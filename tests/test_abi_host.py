@@ -152,3 +152,23 @@ def test_metrics_and_maps_validate_on_host():
     assert lib.scalp_contour_from_lab(5, 5, fake, out, fake, 4095, None) == L.SCALP_ERR_WORKSPACE
     assert lib.scalp_contour_from_lab(5, 0, fake, out, fake, 8, None) == L.SCALP_ERR_ARG
     assert lib.scalp_contour_from_lab(5, 5, None, out, fake, 8, None) == L.SCALP_ERR_ARG
+
+
+def test_static_run_limits_are_checked_on_host():
+    """scalp_run_static rejects, before any HIP call, a workspace larger than
+    its scratch and a request to reuse a packed image."""
+    lib = L.lib()
+    z = ctypes.c_void_p(0x1000)             # never dereferenced: validation fails first
+    p = L.default_params()
+    big = L.make_grid(3840, 2160, 10000)
+    assert L.workspace_bytes(big) > L.STATIC_SCRATCH_BYTES
+    assert lib.scalp_run_static(ctypes.byref(big), ctypes.byref(p), z, z, z, z, z, z,
+                                None) == L.SCALP_ERR_WORKSPACE
+    hd = L.make_grid(1920, 1080, 2000)
+    assert L.workspace_bytes(hd) <= L.STATIC_SCRATCH_BYTES
+    p.reuse_prepared = 1
+    assert lib.scalp_run_static(ctypes.byref(hd), ctypes.byref(p), z, z, z, z, z, z,
+                                None) == L.SCALP_ERR_ARG
+    p.reuse_prepared = 0
+    assert lib.scalp_run_static(ctypes.byref(hd), ctypes.byref(p), z, z, None, z, z, z,
+                                None) == L.SCALP_ERR_ARG
