@@ -94,6 +94,9 @@ def parse():
                     help="also run a plain 512 MiB device copy (counter calibration)")
     ap.add_argument("--launch", default=None,
                     help="WG,LDS_PIXELS: fixed assignment launch shape instead of autotuning")
+    ap.add_argument("--batch-launch", default=None,
+                    help="WG,LDS_PIXELS,BLOCKS_PER_CU: fixed launch shape of the batched "
+                         "persistent kernel instead of autotuning it on the batch")
     return ap.parse_args()
 
 
@@ -147,6 +150,17 @@ def binding_resource(issue, launch_s):
             "lds_TBps": round(lds_b / launch_s / 1e12, 2),
             "lds_frac_of_measured": round(lds_b / launch_s / 1e12 / LDS_MEASURED_TBPS, 4),
             "counter_record": os.path.relpath(ISSUE_FILE, ROOT)}
+
+
+def alu_roofline(flops: float, seconds: float, timed: str) -> dict:
+    """Algorithmic FP32 work of one assignment pass over the measured time of
+    one iteration (`timed` says what that time includes: with the update and
+    projection kernels in it, the rate is a lower bound on the assignment
+    kernel's), against the published FP32 peak."""
+    a = flops / seconds / 1e12
+    return {"bound": "alu", "achieved": round(a, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(a / FP32_PEAK_TFLOPS, 4), "flops_per_iteration": int(flops),
+            "timed": timed}
 
 
 def bench_hard(torch, args):
@@ -362,14 +376,23 @@ def cpu_baseline(img, k, iters):
 
 
 def bench_batched(torch, args, tuned):
-    from paper_1903_07149_amd import synth
+    from paper_1903_07149_amd import counts, synth
     from paper_1903_07149_amd.scalp import Scalp, ScalpBatch
 
+    from paper_1903_07149_amd import autotune
     wls = synth.batch_workloads()
     imgs = [synth.workload_image(w) for w in wls]
-    b = ScalpBatch([(w.width, w.height, w.k) for w in wls], iterations=10, **tuned)
+    shapes = [(w.width, w.height, w.k) for w in wls]
     lab = torch.cat([torch.from_numpy(i.lab.reshape(-1, 3)) for i in imgs]).cuda()
     con = torch.cat([torch.from_numpy(i.contour.reshape(-1)) for i in imgs]).cuda()
+    # launch shape of the persistent kernel, tuned on this batch
+    if args.batch_launch:
+        wg, ldsp, blk = (int(v) for v in args.batch_launch.split(","))
+        tuned_b = {"wg_size": wg, "lds_pixels": ldsp, "persistent_blocks": blk}
+    else:
+        tuned_b = autotune.tune_batch(shapes, lab, con, use_cache=False)
+    log(f"batch launch shape: {tuned_b}")
+    b = ScalpBatch(shapes, iterations=10, **tuned_b)
     st = b.new_state()
     gr = b.graph(lab, con, *st)
     for _ in range(2):
@@ -402,8 +425,19 @@ def bench_batched(torch, args, tuned):
     torch.cuda.synchronize()
     ms1 = t0.elapsed_time(t1) / 2
     px_it = b.total_pixels * 10
+    # algorithmic work of one pass at the initial grid of every image
+    b0 = ScalpBatch(shapes, iterations=0, **tuned_b)
+    _, e0, _, _ = b0.run(lab, con)
+    e0 = e0.cpu().numpy()
+    flops = 0
+    for (s0, s1), g in zip(b0.sp_slices(), b0.grids):
+        flops += counts.pass_work(g.width, g.height, g.nx, g.ny, e0[s0:s1])["flops"]
+    roof = alu_roofline(flops, ms * 1e-3 / 10,
+                        "batched run / 10 (pack, init, then per iteration the persistent "
+                        "assignment, finalize and projection); work at the initial grid")
     return {"workload": f"{len(wls)} ragged Voronoi images, H,W in [240,2160], k = HW/1000, 10 it",
-            "pixels": b.total_pixels, "superpixels": b.total_sp,
+            "roofline": roof,
+            "launch": tuned_b, "pixels": b.total_pixels, "superpixels": b.total_sp,
             "batched_mpx_iter_s": round(px_it / (ms * 1e-3) / 1e6, 1), "batched_ms": round(ms, 3),
             "single_path_mpx_iter_s": round(px_it / (ms1 * 1e-3) / 1e6, 1),
             "single_path_ms": round(ms1, 3)}
@@ -412,7 +446,7 @@ def bench_batched(torch, args, tuned):
 def bench_window(torch, args, img, tuned):
     """Algorithm 1's own candidate rule (windows around each barycenter) on the
     headline workload, one whole job per step as for the headline."""
-    from paper_1903_07149_amd import synth
+    from paper_1903_07149_amd import counts, synth
     from paper_1903_07149_amd._lib import ASSIGN_WINDOW
     from paper_1903_07149_amd.scalp import Scalp
 
@@ -436,7 +470,14 @@ def bench_window(torch, args, img, tuned):
     ms = t0.elapsed_time(t1) / reps
     g3 = Scalp(W, H, wl.k, iterations=wl.iterations, **tuned).run(lab, con)
     agree = float((out[2] == g3.labels).float().mean().item())
-    return {"workload": f"{wl.name}, window of Algorithm 1", "mpx_iter_s":
+    # algorithmic work of one window pass at the initial grid
+    c0, e0, _ = s.init_grid(lab, con)
+    R = int(np.floor(np.sqrt(W * H / wl.k) + 0.5))
+    flops = counts.window_work(W, H, R, c0.cpu().numpy(), e0.cpu().numpy())["flops"]
+    roof = alu_roofline(flops, ms * 1e-3 / wl.iterations,
+                        "run / iterations (pack, init, then per iteration the window "
+                        "assignment, the sums, finalize and projection); work at the initial grid")
+    return {"workload": f"{wl.name}, window of Algorithm 1", "roofline": roof, "mpx_iter_s":
             round(W * H * wl.iterations / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(ms, 3),
             "label_agreement_with_3x3_form": round(agree, 4)}
 
@@ -527,6 +568,23 @@ def quality(torch, tuned):
         r = s.run(lab, con)
         m = metrics(r.labels, gt, num_sp=s.K)
         out[name] = {k: round(v, 4) for k, v in m.items() if k in ("br", "asa", "ue", "co")}
+    # the same ablation where boundary recall does not saturate: 300
+    # ground-truth regions against 250 superpixels; boundary precision is the
+    # recall with the two maps swapped, f their F-measure
+    fine = synth.make_image(W, H, 300, 10.0, 1)
+    flab, fcon, fgt = (torch.from_numpy(a).cuda() for a in (fine.lab, fine.contour, fine.gt))
+    R = int(fine.gt.max()) + 1
+    out["fine_gt_300_regions"] = {}
+    for name, kw in [("slic", dict(lam=1.0, gamma=0.0)), ("path_colour", dict(lam=0.5, gamma=0.0)),
+                     ("contour", dict(lam=1.0)), ("scalp", dict())]:
+        s = Scalp(W, H, 250, **kw, **tuned)
+        r = s.run(flab, fcon)
+        m = metrics(r.labels, fgt, num_sp=s.K, num_regions=R)
+        bp = metrics(fgt, r.labels, num_sp=R, num_regions=s.K)["br"]
+        f = 2 * bp * m["br"] / (bp + m["br"])
+        out["fine_gt_300_regions"][name] = {"br": round(m["br"], 4), "bp": round(bp, 4),
+                                            "f": round(f, 4), "asa": round(m["asa"], 4),
+                                            "ue": round(m["ue"], 4), "co": round(m["co"], 4)}
     # the metric kernels themselves, on the 1920x1080 workload's SCALP labels
     # against its 400-region ground truth
     from paper_1903_07149_amd.metrics import Metrics
@@ -592,7 +650,7 @@ def bench_soft(torch, args):
     torch.cuda.synchronize()
     fwd = sum(e[0].elapsed_time(e[1]) for e in ev) / reps
     bwd = sum(e[1].elapsed_time(e[2]) for e in ev) / reps
-    # the hard path on the same 16 images (one by one, same k and iterations)
+    # the hard path on the same 16 images: one by one (same k and iterations)
     s = Scalp(W, H, k, iterations=iters)
     outs = [s.new_state() for _ in range(B)]
     for b in range(B):
@@ -607,14 +665,48 @@ def bench_soft(torch, args):
     h1.record()
     torch.cuda.synchronize()
     hard = h0.elapsed_time(h1) / reps
+    # ... and as one ragged batch (persistent launch, shape tuned on it)
+    from paper_1903_07149_amd import autotune
+    from paper_1903_07149_amd.scalp import ScalpBatch
+    shapes = [(W, H, k)] * B
+    lab_b, con_b = lab.reshape(-1, 3), con.reshape(-1)
+    if args.batch_launch:
+        wg, ldsp, blk = (int(v) for v in args.batch_launch.split(","))
+        tuned_b = {"wg_size": wg, "lds_pixels": ldsp, "persistent_blocks": blk}
+    else:
+        tuned_b = autotune.tune_batch(shapes, lab_b, con_b, use_cache=False)
+    hb = ScalpBatch(shapes, iterations=iters, **tuned_b)
+    hout = hb.new_state()
+    hb.run(lab_b, con_b, out=hout)
+    torch.cuda.synchronize()
+    h0.record()
+    for _ in range(reps):
+        hb.run(lab_b, con_b, out=hout)
+    h1.record()
+    torch.cuda.synchronize()
+    hard_b = h0.elapsed_time(h1) / reps
     px_it = B * H * W * iters
+    # algorithmic work of one soft assignment pass (every slot's path) at the
+    # endpoints of Theta_0
+    from paper_1903_07149_amd import counts
+    th0 = c_t[0].cpu().numpy()
+    e0 = np.clip(np.floor(th0[..., 3:5] + np.float32(0.5)), 0, [W - 1, H - 1]).astype(np.int64)
+    g = eng.grid
+    flops = sum(counts.pass_work(W, H, g.nx, g.ny, e0[bb])["flops"] for bb in range(B))
+    roof = alu_roofline(flops, fwd * 1e-3 / iters,
+                        "forward / iterations (soft assignment, softmax and soft update); "
+                        "work at Theta_0")
     return {"workload": f"{B} x {W}x{H} Voronoi images, k={k}, T={T}, {iters} iterations",
+            "roofline_forward": roof,
             "wg_size": soft_wg,
             "fwd_bwd_mpx_iter_s": round(px_it / ((fwd + bwd) * 1e-3) / 1e6, 1),
             "fwd_ms": round(fwd, 3), "bwd_ms": round(bwd, 3),
             "fwd_mpx_iter_s": round(px_it / (fwd * 1e-3) / 1e6, 1),
             "hard_same_images_mpx_iter_s": round(px_it / (hard * 1e-3) / 1e6, 1),
-            "hard_same_images_ms": round(hard, 3)}
+            "hard_same_images_ms": round(hard, 3),
+            "hard_same_images_batched_mpx_iter_s": round(px_it / (hard_b * 1e-3) / 1e6, 1),
+            "hard_same_images_batched_ms": round(hard_b, 3),
+            "hard_same_images_batched_launch": tuned_b}
 
 
 def main():

@@ -91,6 +91,10 @@ typedef struct {
                                 every candidate is walked.  The results are
                                 the same either way; 0 or 1, else
                                 SCALP_ERR_ARG                                */
+    int32_t persistent_blocks; /* tuning: workgroups per compute unit of the
+                                batched persistent launch, 0 (default: as many
+                                as fit) or 1..16 (capped at what fits); the
+                                results do not depend on it                  */
 } scalp_params_t;
 
 /* Candidate rule of the assignment.

@@ -38,3 +38,27 @@ def pass_work(width: int, height: int, nx: int, ny: int, endpoints: np.ndarray) 
     return {"samples": samples, "candidates": cands,
             "flops": FLOPS_PER_SAMPLE * samples + FLOPS_PER_CANDIDATE * cands,
             "lds_bytes": BYTES_PER_SAMPLE * samples}
+
+
+def window_work(width: int, height: int, radius: int, centres: np.ndarray,
+                endpoints: np.ndarray) -> dict:
+    """samples, candidates, flops of one pass of the window form: every pixel of
+    every cluster's (2R+1)^2 window (around its barycenter rounded to a pixel,
+    clamped into the image, clipped by the borders) walks its path to the
+    cluster's endpoint."""
+    W, H, R = int(width), int(height), int(radius)
+    c = np.asarray(centres, np.float32).reshape(-1, 5)
+    ep = np.asarray(endpoints, np.int64).reshape(-1, 2)
+    wx = np.clip(np.floor(c[:, 3] + np.float32(0.5)).astype(np.int64), 0, W - 1)
+    wy = np.clip(np.floor(c[:, 4] + np.float32(0.5)).astype(np.int64), 0, H - 1)
+    samples = 0
+    cands = 0
+    for k in range(ep.shape[0]):
+        xs = np.arange(max(0, wx[k] - R), min(W, wx[k] + R + 1))
+        ys = np.arange(max(0, wy[k] - R), min(H, wy[k] + R + 1))
+        n = np.maximum(np.abs(ep[k, 0] - xs)[None, :], np.abs(ep[k, 1] - ys)[:, None])
+        samples += int((n + 1).sum())
+        cands += n.size
+    return {"samples": samples, "candidates": cands,
+            "flops": FLOPS_PER_SAMPLE * samples + FLOPS_PER_CANDIDATE * cands,
+            "lds_bytes": BYTES_PER_SAMPLE * samples}

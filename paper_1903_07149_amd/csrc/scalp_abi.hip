@@ -53,6 +53,7 @@ bool params_valid(const scalp_params_t* p) {
     if (p->contour_source != SCALP_CONTOUR_INPUT && p->contour_source != SCALP_CONTOUR_GRADIENT)
         return false;
     if (p->exact_pruning != 0 && p->exact_pruning != 1) return false;
+    if (p->persistent_blocks < 0 || p->persistent_blocks > 16) return false;
     return true;
 }
 
@@ -65,6 +66,7 @@ Tuning tuning_of(const scalp_params_t* p) {
     Tuning t;
     t.wg = p->wg_size == 0 ? 1024 : p->wg_size;
     t.lds_pixels = p->lds_pixels > 0 ? p->lds_pixels : default_lds_pixels();
+    t.blocks_per_cu = p->persistent_blocks;
     return t;
 }
 
@@ -267,6 +269,7 @@ int scalp_default_params(scalp_params_t* out) {
     out->assign_mode = SCALP_ASSIGN_GRID3X3;
     out->contour_source = SCALP_CONTOUR_INPUT;
     out->exact_pruning = 1;
+    out->persistent_blocks = 0;
     return SCALP_OK;
 }
 

@@ -901,6 +901,7 @@ int persistent_grid(const Tuning& t) {
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_assign_persistent<256>, 256,
                                                          dyn_lds(t));
     if (e != hipSuccess || per < 1) per = 1;
+    if (t.blocks_per_cu > 0 && t.blocks_per_cu < per) per = t.blocks_per_cu;
     return cus * per;
 }
 

@@ -18,3 +18,28 @@ def test_sample_count_matches_oracle(orc):
         w = counts.pass_work(W, H, g.nx, g.ny, e)
         assert w["samples"] == samples
         assert w["flops"] == 10 * samples + 16 * w["candidates"]
+
+
+def test_window_sample_count_brute_force(orc):
+    """The window form's sample count, summed per cluster over its window, equals
+    the count summed per pixel over the clusters whose window contains it."""
+    for (W, H, k, seed) in [(37, 23, 12, 4), (60, 41, 30, 5)]:
+        lab, con = synth.random_lab(W, H, seed)
+        g = orc.grid(W, H, k)
+        c, e, _ = orc.init_grid(g, lab)
+        rng = np.random.default_rng(seed)
+        c[:, 3] = np.clip(c[:, 3] + rng.uniform(-4, 4, g.num_sp), 0, W - 1)
+        c[:, 4] = np.clip(c[:, 4] + rng.uniform(-4, 4, g.num_sp), 0, H - 1)
+        e = orc.round_endpoints(g, c)
+        R = orc.window_radius(g)
+        w = counts.window_work(W, H, R, c, e)
+        cx = [min(max(int(np.floor(np.float32(c[q, 3]) + np.float32(0.5))), 0), W - 1) for q in range(g.num_sp)]
+        cy = [min(max(int(np.floor(np.float32(c[q, 4]) + np.float32(0.5))), 0), H - 1) for q in range(g.num_sp)]
+        samples = cands = 0
+        for y in range(H):
+            for x in range(W):
+                for q in range(g.num_sp):
+                    if abs(x - cx[q]) <= R and abs(y - cy[q]) <= R:
+                        samples += max(abs(int(e[q, 0]) - x), abs(int(e[q, 1]) - y)) + 1
+                        cands += 1
+        assert (w["samples"], w["candidates"]) == (samples, cands)

@@ -17,7 +17,8 @@ def _batch(n, seed0, lo, hi, per_px):
 
 
 @pytest.mark.parametrize("tune", [dict(), dict(wg_size=256), dict(wg_size=512),
-                                  dict(lds_pixels=700), dict(exact_pruning=0)])
+                                  dict(lds_pixels=700), dict(exact_pruning=0),
+                                  dict(persistent_blocks=1), dict(wg_size=256, persistent_blocks=3)])
 def test_batched_equals_single_and_oracle(orc, tune):
     from paper_1903_07149_amd.scalp import Scalp, ScalpBatch
     orc.set_threads(min(16, os.cpu_count() or 1))
@@ -67,18 +68,24 @@ def test_batched_graph_replays():
 @pytest.mark.timeout(400)   # generating the 64 images takes most of it
 def test_batched_full_size_workload(orc):
     """The benchmark's batch (64 ragged images, 92 Mpx, k = HW/1000, 10 iterations)
-    in the launch shape the benchmark uses: every image equals the single-image
-    path bit for bit, and three sampled images (the smallest, a middle one and
-    the largest) equal the oracle."""
+    in the launch shape the benchmark uses (the autotuner's choice for this
+    batch): every image equals the single-image path bit for bit, and three
+    sampled images (the smallest, a middle one and the largest) equal the
+    oracle."""
+    from paper_1903_07149_amd import autotune
     from paper_1903_07149_amd.scalp import Scalp, ScalpBatch
     orc.set_threads(min(16, os.cpu_count() or 1))
     wls = synth.batch_workloads()
     assert len(wls) == 64
     imgs = [synth.workload_image(w) for w in wls]
-    b = ScalpBatch([(w.width, w.height, w.k) for w in wls], iterations=10)
+    shapes = [(w.width, w.height, w.k) for w in wls]
     lab = dev(np.concatenate([i.lab.reshape(-1, 3) for i in imgs]))
     con = dev(np.concatenate([i.contour.reshape(-1) for i in imgs]))
-    say("batched full size")
+    say("batched full size: tuning")
+    tuned = autotune.tune_batch(shapes, lab, con, use_cache=False)
+    assert tuned in autotune.BATCH_CANDIDATES
+    b = ScalpBatch(shapes, iterations=10, **tuned)
+    say("batched full size", tuned)
     c, e, l, n = (host(t) for t in b.run(lab, con))
     del lab, con
     sizes = [w.width * w.height for w in wls]

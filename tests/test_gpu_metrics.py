@@ -111,6 +111,44 @@ def test_metrics_of_a_run_and_ablation():
     assert rows["scalp"]["sp_boundary"] < rows["slic"]["sp_boundary"]
 
 
+def test_ablation_with_a_finer_ground_truth():
+    """The distance ablation of Sec. III-B where boundary recall does not
+    saturate: 300 ground-truth regions against 250 superpixels (481x321, noise
+    sigma 10), so superpixel boundaries cannot reach every region boundary.
+    The paper compares the settings by precision-recall; here boundary recall
+    (GT boundary pixels with a superpixel boundary pixel closer than 2),
+    boundary precision (the same measure with the two maps swapped) and their
+    F-measure.  As in Sec. III-B: the contour term raises recall (over SLIC,
+    and over the path colour alone), and each term raises the F-measure over
+    SLIC's, full SCALP scoring best."""
+    from paper_1903_07149_amd.metrics import metrics
+    from paper_1903_07149_amd.scalp import Scalp
+    img = synth.make_image(481, 321, 300, 10.0, 1)
+    H, W = img.contour.shape
+    R = int(img.gt.max()) + 1
+    lab, con, gt = dev(img.lab), dev(img.contour), dev(img.gt)
+    rows = {}
+    for name, kw in [("slic", dict(lam=1.0, gamma=0.0)), ("path_colour", dict(lam=0.5, gamma=0.0)),
+                     ("contour", dict(lam=1.0)), ("scalp", dict())]:
+        s = Scalp(W, H, 250, **kw)
+        say("fine-gt ablation", name)
+        r = s.run(lab, con)
+        m = metrics(r.labels, gt, num_sp=s.K, num_regions=R)
+        bp = metrics(gt, r.labels, num_sp=R, num_regions=s.K)["br"]   # precision
+        assert m["br"] == M.boundary_recall(host(r.labels), img.gt, 2.0)
+        assert bp == M.boundary_recall(img.gt, host(r.labels), 2.0)
+        f = 2 * bp * m["br"] / (bp + m["br"])
+        rows[name] = dict(br=m["br"], bp=bp, f=f)
+        print(name, {k: round(v, 4) for k, v in rows[name].items()})
+    assert all(v["br"] < 0.99 for v in rows.values())            # not saturated
+    assert rows["contour"]["br"] > rows["slic"]["br"]
+    assert rows["scalp"]["br"] > rows["path_colour"]["br"]
+    assert rows["path_colour"]["f"] > rows["slic"]["f"]
+    assert rows["contour"]["f"] > rows["slic"]["f"]
+    assert rows["scalp"]["f"] > max(rows["slic"]["f"], rows["path_colour"]["f"],
+                                    rows["contour"]["f"])
+
+
 def test_reusable_metrics_call_matches():
     """metrics.Metrics (workspace allocated once, result left on the device)
     gives what metrics() gives, on repeated calls."""
