@@ -279,7 +279,9 @@ int scalp_batched_graph_create(const scalp_batch_desc_t* descs, int32_t n_images
  *   q_t       : float32 [iters][B][9][H][W]   (output)
  *   saved     : scalp_soft_saved_bytes() bytes (output of forward, input of
  *               backward): per-iteration factors A, B of Eqs. (1)-(2) and
- *               the FP64 masses sum Q.
+ *               the FP64 masses sum Q (A and B are written only for slots
+ *               inside the grid whose Q the exact bound does not prove to
+ *               be 0: the only ones the backward reads).
  * lab: float32 [B][H][W][3]; contour: float32 [B][H][W]; 1 <= B <= 65535.
  * The soft entry points support only SCALP_ASSIGN_GRID3X3 and
  * SCALP_CONTOUR_INPUT.
@@ -293,12 +295,13 @@ int scalp_soft_forward(const scalp_grid_t* g, const scalp_params_t* p, float tem
  * (grad_centers: [B][K'][5]) with respect to lab (grad_lab: [B][H][W][3],
  * output) and contour (grad_contour: [B][H][W], output).  Path samples are
  * recomputed, not stored; slots whose Q is below 2^-24 contribute no path
- * terms (each is proportional to Q).  The gradient tiles of a cell take
- * min(lds_pixels, 3968) texels; a cell whose rectangle is larger scatters
- * to global memory instead.  contour is always required (dw/dC
+ * terms (each is proportional to Q).  Per cell, each slot's per-sample
+ * weights go to an LDS tile over the box of its walked paths (FP64, at most
+ * min(16 lds_pixels, 58 KiB) bytes of tiles in all); a slot whose tile does
+ * not fit scatters to global memory instead.  contour is always required (dw/dC
  * needs it); lab may be null when reuse_prepared is set and the workspace
- * holds the packed image of the forward call.  FP32 with float atomics: not
- * bit-reproducible. */
+ * holds the packed image of the forward call.  FP32 with float atomics, the
+ * centre gradients summed in FP64: not bit-reproducible. */
 int scalp_soft_backward(const scalp_grid_t* g, const scalp_params_t* p, float temperature,
                         int32_t batch, const float* lab, const float* contour,
                         const float* centers_t, const float* q_t, const void* saved,

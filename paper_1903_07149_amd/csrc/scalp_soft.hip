@@ -187,8 +187,9 @@ __global__ __launch_bounds__(WG) void k_soft_assign(SoftImg s, const float4* __r
     // (D - Dmin) / T > 110 in FP64; Dmin <= best, the smallest D computed so
     // far, and both FP64 steps are monotone, so a slot with
     // (LB - best) / T > 110 gets Q = 0 whatever its walk would give: its D is
-    // written as +inf (the softmax maps it to 0) and its saved factors as 0
-    // (the backward reads them only where dL/dD, a multiple of Q, is not 0).
+    // written as +inf (the softmax maps it to 0) and its saved factors are not
+    // written (the backward reads them only where dL/dD, a multiple of Q, is
+    // not 0; slots outside the grid likewise).
     // The own cell is visited first, then the edge neighbours, then the
     // corners; each slot is written separately, so the order changes nothing.
     const float4 fown = mine ? img[p] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -199,13 +200,7 @@ __global__ __launch_bounds__(WG) void k_soft_assign(SoftImg s, const float4* __r
         const int j = (int)((kOrder >> (4 * t)) & 15ULL);
         const int k = sh.cand[j].k;
         const long long o = base + (long long)j * s.N;
-        if (k < 0) {                                            // uniform
-            if (mine) {
-                fa[o] = 0.0f;
-                fb[o] = 0.0f;
-            }
-            continue;
-        }
+        if (k < 0) continue;                                    // uniform
         const float l = sh.cand[j].l, a = sh.cand[j].a, bb = sh.cand[j].b;
         const int cx = sh.cand[j].cx, cy = sh.cand[j].cy;
         const int tx0 = sh.cand[j].tx0, ty0 = sh.cand[j].ty0, tw = sh.cand[j].tw;
@@ -224,8 +219,6 @@ __global__ __launch_bounds__(WG) void k_soft_assign(SoftImg s, const float4* __r
         const float lb = lambda * colour_dist(fown, l, a, bb) + ds * s.spw;
         if (s.prune && ((double)lb - (double)best) / s.temp > 110.0) {
             q[o] = INFINITY;
-            fa[o] = 0.0f;
-            fb[o] = 0.0f;
             continue;
         }
         const int dx = cx - x, dy = cy - y;
