@@ -487,7 +487,7 @@ __global__ void k_soft_bwd_pass(SoftImg s, const double* __restrict__ z,
 constexpr int kBwdBatch = 192;
 constexpr int kBwdCopies = 8;
 // Texels per thread and trip of the fold.
-constexpr int kFold = 4;
+constexpr int kFold = 2;
 
 // Where the backward path pass of one work item keeps its tiles: per slot,
 // the box [bx0, bx1) x [by0, by1) of the pixels whose path to the slot it
