@@ -183,6 +183,39 @@ __device__ __forceinline__ void fill_table(float2* tab, const float4* __restrict
     }
 }
 
+// The same table, filled column by column: with R = WG / tw >= 1 rows per
+// pass, lane tid < R tw keeps column c = tid mod tw of rows r0 = tid / tw,
+// r0 + R, r0 + 2R, ... (entry e = r tw + c, starting at e = tid), so an
+// entry costs one texel load, its colour distance and two index adds.
+// r0 = floor(tid m / 2^24) with m = ceil(2^24 / tw): exact for tid < 2^10
+// and tw < 2^14, since m tw - 2^24 < tw and tid (m tw - 2^24) < 2^24.  rows:
+// the rectangle's rows; the caller supplies R and m (computed once per
+// table) and takes fill_table when tw > WG.
+template <int WG>
+__device__ __forceinline__ void fill_table_cols(float2* tab, const float4* __restrict__ img,
+                                                int W, int tx0, int ty0, int tw, int rows, int R,
+                                                unsigned m, float l, float a, float b) {
+    const int tid = threadIdx.x;
+    const int r0 = (int)__umulhi((unsigned)tid << 8, m);
+    if (r0 >= R) return;                           // lanes past R tw
+    const int c = tid - r0 * tw;
+    int p = (ty0 + r0) * W + min(tx0 + c, W - 1);  // < W H < 2^31
+    const int dp = R * W, de = R * tw;
+    int e = tid, r = r0;
+    for (; r + R < rows; r += 2 * R) {
+        const float4 f0 = img[p];
+        const float4 f1 = img[p + dp];
+        tab[e] = make_float2(colour_dist(f0, l, a, b), f0.w);
+        tab[e + de] = make_float2(colour_dist(f1, l, a, b), f1.w);
+        p += 2 * dp;
+        e += 2 * de;
+    }
+    if (r < rows) {
+        const float4 f = img[p];
+        tab[e] = make_float2(colour_dist(f, l, a, b), f.w);
+    }
+}
+
 // The walk over a per-candidate LDS table of (colour distance, w) pairs: the
 // colour distance of a texel to the candidate does not depend on the pixel
 // the path starts from, so it is computed once per texel (same FP32

@@ -44,6 +44,8 @@ struct Cand {
     int cx, cy;       // path endpoint
     float dcc, wc;    // colour distance and w of the endpoint sample
     int tx0, ty0, tw, th;   // its LDS table: origin, row pitch, rows; tw == 0: paths read global memory
+    int rpp;                // rows per pass of the column-wise fill (WG / tw, 0 when tw > WG)
+    unsigned mag;           // ceil(2^24 / tw): lane tid's first row is tid * mag >> 24
 };
 
 // Copies of the update bins: the lanes of a wave mostly pick the same
@@ -116,6 +118,8 @@ __device__ __forceinline__ void process_cell(const Img& im, int cell, int slice,
         const int ii = ci + tid / 3 - 1, jj = cj + tid % 3 - 1;
         c.tw = 0;
         c.tx0 = c.ty0 = c.th = 0;
+        c.rpp = 0;
+        c.mag = 0u;
         if (ii >= 0 && ii < ny && jj >= 0 && jj < nx) {
             const int k = ii * nx + jj;
             const float* ck = centres + 5LL * (im.sp + k);
@@ -134,6 +138,8 @@ __device__ __forceinline__ void process_cell(const Img& im, int cell, int slice,
             const int pitch = (ax1 - ax0) + ((24 - (ax1 - ax0) % 16) % 16);
             if ((long long)pitch * (ay1 - ay0) <= cap) {
                 c.tx0 = ax0; c.ty0 = ay0; c.tw = pitch; c.th = ay1 - ay0;
+                c.rpp = WG / pitch;
+                c.mag = (0x1000000u + (unsigned)pitch - 1u) / (unsigned)pitch;
             }
         } else {
             c.k = -1;
@@ -173,7 +179,12 @@ __device__ __forceinline__ void process_cell(const Img& im, int cell, int slice,
         const int tw = sh.cand[j].tw, tx0 = sh.cand[j].tx0, ty0 = sh.cand[j].ty0;
         float2* tab = lds + (buf ? cap : 0);
         if (tw > 0) {                              // uniform
-            fill_table<WG>(tab, img, W, tx0, ty0, tw, tw * sh.cand[j].th, l, a, b);
+            const int rpp = sh.cand[j].rpp;
+            if (rpp > 0)                           // uniform
+                fill_table_cols<WG>(tab, img, W, tx0, ty0, tw, sh.cand[j].th, rpp,
+                                    sh.cand[j].mag, l, a, b);
+            else
+                fill_table<WG>(tab, img, W, tx0, ty0, tw, tw * sh.cand[j].th, l, a, b);
             __syncthreads();
             buf ^= 1;
         }

@@ -103,6 +103,25 @@ def test_assign_long_paths(orc, W, H, k, tune):
     assert (lbl == ol).all(), f"{int((lbl != ol).sum())} labels differ"
 
 
+@pytest.mark.parametrize("W,H,k,tune", [(481, 321, 30, {"lds_pixels": 1100}),
+                                         (600, 600, 4, {}),
+                                         (600, 600, 4, {"wg_size": 256, "lds_pixels": 4500}),
+                                         (700, 500, 12, {"lds_pixels": 9728}),
+                                         (97, 900, 3, {"wg_size": 512, "lds_pixels": 1000})])
+def test_assign_tables_beyond_budget(orc, W, H, k, tune):
+    """Cells whose table rectangles exceed the LDS budget by a few to tens of
+    times (their paths read global memory) beside candidates whose tables
+    fit, with endpoints jittered above, below and inside the cells."""
+    img = _image(W, H, 11, regions=12)
+    g = orc.grid(W, H, k)
+    c, e = perturbed_state(orc, g, img.lab, seed=W * 3 + k, jitter=0.4 * g.r + 1)
+    s = _scalp(W, H, k, **tune)
+    say("assign tables beyond budget", W, H, k, tune)
+    lbl = host(s.assign(dev(img.lab), dev(img.contour), dev(c), dev(e)))
+    ol, _, _ = orc.assign(g, img.lab, orc.wmap(img.contour), c, e)
+    assert (lbl == ol).all(), f"{int((lbl != ol).sum())} labels differ"
+
+
 def test_assign_paths_beyond_carry_range(orc):
     """Caller-supplied endpoints of the last three superpixels of a 60000-pixel
     row at its left end: the paths to them from the right end have more than
