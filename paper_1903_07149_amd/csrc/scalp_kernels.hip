@@ -347,7 +347,11 @@ __global__ __launch_bounds__(WG) void k_assign_window(Img im, const float4* __re
     const bool staged = (long long)(rx1 - rx0) * (ry1 - ry0) <= 2LL * cap;
     const int rw = rx1 - rx0;
     if (staged) {
-        fill_table<WG>(win_tab, img, W, rx0, ry0, rw, rw * (ry1 - ry0), l, a, b);
+        if (rw <= WG)                                // uniform
+            fill_table_cols<WG>(win_tab, img, W, rx0, ry0, rw, ry1 - ry0, WG / rw,
+                                (0x1000000u + (unsigned)rw - 1u) / (unsigned)rw, l, a, b);
+        else
+            fill_table<WG>(win_tab, img, W, rx0, ry0, rw, rw * (ry1 - ry0), l, a, b);
     }
     __syncthreads();
     const float4 fc = img[(long long)cy * W + cx];

@@ -56,6 +56,8 @@ struct SoftCand {
     int cx, cy;
     float dcc, wc;
     int tx0, ty0, tw, th;       // forward: table origin, row pitch, rows; tw == 0: not staged
+    int rpp;                    // rows per pass of the column-wise fill (WG / tw, 0 when tw > WG)
+    unsigned mag;               // ceil(2^24 / tw): lane tid's first row is tid * mag >> 24
 };
 
 struct SoftShared {
@@ -161,12 +163,16 @@ __global__ __launch_bounds__(WG) void k_soft_assign(SoftImg s, const float4* __r
         SoftCand& c = sh.cand[tid];
         c.tw = 0;
         c.tx0 = c.ty0 = c.th = 0;
+        c.rpp = 0;
+        c.mag = 0u;
         if (c.k >= 0) {
             const int tx0 = min(ix0, c.cx), ty0 = min(y0, c.cy);
             const int rwid = max(ix1, c.cx + 1) - tx0, th = max(y1, c.cy + 1) - ty0;
             const int tw = rwid + (24 - rwid % 16) % 16;        // pitch: 8 (mod 16) entries
             if ((long long)tw * th <= cap) {
                 c.tx0 = tx0; c.ty0 = ty0; c.tw = tw; c.th = th;
+                c.rpp = WG / tw;
+                c.mag = (0x1000000u + (unsigned)tw - 1u) / (unsigned)tw;
             }
         }
     }
@@ -207,7 +213,12 @@ __global__ __launch_bounds__(WG) void k_soft_assign(SoftImg s, const float4* __r
         const bool staged = tw > 0;
         float2* tab = tabs + (buf ? cap : 0);
         if (staged) {                                           // uniform
-            fill_table<WG>(tab, img, W, tx0, ty0, tw, tw * sh.cand[j].th, l, a, bb);
+            const int rpp = sh.cand[j].rpp;
+            if (rpp > 0)                                        // uniform
+                fill_table_cols<WG>(tab, img, W, tx0, ty0, tw, sh.cand[j].th, rpp,
+                                    sh.cand[j].mag, l, a, bb);
+            else
+                fill_table<WG>(tab, img, W, tx0, ty0, tw, tw * sh.cand[j].th, l, a, bb);
             __syncthreads();
             buf ^= 1;
         }
