@@ -502,10 +502,22 @@ def bench_multiscale(torch, args, tuned):
     from paper_1903_07149_amd import synth
     from paper_1903_07149_amd.maps import MultiScale, boundary_map
 
+    from paper_1903_07149_amd import autotune
+    from paper_1903_07149_amd.maps import scales
+
     img = synth.workload_image(synth.BSD_SHAPE)
     H, W = img.contour.shape
-    ms = MultiScale(W, H, **{k: v for k, v in tuned.items()})
-    lab_b, con_b = ms.stack(torch.from_numpy(img.lab).cuda(), torch.from_numpy(img.contour).cuda())
+    ks = scales()
+    lab_b, con_b = MultiScale.stack_of(len(ks), torch.from_numpy(img.lab).cuda(),
+                                       torch.from_numpy(img.contour).cuda())
+    # launch shape of the persistent kernel, tuned on this batch of 12 scales
+    if args.batch_launch:
+        wg, ldsp, blk = (int(v) for v in args.batch_launch.split(","))
+        tuned_ms = {"wg_size": wg, "lds_pixels": ldsp, "persistent_blocks": blk}
+    else:
+        tuned_ms = autotune.tune_batch([(W, H, k) for k in ks], lab_b, con_b, use_cache=False)
+    log(f"multiscale launch shape: {tuned_ms}")
+    ms = MultiScale(W, H, ks, **tuned_ms)
     state = ms.batch.new_state()
     n = len(ms.ks)
 
@@ -515,7 +527,7 @@ def bench_multiscale(torch, args, tuned):
 
     ms_step = _time(torch, step, max(2, args.steps))
     return {"workload": f"481x321, k in {ms.ks}, 10 iterations, one batch + boundary map",
-            "ms_per_image": round(ms_step, 3), "images_per_s": round(1e3 / ms_step, 1),
+            "launch": tuned_ms, "ms_per_image": round(ms_step, 3), "images_per_s": round(1e3 / ms_step, 1),
             "mpx_iter_s": round(n * W * H * 10 / (ms_step * 1e-3) / 1e6, 1)}
 
 

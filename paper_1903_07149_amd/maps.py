@@ -52,7 +52,11 @@ class MultiScale:
     def stack(self, lab: torch.Tensor, contour: torch.Tensor | None):
         """The image (and its contour map, if given) repeated once per scale,
         in the batch's concatenated layout."""
-        n = len(self.ks)
+        return self.stack_of(len(self.ks), lab, contour)
+
+    @staticmethod
+    def stack_of(n: int, lab: torch.Tensor, contour: torch.Tensor | None):
+        """The image (and its contour map, if given) repeated n times."""
         lab_b = lab.reshape(1, -1, 3).expand(n, -1, -1).reshape(-1, 3).contiguous()
         con_b = None if contour is None else contour.reshape(1, -1).expand(n, -1).reshape(-1).contiguous()
         return lab_b, con_b
