@@ -93,11 +93,21 @@ def parse():
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 512 MiB device copy (counter calibration)")
     ap.add_argument("--launch", default=None,
-                    help="WG,LDS_PIXELS: fixed assignment launch shape instead of autotuning")
+                    help="WG,LDS_PIXELS[,TABLE_MODE]: fixed assignment launch shape instead of "
+                         "autotuning")
     ap.add_argument("--batch-launch", default=None,
-                    help="WG,LDS_PIXELS,BLOCKS_PER_CU: fixed launch shape of the batched "
-                         "persistent kernel instead of autotuning it on the batch")
+                    help="WG,LDS_PIXELS,BLOCKS_PER_CU[,TABLE_MODE]: fixed launch shape of the "
+                         "batched persistent kernel instead of autotuning it on the batch")
     return ap.parse_args()
+
+
+def batch_launch(text: str) -> dict:
+    """--batch-launch WG,LDS_PIXELS,BLOCKS_PER_CU[,TABLE_MODE] as launch keywords."""
+    v = [int(x) for x in text.split(",")]
+    out = {"wg_size": v[0], "lds_pixels": v[1], "persistent_blocks": v[2]}
+    if len(v) > 3:
+        out["table_mode"] = v[3]
+    return out
 
 
 def traffic_for(digest: str):
@@ -173,8 +183,10 @@ def bench_hard(torch, args):
     lab = torch.from_numpy(img.lab).cuda()
     con = torch.from_numpy(img.contour).cuda()
     if args.launch:
-        wg, ldsp = (int(v) for v in args.launch.split(","))
-        tuned = {"wg_size": wg, "lds_pixels": ldsp}
+        v = [int(x) for x in args.launch.split(",")]
+        tuned = {"wg_size": v[0], "lds_pixels": v[1]}
+        if len(v) > 2:
+            tuned["table_mode"] = v[2]
         log(f"fixed launch shape: {tuned}")
     else:
         tuned = autotune.tune(W, H, wl.k, lab, con, use_cache=False)
@@ -387,8 +399,7 @@ def bench_batched(torch, args, tuned):
     con = torch.cat([torch.from_numpy(i.contour.reshape(-1)) for i in imgs]).cuda()
     # launch shape of the persistent kernel, tuned on this batch
     if args.batch_launch:
-        wg, ldsp, blk = (int(v) for v in args.batch_launch.split(","))
-        tuned_b = {"wg_size": wg, "lds_pixels": ldsp, "persistent_blocks": blk}
+        tuned_b = batch_launch(args.batch_launch)
     else:
         tuned_b = autotune.tune_batch(shapes, lab, con, use_cache=False)
     log(f"batch launch shape: {tuned_b}")
@@ -512,8 +523,7 @@ def bench_multiscale(torch, args, tuned):
                                        torch.from_numpy(img.contour).cuda())
     # launch shape of the persistent kernel, tuned on this batch of 12 scales
     if args.batch_launch:
-        wg, ldsp, blk = (int(v) for v in args.batch_launch.split(","))
-        tuned_ms = {"wg_size": wg, "lds_pixels": ldsp, "persistent_blocks": blk}
+        tuned_ms = batch_launch(args.batch_launch)
     else:
         tuned_ms = autotune.tune_batch([(W, H, k) for k in ks], lab_b, con_b, use_cache=False)
     log(f"multiscale launch shape: {tuned_ms}")
@@ -683,8 +693,7 @@ def bench_soft(torch, args):
     shapes = [(W, H, k)] * B
     lab_b, con_b = lab.reshape(-1, 3), con.reshape(-1)
     if args.batch_launch:
-        wg, ldsp, blk = (int(v) for v in args.batch_launch.split(","))
-        tuned_b = {"wg_size": wg, "lds_pixels": ldsp, "persistent_blocks": blk}
+        tuned_b = batch_launch(args.batch_launch)
     else:
         tuned_b = autotune.tune_batch(shapes, lab_b, con_b, use_cache=False)
     hb = ScalpBatch(shapes, iterations=iters, **tuned_b)

@@ -95,6 +95,18 @@ typedef struct {
                                 batched persistent launch, 0 (default: as many
                                 as fit) or 1..16 (capped at what fits); the
                                 results do not depend on it                  */
+    int32_t table_mode;      /* tuning of the 3x3 assignment: 0 (default): a
+                                (colour distance, w) table per candidate over
+                                the rectangle of the work item's pixels and the
+                                endpoint, two tables of lds_pixels entries
+                                alternating, one barrier per candidate; 1: the
+                                waves with a lane that walks the candidate vote
+                                the table down to the box of their pixels and
+                                the endpoint, one table of twice as many
+                                entries, two barriers per candidate, no table
+                                when no lane walks (pays off for cells much
+                                larger than the workgroup).  The results do
+                                not depend on it; 0 or 1, else SCALP_ERR_ARG */
 } scalp_params_t;
 
 /* Candidate rule of the assignment.

@@ -56,7 +56,8 @@ class Params(ctypes.Structure):
                 ("project", ctypes.c_int32), ("reuse_prepared", ctypes.c_int32),
                 ("lds_pixels", ctypes.c_int32), ("wg_size", ctypes.c_int32),
                 ("assign_mode", ctypes.c_int32), ("contour_source", ctypes.c_int32),
-                ("exact_pruning", ctypes.c_int32), ("persistent_blocks", ctypes.c_int32)]
+                ("exact_pruning", ctypes.c_int32), ("persistent_blocks", ctypes.c_int32),
+                ("table_mode", ctypes.c_int32)]
 
 
 ASSIGN_GRID3X3 = 0

@@ -5,8 +5,9 @@ bit-exact against the oracle by the GPU tests): the workgroup size (lanes
 of one work item, one pixel each, sharing its LDS tables), the LDS budget
 in 16-byte units (the size of the two per-candidate tables, which bounds
 which candidates walk over LDS rather than global memory, and how many
-workgroups fit on a CU) and, for a ragged batch, the number of persistent
-workgroups per CU.
+workgroups fit on a CU), the table mode (per-candidate tables over the work
+item's rectangle, or voted down to the walking waves' box) and, for a ragged
+batch, the number of persistent workgroups per CU.
 
 tune() times one fused assignment pass (`scalp_assign_accumulate`) per
 configuration with HIP events on the workload's own image and superpixel
@@ -26,11 +27,15 @@ import torch
 
 from .scalp import Scalp, ScalpBatch
 
-CANDIDATES = [dict(wg_size=w, lds_pixels=p) for w in (256, 512, 1024)
-              for p in (1, 2400, 3200, 3840, 4800)]
-BATCH_CANDIDATES = [dict(wg_size=w, lds_pixels=p, persistent_blocks=b)
-                    for w in (256, 512, 1024) for p in (2400, 3840, 4800, 9728)
-                    for b in (0, 1, 2)]
+CANDIDATES = ([dict(wg_size=w, lds_pixels=p) for w in (256, 512, 1024)
+               for p in (1, 2400, 3200, 3840, 4800)] +
+              [dict(wg_size=w, lds_pixels=p, table_mode=1) for w in (256, 512, 1024)
+               for p in (2400, 4800, 9728)])
+BATCH_CANDIDATES = ([dict(wg_size=w, lds_pixels=p, persistent_blocks=b)
+                     for w in (256, 512, 1024) for p in (2400, 3840, 4800, 9728)
+                     for b in (0, 1, 2)] +
+                    [dict(wg_size=w, lds_pixels=p, persistent_blocks=b, table_mode=1)
+                     for w in (256, 512, 1024) for p in (2400, 4800, 9728) for b in (0, 1)])
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_cache.json")
 
 

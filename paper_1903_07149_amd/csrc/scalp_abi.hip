@@ -54,6 +54,7 @@ bool params_valid(const scalp_params_t* p) {
         return false;
     if (p->exact_pruning != 0 && p->exact_pruning != 1) return false;
     if (p->persistent_blocks < 0 || p->persistent_blocks > 16) return false;
+    if (p->table_mode != 0 && p->table_mode != 1) return false;
     return true;
 }
 
@@ -67,6 +68,7 @@ Tuning tuning_of(const scalp_params_t* p) {
     t.wg = p->wg_size == 0 ? 1024 : p->wg_size;
     t.lds_pixels = p->lds_pixels > 0 ? p->lds_pixels : default_lds_pixels();
     t.blocks_per_cu = p->persistent_blocks;
+    t.voted = p->table_mode;
     return t;
 }
 
@@ -270,6 +272,7 @@ int scalp_default_params(scalp_params_t* out) {
     out->contour_source = SCALP_CONTOUR_INPUT;
     out->exact_pruning = 1;
     out->persistent_blocks = 0;
+    out->table_mode = 0;
     return SCALP_OK;
 }
 

@@ -54,6 +54,7 @@ struct Tuning {
     int wg;           // workgroup size of the assignment kernel (256, 512 or 1024)
     int lds_pixels;   // LDS table budget in 16-byte units
     int blocks_per_cu = 0;   // persistent launch: workgroups per CU (0: as many as fit)
+    int voted = 0;           // 1: voted per-candidate tables (one buffer, two barriers)
 };
 
 int default_lds_pixels();

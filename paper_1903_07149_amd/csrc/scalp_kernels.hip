@@ -58,6 +58,7 @@ constexpr int kBinCopies = 8;
 // Per work item: the candidates and the update bins, [slot * 6 + sum][copy].
 struct CellShared {
     Cand cand[9];
+    int box[9][4];    // voted tables: per slot, min x, min y, max x, max y of the waves that walk it
     unsigned long long bins[9 * 6][kBinCopies];
 };
 
@@ -86,7 +87,7 @@ struct CellShared {
 // rectangle exceeds the budget (cap entries) walks its paths from global
 // memory, computing d_c per sample.  All of these give the same FP32 values
 // in the same order as the plain definition.
-template <int WG, bool ACCUM>
+template <int WG, bool ACCUM, bool VOTED>
 __device__ __forceinline__ void process_cell(const Img& im, int cell, int slice,
                                              const float4* __restrict__ packed,
                                              const float* __restrict__ centres,
@@ -149,6 +150,7 @@ __device__ __forceinline__ void process_cell(const Img& im, int cell, int slice,
         }
         sh.cand[tid] = c;
     }
+    if (VOTED && tid < 36) (&sh.box[0][0])[tid] = (tid & 2) ? INT_MIN : INT_MAX;
     if (ACCUM) {
         for (int t = tid; t < 54 * kBinCopies; t += WG) (&sh.bins[0][0])[t] = 0ULL;
     }
@@ -169,6 +171,91 @@ __device__ __forceinline__ void process_cell(const Img& im, int cell, int slice,
     // the pixel's own texel, for the lower bounds
     const float4 fown = mine ? img[(long long)y * W + x] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     constexpr unsigned long long kOrder = 0x862075314ULL;   // slots 4, 1, 3, 5, 7, 0, 2, 6, 8
+    if constexpr (VOTED) {
+    // Voted tables: before each candidate's table is filled, the waves with
+    // a lane that walks it report the box of their pixels; the table covers
+    // that box and the endpoint, in one buffer of twice the entries (the
+    // vote's barrier already orders the previous candidate's walks before
+    // the fill), and is not filled at all when no lane walks.  Two barriers
+    // per candidate instead of one, in return for smaller fills and more
+    // tables within the budget (cells much larger than the workgroup).
+    const int wx0 = wave_min_i32(mine ? x : INT_MAX), wy0 = wave_min_i32(mine ? y : INT_MAX);
+    const int wx1 = wave_max_i32(mine ? x : INT_MIN), wy1 = wave_max_i32(mine ? y : INT_MIN);
+#pragma unroll 1
+    for (int t = 0; t < 9; ++t) {
+        const int j = (int)((kOrder >> (4 * t)) & 15ULL);
+        const int k = sh.cand[j].k;
+        if (k < 0) continue;                       // uniform
+        const float l = sh.cand[j].l, a = sh.cand[j].a, b = sh.cand[j].b;
+        const int cx = sh.cand[j].cx, cy = sh.cand[j].cy;
+        const float ccx = sh.cand[j].x, ccy = sh.cand[j].y;
+        const float ex = (float)x - ccx;
+        const float ey = (float)y - ccy;
+        const float ds = ex * ex + ey * ey;
+        const float lb = lambda * colour_dist(fown, l, a, b) + ds * spw;   // <= D
+        const bool walks = mine && !(im.prune && (lb > best || (lb == best && j > bestj)));
+        if (__ballot(walks) != 0ULL && (tid & 63) == 0) {
+            atomicMin(&sh.box[j][0], wx0);
+            atomicMin(&sh.box[j][1], wy0);
+            atomicMax(&sh.box[j][2], wx1);
+            atomicMax(&sh.box[j][3], wy1);
+        }
+        __syncthreads();   // the box is complete, and every wave is done with the table
+        const int bx0 = __builtin_amdgcn_readfirstlane(sh.box[j][0]);
+        const int bx1 = __builtin_amdgcn_readfirstlane(sh.box[j][2]);
+        if (bx0 > bx1) continue;                   // uniform: no lane of the item walks j
+        const int by0 = __builtin_amdgcn_readfirstlane(sh.box[j][1]);
+        const int by1 = __builtin_amdgcn_readfirstlane(sh.box[j][3]);
+        const int tx0 = min(bx0, cx), tx1 = max(bx1, cx) + 1;
+        const int ty0 = min(by0, cy), ty1 = max(by1, cy) + 1;
+        const int tw = (tx1 - tx0) + ((24 - (tx1 - tx0) % 16) % 16);
+        const bool staged = (long long)tw * (ty1 - ty0) <= 2LL * cap;   // uniform
+        if (staged) {
+            if (tw <= WG)                          // uniform
+                fill_table_cols<WG>(lds, img, W, tx0, ty0, tw, ty1 - ty0, WG / tw,
+                                    (0x1000000u + (unsigned)tw - 1u) / (unsigned)tw, l, a, b);
+            else
+                fill_table<WG>(lds, img, W, tx0, ty0, tw, tw * (ty1 - ty0), l, a, b);
+            __syncthreads();
+        }
+        if (walks) {
+            const float dcc = sh.cand[j].dcc, wc = sh.cand[j].wc;
+            const int dx = cx - x, dy = cy - y;
+            const int adx = dx < 0 ? -dx : dx, ady = dy < 0 ? -dy : dy;
+            const int n = adx > ady ? adx : ady;
+            const double inv = path_recip(n);
+            float dcp, sc, sw;
+            if (staged) {
+                const int lidx = (y - ty0) * tw + (x - tx0);
+                const float2 e0 = lds[lidx];
+                dcp = e0.x;
+                sc = dcp;                          // sample i = 0 is p itself
+                sw = e0.y;
+                walk_table(lds, lidx, tw, dx, dy, sc, sw);
+            } else {
+                const int p = y * W + x;
+                const float4 fp = img[p];
+                dcp = colour_dist(fp, l, a, b);
+                sc = dcp;
+                sw = fp.w;
+                walk_path(img, p, 1, W, dx, dy, l, a, b, sc, sw);
+            }
+            if (n > 0) {                           // sample i = n is the endpoint
+                sc = sc + dcc;
+                sw = sw + wc;
+            }
+            float qc, qw;                          // sc / |P|, sw / |P|
+            div_path_len(sc, sw, n, inv, qc, qw);
+            const float A = lambda * dcp + oml * qc;             // Eq. (1)
+            const float B = 1.0f + gamma * qw;                   // Eq. (2)
+            const float D = A * B + ds * spw;                    // Eq. (3)
+            if (D < best || (D == best && j < bestj)) {
+                best = D;
+                bestj = j;
+            }
+        }
+    }
+    } else {
 #pragma unroll 1
     for (int t = 0; t < 9; ++t) {
         const int j = (int)((kOrder >> (4 * t)) & 15ULL);
@@ -230,6 +317,7 @@ __device__ __forceinline__ void process_cell(const Img& im, int cell, int slice,
             }
         }
     }
+    }
 
     if (mine) {
         const int p = y * W + x;
@@ -266,7 +354,7 @@ __device__ __forceinline__ void process_cell(const Img& im, int cell, int slice,
     __syncthreads();   // shared state is reused by the next cell of a persistent workgroup
 }
 
-template <int WG, bool ACCUM>
+template <int WG, bool ACCUM, bool VOTED>
 __global__ __launch_bounds__(WG) void k_assign(Img im, const float4* __restrict__ packed,
                                                const float* __restrict__ centres,
                                                const int* __restrict__ endpoints,
@@ -278,12 +366,12 @@ __global__ __launch_bounds__(WG) void k_assign(Img im, const float4* __restrict_
     if (ACCUM && blockIdx.x == 0 && threadIdx.x == 0) ctrl[kCtrlProjCount] = 0;
     const int item = xcd_remap(blockIdx.x, gridDim.x);
     const int cell = item / im.spl;
-    process_cell<WG, ACCUM>(im, cell, item - cell * im.spl, packed, centres, endpoints, labels,
+    process_cell<WG, ACCUM, VOTED>(im, cell, item - cell * im.spl, packed, centres, endpoints, labels,
                             acc, lambda, cap, tab_dyn, sh);
 }
 
 // At most 64 VGPRs (8 waves per SIMD): two 1024-thread workgroups per CU.
-template <int WG>
+template <int WG, bool VOTED>
 __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(8)))
 void k_assign_persistent(const Img* __restrict__ imgs,
                                                           const int* __restrict__ item_start,
@@ -308,7 +396,7 @@ void k_assign_persistent(const Img* __restrict__ imgs,
         const Img im = imgs[i];
         const int local = it - item_start[i];
         const int cell = local / im.spl;
-        process_cell<WG, true>(im, cell, local - cell * im.spl, packed, centres, endpoints, labels,
+        process_cell<WG, true, VOTED>(im, cell, local - cell * im.spl, packed, centres, endpoints, labels,
                                acc, lambda, cap, tab_dyn, sh);
     }
 }
@@ -805,15 +893,24 @@ void lift_lds_limits() {
     allow_lds(k_assign_window<256>, cap);
     allow_lds(k_assign_window<512>, cap);
     allow_lds(k_assign_window<1024>, cap);
-    allow_lds(k_assign<256, true>, cap);
-    allow_lds(k_assign<256, false>, cap);
-    allow_lds(k_assign<512, true>, cap);
-    allow_lds(k_assign<512, false>, cap);
-    allow_lds(k_assign<1024, true>, cap);
-    allow_lds(k_assign<1024, false>, cap);
-    allow_lds(k_assign_persistent<256>, cap);
-    allow_lds(k_assign_persistent<512>, cap);
-    allow_lds(k_assign_persistent<1024>, cap);
+    allow_lds(k_assign<256, true, false>, cap);
+    allow_lds(k_assign<256, false, false>, cap);
+    allow_lds(k_assign<512, true, false>, cap);
+    allow_lds(k_assign<512, false, false>, cap);
+    allow_lds(k_assign<1024, true, false>, cap);
+    allow_lds(k_assign<1024, false, false>, cap);
+    allow_lds(k_assign<256, true, true>, cap);
+    allow_lds(k_assign<256, false, true>, cap);
+    allow_lds(k_assign<512, true, true>, cap);
+    allow_lds(k_assign<512, false, true>, cap);
+    allow_lds(k_assign<1024, true, true>, cap);
+    allow_lds(k_assign<1024, false, true>, cap);
+    allow_lds(k_assign_persistent<256, false>, cap);
+    allow_lds(k_assign_persistent<512, false>, cap);
+    allow_lds(k_assign_persistent<1024, false>, cap);
+    allow_lds(k_assign_persistent<256, true>, cap);
+    allow_lds(k_assign_persistent<512, true>, cap);
+    allow_lds(k_assign_persistent<1024, true>, cap);
 }
 
 int launch_prepare(long long n, const float* lab, const float* contour, float sigma,
@@ -846,58 +943,92 @@ int launch_init_cells_batched(const Img* imgs, const int* cell_start, int n_img,
     return hipGetLastError();
 }
 
-template <int WG, bool ACCUM>
+template <int WG, bool ACCUM, bool VOTED>
 static int launch_assign_t(const Img& im, const float4* packed, const float* centres,
                            const int* endpoints, int* labels, long long* acc, int* ctrl,
                            float lambda, const Tuning& t, hipStream_t s) {
     const size_t bytes = dyn_lds(t);
-    hipLaunchKernelGGL((k_assign<WG, ACCUM>), dim3(im.nx * im.ny * im.spl), dim3(WG), bytes, s, im, packed,
-                       centres, endpoints, labels, acc, ctrl, lambda, t.lds_pixels);
+    hipLaunchKernelGGL((k_assign<WG, ACCUM, VOTED>), dim3(im.nx * im.ny * im.spl), dim3(WG), bytes,
+                       s, im, packed, centres, endpoints, labels, acc, ctrl, lambda,
+                       t.lds_pixels);
     return hipGetLastError();
+}
+
+template <int WG, bool VOTED>
+static int launch_assign_wg(const Img& im, const float4* packed, const float* centres,
+                            const int* endpoints, int* labels, long long* acc, int* ctrl,
+                            float lambda, bool accumulate, const Tuning& t, hipStream_t s) {
+    return accumulate ? launch_assign_t<WG, true, VOTED>(im, packed, centres, endpoints, labels,
+                                                         acc, ctrl, lambda, t, s)
+                      : launch_assign_t<WG, false, VOTED>(im, packed, centres, endpoints, labels,
+                                                          acc, ctrl, lambda, t, s);
+}
+
+template <bool VOTED>
+static int launch_assign_v(const Img& im, const float4* packed, const float* centres,
+                           const int* endpoints, int* labels, long long* acc, int* ctrl,
+                           float lambda, bool accumulate, const Tuning& t, hipStream_t s) {
+    if (t.wg == 1024)
+        return launch_assign_wg<1024, VOTED>(im, packed, centres, endpoints, labels, acc, ctrl,
+                                             lambda, accumulate, t, s);
+    if (t.wg == 512)
+        return launch_assign_wg<512, VOTED>(im, packed, centres, endpoints, labels, acc, ctrl,
+                                            lambda, accumulate, t, s);
+    return launch_assign_wg<256, VOTED>(im, packed, centres, endpoints, labels, acc, ctrl, lambda,
+                                        accumulate, t, s);
 }
 
 int launch_assign(const Img& im, const float4* packed, const float* centres,
                   const int* endpoints, int* labels, long long* acc, int* ctrl, float lambda,
                   bool accumulate, const Tuning& t, hipStream_t s) {
-    if (t.wg == 1024)
-        return accumulate ? launch_assign_t<1024, true>(im, packed, centres, endpoints, labels,
-                                                        acc, ctrl, lambda, t, s)
-                          : launch_assign_t<1024, false>(im, packed, centres, endpoints, labels,
-                                                         acc, ctrl, lambda, t, s);
-    if (t.wg == 512)
-        return accumulate ? launch_assign_t<512, true>(im, packed, centres, endpoints, labels, acc,
-                                                       ctrl, lambda, t, s)
-                          : launch_assign_t<512, false>(im, packed, centres, endpoints, labels,
-                                                        acc, ctrl, lambda, t, s);
-    return accumulate ? launch_assign_t<256, true>(im, packed, centres, endpoints, labels, acc,
-                                                   ctrl, lambda, t, s)
-                      : launch_assign_t<256, false>(im, packed, centres, endpoints, labels, acc,
-                                                    ctrl, lambda, t, s);
+    return t.voted ? launch_assign_v<true>(im, packed, centres, endpoints, labels, acc, ctrl,
+                                           lambda, accumulate, t, s)
+                   : launch_assign_v<false>(im, packed, centres, endpoints, labels, acc, ctrl,
+                                            lambda, accumulate, t, s);
 }
 
-template <int WG>
+template <int WG, bool VOTED>
 static int launch_persistent_t(const Img* imgs, const int* item_start, int n_img, int total,
                                const float4* packed, const float* centres, const int* endpoints,
                                int* labels, long long* acc, int* ctrl, float lambda,
                                const Tuning& t, int grid, hipStream_t s) {
-    hipLaunchKernelGGL(k_assign_persistent<WG>, dim3(grid), dim3(WG), dyn_lds(t), s, imgs,
-                       item_start, n_img, total, packed, centres, endpoints, labels, acc, ctrl,
-                       lambda, t.lds_pixels);
+    hipLaunchKernelGGL((k_assign_persistent<WG, VOTED>), dim3(grid), dim3(WG), dyn_lds(t), s,
+                       imgs, item_start, n_img, total, packed, centres, endpoints, labels, acc,
+                       ctrl, lambda, t.lds_pixels);
     return hipGetLastError();
+}
+
+template <bool VOTED>
+static int launch_persistent_v(const Img* imgs, const int* item_start, int n_img, int total,
+                               const float4* packed, const float* centres, const int* endpoints,
+                               int* labels, long long* acc, int* ctrl, float lambda,
+                               const Tuning& t, int grid, hipStream_t s) {
+    if (t.wg == 1024)
+        return launch_persistent_t<1024, VOTED>(imgs, item_start, n_img, total, packed, centres,
+                                                endpoints, labels, acc, ctrl, lambda, t, grid, s);
+    if (t.wg == 512)
+        return launch_persistent_t<512, VOTED>(imgs, item_start, n_img, total, packed, centres,
+                                               endpoints, labels, acc, ctrl, lambda, t, grid, s);
+    return launch_persistent_t<256, VOTED>(imgs, item_start, n_img, total, packed, centres,
+                                           endpoints, labels, acc, ctrl, lambda, t, grid, s);
 }
 
 int launch_assign_persistent(const Img* imgs, const int* item_start, int n_img, int total_items,
                              const float4* packed, const float* centres, const int* endpoints,
                              int* labels, long long* acc, int* ctrl, float lambda,
                              const Tuning& t, int grid, hipStream_t s) {
-    if (t.wg == 1024)
-        return launch_persistent_t<1024>(imgs, item_start, n_img, total_items, packed, centres,
-                                         endpoints, labels, acc, ctrl, lambda, t, grid, s);
-    if (t.wg == 512)
-        return launch_persistent_t<512>(imgs, item_start, n_img, total_items, packed, centres,
-                                        endpoints, labels, acc, ctrl, lambda, t, grid, s);
-    return launch_persistent_t<256>(imgs, item_start, n_img, total_items, packed, centres,
-                                    endpoints, labels, acc, ctrl, lambda, t, grid, s);
+    return t.voted ? launch_persistent_v<true>(imgs, item_start, n_img, total_items, packed,
+                                               centres, endpoints, labels, acc, ctrl, lambda, t,
+                                               grid, s)
+                   : launch_persistent_v<false>(imgs, item_start, n_img, total_items, packed,
+                                                centres, endpoints, labels, acc, ctrl, lambda, t,
+                                                grid, s);
+}
+
+template <int WG, bool VOTED>
+static int persistent_occupancy(int* per, size_t lds) {
+    return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_assign_persistent<WG, VOTED>,
+                                                             WG, lds);
 }
 
 int persistent_grid(const Tuning& t) {
@@ -905,17 +1036,18 @@ int persistent_grid(const Tuning& t) {
     if (hipGetDevice(&dev) != hipSuccess) return -1;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return -1;
-    hipError_t e;
+    const size_t lds = dyn_lds(t);
+    int e;
     if (t.wg == 1024)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_assign_persistent<1024>, 1024,
-                                                         dyn_lds(t));
+        e = t.voted ? persistent_occupancy<1024, true>(&per, lds)
+                    : persistent_occupancy<1024, false>(&per, lds);
     else if (t.wg == 512)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_assign_persistent<512>, 512,
-                                                         dyn_lds(t));
+        e = t.voted ? persistent_occupancy<512, true>(&per, lds)
+                    : persistent_occupancy<512, false>(&per, lds);
     else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_assign_persistent<256>, 256,
-                                                         dyn_lds(t));
-    if (e != hipSuccess || per < 1) per = 1;
+        e = t.voted ? persistent_occupancy<256, true>(&per, lds)
+                    : persistent_occupancy<256, false>(&per, lds);
+    if (e != (int)hipSuccess || per < 1) per = 1;
     if (t.blocks_per_cu > 0 && t.blocks_per_cu < per) per = t.blocks_per_cu;
     return cus * per;
 }

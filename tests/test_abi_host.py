@@ -46,7 +46,7 @@ def test_default_params():
     p = L.default_params()
     assert (p.m, p.lambda_, p.sigma, p.gamma) == (10.0, 0.5, 0.25, -1.0)
     assert (p.iterations, p.project, p.reuse_prepared) == (10, 1, 0)
-    assert (p.exact_pruning, p.persistent_blocks) == (1, 0)
+    assert (p.exact_pruning, p.persistent_blocks, p.table_mode) == (1, 0, 0)
 
 
 def test_bad_arguments_are_rejected_on_host():
@@ -103,7 +103,8 @@ def test_mode_parameters_are_validated_on_host():
                        None)
     for field, val in [("assign_mode", 2), ("assign_mode", -1), ("contour_source", 2),
                        ("contour_source", -1), ("exact_pruning", 2), ("exact_pruning", -1),
-                       ("persistent_blocks", -1), ("persistent_blocks", 17)]:
+                       ("persistent_blocks", -1), ("persistent_blocks", 17),
+                       ("table_mode", 2), ("table_mode", -1)]:
         pp = L.default_params(**{field: val})
         assert lib.scalp_assign(*args(pp)) == L.SCALP_ERR_ARG, (field, val)
     # a computed contour prior makes the contour pointer optional, a given one does not

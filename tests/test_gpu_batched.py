@@ -18,7 +18,8 @@ def _batch(n, seed0, lo, hi, per_px):
 
 @pytest.mark.parametrize("tune", [dict(), dict(wg_size=256), dict(wg_size=512),
                                   dict(lds_pixels=700), dict(exact_pruning=0),
-                                  dict(persistent_blocks=1), dict(wg_size=256, persistent_blocks=3)])
+                                  dict(persistent_blocks=1), dict(wg_size=256, persistent_blocks=3),
+                                  dict(table_mode=1), dict(table_mode=1, lds_pixels=700, wg_size=512)])
 def test_batched_equals_single_and_oracle(orc, tune):
     from paper_1903_07149_amd.scalp import Scalp, ScalpBatch
     orc.set_threads(min(16, os.cpu_count() or 1))

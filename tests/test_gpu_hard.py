@@ -36,9 +36,12 @@ SMALL = [(97, 61, 30), (256, 200, 100), (481, 321, 250), (37, 5, 7), (1, 1, 1), 
          (50, 1, 5), (64, 64, 4096), (300, 200, 2), (129, 77, 1)]
 # tuning variants: default (1024 threads, 4800-unit LDS tables); tables too small for
 # most endpoints; budget below one cell (every path from global memory);
-# 256- and 512-thread workgroups
+# 256- and 512-thread workgroups; tables voted down to the walking waves' box
+# (alone, with a small budget, and with every candidate walked)
 TUNINGS = [dict(), dict(lds_pixels=900), dict(lds_pixels=1), dict(wg_size=256),
-           dict(wg_size=512, lds_pixels=3200)]
+           dict(wg_size=512, lds_pixels=3200), dict(table_mode=1),
+           dict(table_mode=1, wg_size=256, lds_pixels=900),
+           dict(table_mode=1, exact_pruning=0, wg_size=512)]
 
 
 def _scalp(W, H, k, **kw):
@@ -107,7 +110,12 @@ def test_assign_long_paths(orc, W, H, k, tune):
                                          (600, 600, 4, {}),
                                          (600, 600, 4, {"wg_size": 256, "lds_pixels": 4500}),
                                          (700, 500, 12, {"lds_pixels": 9728}),
-                                         (97, 900, 3, {"wg_size": 512, "lds_pixels": 1000})])
+                                         (97, 900, 3, {"wg_size": 512, "lds_pixels": 1000}),
+                                         (481, 321, 30, {"lds_pixels": 1100, "table_mode": 1}),
+                                         (600, 600, 4, {"table_mode": 1}),
+                                         (700, 500, 12, {"lds_pixels": 9728, "table_mode": 1}),
+                                         (97, 900, 3, {"wg_size": 256, "lds_pixels": 1000,
+                                                       "table_mode": 1})])
 def test_assign_tables_beyond_budget(orc, W, H, k, tune):
     """Cells whose table rectangles exceed the LDS budget by a few to tens of
     times (their paths read global memory) beside candidates whose tables

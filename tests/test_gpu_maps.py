@@ -95,16 +95,18 @@ def test_gradient_prior_rejected_by_soft_and_null_contour_rejected():
     assert ei.value.code == L.SCALP_ERR_ARG
 
 
-def test_multiscale_boundary_map(orc):
+@pytest.mark.parametrize("tune", [dict(), dict(table_mode=1)])
+def test_multiscale_boundary_map(orc, tune):
     """12 decompositions of the 481x321 image (6 to 600 superpixels) in one
     batch: every scale bit-exact against the oracle, and the boundary map
-    bit-exact against the oracle's map of the oracle's labels."""
+    bit-exact against the oracle's map of the oracle's labels (with both
+    table modes of the assignment)."""
     from paper_1903_07149_amd.maps import MultiScale, scales
     img = synth.workload_image(synth.BSD_SHAPE)
     H, W = img.contour.shape
-    ms = MultiScale(W, H)
+    ms = MultiScale(W, H, **tune)
     assert ms.ks == scales() and len(ms.ks) == 12 and ms.ks[0] == 6 and ms.ks[-1] == 600
-    say("multiscale", W, H, ms.ks)
+    say("multiscale", W, H, ms.ks, tune)
     labels, bmap = ms.run(dev(img.lab), dev(img.contour))
     labels, bmap = host(labels), host(bmap)
     ref = []
