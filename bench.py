@@ -302,7 +302,8 @@ def bench_hard(torch, args):
     # kernel's measured launch time, against the published FP32 peak
     roofline = {
         "bound": "alu",
-        "kernel": f"k_assign<{s.params.wg_size},true> (fused assignment + update sums)",
+        "kernel": (f"k_assign<{s.params.wg_size},true,{'true' if s.params.table_mode else 'false'}> "
+                   "(fused assignment + update sums)"),
         "achieved": round(achieved, 3),
         "peak": FP32_PEAK_TFLOPS,
         "unit": "TFLOP/s",

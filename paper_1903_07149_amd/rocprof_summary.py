@@ -6,6 +6,7 @@
          <algorithmic bytes per launch> <source digest> <workload> "<fetch cmd>" "<write cmd>"
   python -m paper_1903_07149_amd.rocprof_summary derived <sq1.csv> <sq2.csv> <fetch.csv>
          <write.csv> <kernel substring>[,<kernel substring>...] [first=N] [grid=G]
+         (separate the substrings with ';' instead when they contain commas)
 
 `stats` lists per-kernel call counts and durations; `counters` lists, per
 kernel, the mean per-dispatch value of every collected counter; `traffic`
@@ -193,7 +194,8 @@ if __name__ == "__main__":
     if kind == "derived":
         a = sys.argv[2:]
         opts = dict(x.split("=", 1) for x in a[5:])
-        sys.stdout.write(derived(a[:4], a[4].split(","), int(opts["first"]) if "first" in opts
+        names = a[4].split(";") if ";" in a[4] else a[4].split(",")
+        sys.stdout.write(derived(a[:4], names, int(opts["first"]) if "first" in opts
                                  else None, int(opts["grid"]) if "grid" in opts else None)[0])
     elif kind == "traffic":
         import json
