@@ -74,8 +74,8 @@ typedef struct {
     int32_t lds_pixels;      /* tuning: LDS budget of the assignment in 16-byte
                                 units (per-candidate tables of 8-byte entries,
                                 two of this many; one table of twice as many
-                                for the window form), 0..9728; 0 selects the
-                                default (4800)                               */
+                                with table_mode 1 and for the window form),
+                                0..9728; 0 selects the default (4800)        */
     int32_t wg_size;         /* tuning: assignment workgroup size, 0 (default
                                 1024), 256, 512 or 1024                      */
     int32_t assign_mode;     /* SCALP_ASSIGN_GRID3X3 (default) or
