@@ -186,14 +186,19 @@ int enq_init(const Img& im, const Views& v, float* centers, int* endpoints, int*
 }
 
 // One window-form pass and its sums (the update cannot be fused: a pixel's
-// label is known only after every window covering it).
+// label is known only after every window covering it).  The sums pass takes
+// the labels from the window minima and resets them, so consecutive passes
+// need no fill in between; fill_first: fill the minima first (the keys of a
+// workspace hold all ones only after a window pass or a fill).
 int enq_window_pass(const Img& im, const scalp_params_t* p, const Views& v, int R,
                     const float* centers, const int* endpoints, int* labels, long long clear_n,
-                    hipStream_t s) {
-    int e = launch_assign_window(im, v.packed, centers, endpoints, labels, v.keys, R, p->lambda,
-                                 tuning_of(p), s);
+                    bool fill_first, hipStream_t s) {
+    int e = fill_first ? launch_fill_keys(im, v.keys, s) : (int)hipSuccess;
+    if (e == hipSuccess)
+        e = launch_assign_window(im, v.packed, centers, endpoints, labels, v.keys, R, p->lambda,
+                                 false, tuning_of(p), s);
     if (e == hipSuccess) e = launch_clear(v.acc, clear_n, s);
-    if (e == hipSuccess) e = launch_accumulate_packed(im, v.packed, labels, v.acc, s);
+    if (e == hipSuccess) e = launch_accumulate_window(im, v.packed, labels, v.keys, v.acc, s);
     return e;
 }
 
@@ -203,7 +208,7 @@ int enq_iterations(const Img& im, const scalp_params_t* p, const Views& v, float
     const Tuning t = tuning_of(p);
     for (int it = 0; it < p->iterations; ++it) {
         int e = p->assign_mode == SCALP_ASSIGN_WINDOW
-                    ? enq_window_pass(im, p, v, R, centers, endpoints, labels, clear_n, s)
+                    ? enq_window_pass(im, p, v, R, centers, endpoints, labels, clear_n, it == 0, s)
                     : launch_assign(im, v.packed, centers, endpoints, labels, v.acc, v.ctrl,
                                     p->lambda, true, t, s);
         if (e == hipSuccess)
@@ -340,7 +345,8 @@ int scalp_assign(const scalp_grid_t* g, const scalp_params_t* p, const float* la
     if (!p->reuse_prepared) CHECK_HIP(enq_prepare(g, p, lab, contour, v, s));
     if (p->assign_mode == SCALP_ASSIGN_WINDOW)
         CHECK_HIP(launch_assign_window(img_of(g, p, 0, 0), v.packed, centers, endpoints, labels,
-                                       v.keys, window_radius(g), p->lambda, tuning_of(p), s));
+                                       v.keys, window_radius(g), p->lambda, true, tuning_of(p),
+                                       s));
     else
         CHECK_HIP(launch_assign(img_of(g, p, 0, 0), v.packed, centers, endpoints, labels, v.acc,
                                 v.ctrl, p->lambda, false, tuning_of(p), s));
@@ -378,7 +384,7 @@ int scalp_assign_accumulate(const scalp_grid_t* g, const scalp_params_t* p, cons
     const Views v = views_of(ws, L);
     if (p->assign_mode == SCALP_ASSIGN_WINDOW)
         CHECK_HIP(enq_window_pass(img_of(g, p, 0, 0), p, v, window_radius(g), centers, endpoints,
-                                  labels, clear_words(L), (hipStream_t)stream));
+                                  labels, clear_words(L), true, (hipStream_t)stream));
     else
         CHECK_HIP(launch_assign(img_of(g, p, 0, 0), v.packed, centers, endpoints, labels, v.acc,
                                 v.ctrl, p->lambda, true, tuning_of(p), (hipStream_t)stream));

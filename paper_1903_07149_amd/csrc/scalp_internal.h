@@ -79,12 +79,18 @@ int launch_assign(const Img& im, const float4* packed, const float* centres,
                   bool accumulate, const Tuning& t, hipStream_t s);
 int launch_accumulate(const Img& im, const float* lab, const int* labels, long long* acc,
                       hipStream_t s);
-// Window form of the assignment (candidate rule of Algorithm 1); labels in/out.
+// Window form of the assignment (candidate rule of Algorithm 1).  keys: one
+// 64-bit minimum per pixel.  labels_out: fill the keys, then write the labels
+// (labels in/out); else the keys must hold all ones on entry and keep the
+// pass's minima for launch_accumulate_window.
 int launch_assign_window(const Img& im, const float4* packed, const float* centres,
                          const int* endpoints, int* labels, unsigned long long* keys, int R,
-                         float lambda, const Tuning& t, hipStream_t s);
-int launch_accumulate_packed(const Img& im, const float4* packed, const int* labels,
-                             long long* acc, hipStream_t s);
+                         float lambda, bool labels_out, const Tuning& t, hipStream_t s);
+int launch_fill_keys(const Img& im, unsigned long long* keys, hipStream_t s);
+// The update sums of a window pass: labels from the keys where a window
+// covered the pixel, keys reset to all ones.
+int launch_accumulate_window(const Img& im, const float4* packed, int* labels,
+                             unsigned long long* keys, long long* acc, hipStream_t s);
 int launch_finalize(const Img& im, float* centres, int* endpoints, int* counts,
                     long long* acc, const int* labels, int* ctrl, int* plist, bool project,
                     hipStream_t s);

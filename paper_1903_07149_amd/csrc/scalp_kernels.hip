@@ -591,9 +591,13 @@ struct LabSource {
 // not depend on the order of the atomics.
 constexpr int kAccSlots = 32;
 
+// wkeys (window form, else null): the pass's window minima; a pixel whose
+// key is set takes its label from it (the others keep theirs), and every key
+// is reset to the all-ones "no window" value for the next pass.
 template <int WG>
 __global__ __launch_bounds__(WG) void k_accumulate(Img im, LabSource src,
-                                                   const int* __restrict__ labels,
+                                                   int* __restrict__ labels,
+                                                   unsigned long long* __restrict__ wkeys,
                                                    long long* __restrict__ acc) {
     __shared__ int keys[kAccSlots];
     // [slot * 6 + sum][copy]: the lanes of a wave mostly carry one label, so
@@ -614,7 +618,19 @@ __global__ __launch_bounds__(WG) void k_accumulate(Img im, LabSource src,
         const int r = t / cw;
         const int x = x0 + (t - r * cw), y = y0 + r;
         const long long p = (long long)y * im.W + x;
-        const int k = labels[p];
+        int k;
+        if (wkeys) {
+            const unsigned long long key = wkeys[p];
+            if (key != ~0ULL) {
+                k = (int)(unsigned)(key & 0xffffffffULL);
+                labels[p] = k;
+            } else {
+                k = labels[p];
+            }
+            wkeys[p] = ~0ULL;
+        } else {
+            k = labels[p];
+        }
         if (k < 0 || k >= K) continue;
         const float3 f = src(p);
         const unsigned long long v[6] = {1ULL, (unsigned long long)x, (unsigned long long)y,
@@ -1061,19 +1077,27 @@ static int launch_window_t(const Img& im, const float4* packed, const float* cen
     return hipGetLastError();
 }
 
-int launch_assign_window(const Img& im, const float4* packed, const float* centres,
-                         const int* endpoints, int* labels, unsigned long long* keys, int R,
-                         float lambda, const Tuning& t, hipStream_t s) {
+int launch_fill_keys(const Img& im, unsigned long long* keys, hipStream_t s) {
     const long long n = (long long)im.W * im.H;
     const unsigned blocks = (unsigned)std::min<long long>((n + 255) / 256, 65536);
     hipLaunchKernelGGL(k_fill_u64, dim3(blocks), dim3(256), 0, s, keys + im.pix, n, ~0ULL);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+int launch_assign_window(const Img& im, const float4* packed, const float* centres,
+                         const int* endpoints, int* labels, unsigned long long* keys, int R,
+                         float lambda, bool labels_out, const Tuning& t, hipStream_t s) {
+    const long long n = (long long)im.W * im.H;
+    const unsigned blocks = (unsigned)std::min<long long>((n + 255) / 256, 65536);
+    if (labels_out) {
+        const int e = launch_fill_keys(im, keys, s);
+        if (e != hipSuccess) return e;
+    }
     int r;
     if (t.wg == 1024) r = launch_window_t<1024>(im, packed, centres, endpoints, keys, R, lambda, t, s);
     else if (t.wg == 512) r = launch_window_t<512>(im, packed, centres, endpoints, keys, R, lambda, t, s);
     else r = launch_window_t<256>(im, packed, centres, endpoints, keys, R, lambda, t, s);
-    if (r != hipSuccess) return r;
+    if (r != hipSuccess || !labels_out) return r;
     hipLaunchKernelGGL(k_window_labels, dim3(blocks), dim3(256), 0, s, keys + im.pix,
                        labels + im.pix, n);
     return hipGetLastError();
@@ -1083,15 +1107,15 @@ int launch_accumulate(const Img& im, const float* lab, const int* labels, long l
                       hipStream_t s) {
     const LabSource src{lab, nullptr};
     hipLaunchKernelGGL(k_accumulate<kSmallWG>, dim3(im.nx * im.ny), dim3(kSmallWG), 0, s, im, src,
-                       labels, acc);
+                       const_cast<int*>(labels), static_cast<unsigned long long*>(nullptr), acc);
     return hipGetLastError();
 }
 
-int launch_accumulate_packed(const Img& im, const float4* packed, const int* labels,
-                             long long* acc, hipStream_t s) {
+int launch_accumulate_window(const Img& im, const float4* packed, int* labels,
+                             unsigned long long* keys, long long* acc, hipStream_t s) {
     const LabSource src{nullptr, packed};
     hipLaunchKernelGGL(k_accumulate<kSmallWG>, dim3(im.nx * im.ny), dim3(kSmallWG), 0, s, im, src,
-                       labels, acc);
+                       labels, keys + im.pix, acc);
     return hipGetLastError();
 }
 
