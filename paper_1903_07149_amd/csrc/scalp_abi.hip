@@ -188,17 +188,20 @@ int enq_init(const Img& im, const Views& v, float* centers, int* endpoints, int*
 // One window-form pass and its sums (the update cannot be fused: a pixel's
 // label is known only after every window covering it).  The sums pass takes
 // the labels from the window minima and resets them, so consecutive passes
-// need no fill in between; fill_first: fill the minima first (the keys of a
-// workspace hold all ones only after a window pass or a fill).
+// need no fill in between; first: fill the minima and clear the sums first
+// (the keys of a workspace hold all ones only after a window pass or a fill;
+// within a run the finalize step leaves every sum at zero, as the grid form
+// relies on).
 int enq_window_pass(const Img& im, const scalp_params_t* p, const Views& v, int R,
                     const float* centers, const int* endpoints, int* labels, long long clear_n,
-                    bool fill_first, hipStream_t s) {
-    int e = fill_first ? launch_fill_keys(im, v.keys, s) : (int)hipSuccess;
+                    bool first, hipStream_t s) {
+    int e = first ? launch_fill_keys(im, v.keys, s) : (int)hipSuccess;
+    if (e == hipSuccess && first) e = launch_clear(v.acc, clear_n, s);
     if (e == hipSuccess)
         e = launch_assign_window(im, v.packed, centers, endpoints, labels, v.keys, R, p->lambda,
                                  false, tuning_of(p), s);
-    if (e == hipSuccess) e = launch_clear(v.acc, clear_n, s);
-    if (e == hipSuccess) e = launch_accumulate_window(im, v.packed, labels, v.keys, v.acc, s);
+    if (e == hipSuccess)
+        e = launch_accumulate_window(im, v.packed, labels, v.keys, v.ctrl, v.acc, s);
     return e;
 }
 

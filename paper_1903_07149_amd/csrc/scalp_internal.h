@@ -88,9 +88,9 @@ int launch_assign_window(const Img& im, const float4* packed, const float* centr
                          float lambda, bool labels_out, const Tuning& t, hipStream_t s);
 int launch_fill_keys(const Img& im, unsigned long long* keys, hipStream_t s);
 // The update sums of a window pass: labels from the keys where a window
-// covered the pixel, keys reset to all ones.
+// covered the pixel, keys reset to all ones, the projection queue emptied.
 int launch_accumulate_window(const Img& im, const float4* packed, int* labels,
-                             unsigned long long* keys, long long* acc, hipStream_t s);
+                             unsigned long long* keys, int* ctrl, long long* acc, hipStream_t s);
 int launch_finalize(const Img& im, float* centres, int* endpoints, int* counts,
                     long long* acc, const int* labels, int* ctrl, int* plist, bool project,
                     hipStream_t s);

@@ -593,11 +593,14 @@ constexpr int kAccSlots = 32;
 
 // wkeys (window form, else null): the pass's window minima; a pixel whose
 // key is set takes its label from it (the others keep theirs), and every key
-// is reset to the all-ones "no window" value for the next pass.
+// is reset to the all-ones "no window" value for the next pass; the pass
+// also empties the projection queue that the finalize step after it fills
+// (ctrl, as the fused grid-form pass does).
 template <int WG>
 __global__ __launch_bounds__(WG) void k_accumulate(Img im, LabSource src,
                                                    int* __restrict__ labels,
                                                    unsigned long long* __restrict__ wkeys,
+                                                   int* __restrict__ ctrl,
                                                    long long* __restrict__ acc) {
     __shared__ int keys[kAccSlots];
     // [slot * 6 + sum][copy]: the lanes of a wave mostly carry one label, so
@@ -605,6 +608,7 @@ __global__ __launch_bounds__(WG) void k_accumulate(Img im, LabSource src,
     __shared__ unsigned long long bins[kAccSlots * 6][kBinCopies];
     const int tid = threadIdx.x;
     const int cell = blockIdx.x;
+    if (ctrl && cell == 0 && tid == 0) ctrl[kCtrlProjCount] = 0;
     const int ci = cell / im.nx, cj = cell - ci * im.nx;
     const int x0 = cell_lo(cj, im.W, im.nx), x1 = cell_lo(cj + 1, im.W, im.nx);
     const int y0 = cell_lo(ci, im.H, im.ny), y1 = cell_lo(ci + 1, im.H, im.ny);
@@ -1107,15 +1111,16 @@ int launch_accumulate(const Img& im, const float* lab, const int* labels, long l
                       hipStream_t s) {
     const LabSource src{lab, nullptr};
     hipLaunchKernelGGL(k_accumulate<kSmallWG>, dim3(im.nx * im.ny), dim3(kSmallWG), 0, s, im, src,
-                       const_cast<int*>(labels), static_cast<unsigned long long*>(nullptr), acc);
+                       const_cast<int*>(labels), static_cast<unsigned long long*>(nullptr),
+                       static_cast<int*>(nullptr), acc);
     return hipGetLastError();
 }
 
 int launch_accumulate_window(const Img& im, const float4* packed, int* labels,
-                             unsigned long long* keys, long long* acc, hipStream_t s) {
+                             unsigned long long* keys, int* ctrl, long long* acc, hipStream_t s) {
     const LabSource src{nullptr, packed};
     hipLaunchKernelGGL(k_accumulate<kSmallWG>, dim3(im.nx * im.ny), dim3(kSmallWG), 0, s, im, src,
-                       labels, keys + im.pix, acc);
+                       labels, keys + im.pix, ctrl, acc);
     return hipGetLastError();
 }
 
