@@ -718,8 +718,25 @@ def bench_soft(torch, args):
     roof = alu_roofline(flops, fwd * 1e-3 / iters,
                         "forward / iterations (soft assignment, softmax and soft update); "
                         "work at Theta_0")
+    # the backward's: per iteration, the pairs with Q >= 2^-24 re-walk their
+    # paths to that iteration's endpoints (the last timed forward's Q and Theta)
+    bflops = 0
+    bsamples = 0
+    for t in range(iters):
+        walked = (q_t[t] >= 2.0 ** -24).cpu().numpy()
+        tht = c_t[t].cpu().numpy()
+        et = np.clip(np.floor(tht[..., 3:5] + np.float32(0.5)), 0, [W - 1, H - 1]).astype(np.int64)
+        for bb in range(B):
+            w = counts.soft_backward_work(W, H, g.nx, g.ny, et[bb], walked[bb])
+            bflops += w["flops"]
+            bsamples += w["samples"]
+    roof_b = alu_roofline(bflops / iters, bwd * 1e-3 / iters,
+                          "backward / iterations (softmax and soft-update backward, and the "
+                          "path re-walk of every pair with Q >= 2^-24); work at every iteration's Q")
+    roof_b["walked_samples_per_iteration"] = int(bsamples // iters)
     return {"workload": f"{B} x {W}x{H} Voronoi images, k={k}, T={T}, {iters} iterations",
             "roofline_forward": roof,
+            "roofline_backward": roof_b,
             "wg_size": soft_wg,
             "fwd_bwd_mpx_iter_s": round(px_it / ((fwd + bwd) * 1e-3) / 1e6, 1),
             "fwd_ms": round(fwd, 3), "bwd_ms": round(bwd, 3),

@@ -62,3 +62,41 @@ def window_work(width: int, height: int, radius: int, centres: np.ndarray,
     return {"samples": samples, "candidates": cands,
             "flops": FLOPS_PER_SAMPLE * samples + FLOPS_PER_CANDIDATE * cands,
             "lds_bytes": BYTES_PER_SAMPLE * samples}
+
+
+# The soft backward, per iteration: every (pixel, slot) pair whose softmax
+# weight is at least 2^-24 re-walks its path, and every sample q of it takes
+# dL/df_q += cf (f_q - f_k) (3 sub, 3 mul, 3 add), dL/dw_q += cw (1 add) and
+# the candidate's centre gradient -cf (f_q - f_k) (3 add); per pair the two
+# weights cf, cw and the spatial part of the centre gradient; per pixel the
+# softmax and soft-update backward over its 9 slots (dL/dQ from the two
+# candidate terms, its dot with Q, dL/dD, dL/df through the update).
+SOFT_BWD_FLOPS_PER_SAMPLE = 13
+SOFT_BWD_FLOPS_PER_PAIR = 14
+SOFT_BWD_FLOPS_PER_PIXEL = 9 * 19
+
+
+def soft_backward_work(width: int, height: int, nx: int, ny: int, endpoints: np.ndarray,
+                       walked: np.ndarray) -> dict:
+    """samples, pairs, flops of one soft backward iteration of one image.
+    endpoints: [K'][2] (x, y) of the iteration's candidate endpoints;
+    walked: bool [9][H][W] (slot-major, slot j = 3 (di + 1) + (dj + 1) of the
+    pixel's cell offset), True where the pair's path is re-walked."""
+    W, H = int(width), int(height)
+    yy, xx = np.mgrid[0:H, 0:W]
+    ci = (yy.astype(np.int64) * ny) // H
+    cj = (xx.astype(np.int64) * nx) // W
+    ep = np.asarray(endpoints, np.int64).reshape(-1, 2)
+    wk = np.asarray(walked, bool).reshape(9, H, W)
+    samples = 0
+    pairs = 0
+    for j in range(9):
+        ii, jj = ci + j // 3 - 1, cj + j % 3 - 1
+        ok = (ii >= 0) & (ii < ny) & (jj >= 0) & (jj < nx) & wk[j]
+        k = np.where(ok, ii * nx + jj, 0)
+        n = np.maximum(np.abs(ep[k, 0] - xx), np.abs(ep[k, 1] - yy))
+        samples += int(((n + 1) * ok).sum())
+        pairs += int(ok.sum())
+    return {"samples": samples, "pairs": pairs,
+            "flops": SOFT_BWD_FLOPS_PER_SAMPLE * samples + SOFT_BWD_FLOPS_PER_PAIR * pairs +
+                     SOFT_BWD_FLOPS_PER_PIXEL * W * H}

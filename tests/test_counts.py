@@ -43,3 +43,27 @@ def test_window_sample_count_brute_force(orc):
                         samples += max(abs(int(e[q, 0]) - x), abs(int(e[q, 1]) - y)) + 1
                         cands += 1
         assert (w["samples"], w["candidates"]) == (samples, cands)
+
+
+def test_soft_backward_count_brute_force(orc):
+    """The soft backward's re-walked samples, summed slot-plane by slot-plane,
+    equal a per-pixel loop over the walked pairs with the oracle's own path
+    length (its path from the pixel to the slot's endpoint)."""
+    rng = np.random.default_rng(12)
+    for (W, H, k) in [(23, 17, 6), (40, 9, 8)]:
+        g = orc.grid(W, H, k)
+        ep = np.stack([rng.integers(0, W, g.num_sp), rng.integers(0, H, g.num_sp)], 1)
+        walked = rng.random((9, H, W)) < 0.4
+        w = counts.soft_backward_work(W, H, g.nx, g.ny, ep, walked)
+        samples = pairs = 0
+        for y in range(H):
+            for x in range(W):
+                ci, cj = (y * g.ny) // H, (x * g.nx) // W
+                for j in range(9):
+                    ii, jj = ci + j // 3 - 1, cj + j % 3 - 1
+                    if 0 <= ii < g.ny and 0 <= jj < g.nx and walked[j, y, x]:
+                        kk = ii * g.nx + jj
+                        samples += len(orc.path(x, y, int(ep[kk, 0]), int(ep[kk, 1])))
+                        pairs += 1
+        assert (w["samples"], w["pairs"]) == (samples, pairs)
+        assert w["flops"] == 13 * samples + 14 * pairs + 171 * W * H
