@@ -718,12 +718,16 @@ def bench_soft(torch, args):
     roof = alu_roofline(flops, fwd * 1e-3 / iters,
                         "forward / iterations (soft assignment, softmax and soft update); "
                         "work at Theta_0")
-    # the backward's: per iteration, the pairs with Q >= 2^-24 re-walk their
-    # paths to that iteration's endpoints (the last timed forward's Q and Theta)
+    # the backward's: per iteration, a pair re-walks its path to that
+    # iteration's endpoint when its dL/dD is not zero: Q >= 2^-24 at a pixel
+    # whose Q is not one-hot in FP32 (where the largest Q is exactly 1, the
+    # softmax backward G_j - sum_i Q_i G_i rounds to 0); the last timed
+    # forward's Q and Theta
     bflops = 0
     bsamples = 0
     for t in range(iters):
-        walked = (q_t[t] >= 2.0 ** -24).cpu().numpy()
+        qt = q_t[t]
+        walked = ((qt >= 2.0 ** -24) & (qt.amax(dim=1, keepdim=True) < 1.0)).cpu().numpy()
         tht = c_t[t].cpu().numpy()
         et = np.clip(np.floor(tht[..., 3:5] + np.float32(0.5)), 0, [W - 1, H - 1]).astype(np.int64)
         for bb in range(B):
@@ -732,7 +736,8 @@ def bench_soft(torch, args):
             bsamples += w["samples"]
     roof_b = alu_roofline(bflops / iters, bwd * 1e-3 / iters,
                           "backward / iterations (softmax and soft-update backward, and the "
-                          "path re-walk of every pair with Q >= 2^-24); work at every iteration's Q")
+                          "path re-walk of every pair whose dL/dD is not zero); work at every "
+                          "iteration's Q")
     roof_b["walked_samples_per_iteration"] = int(bsamples // iters)
     return {"workload": f"{B} x {W}x{H} Voronoi images, k={k}, T={T}, {iters} iterations",
             "roofline_forward": roof,
