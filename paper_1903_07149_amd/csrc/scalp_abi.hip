@@ -1,6 +1,7 @@
 // scalp_abi.hip -- the extern "C" entry points of libscalp.so: argument
 // validation, workspace layout, kernel sequencing and hipGraph capture.
 // Declarations and their contracts are in include/scalp.h.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <functional>
@@ -95,6 +96,11 @@ Img img_of(const scalp_grid_t* g, const scalp_params_t* p, long long pix, int sp
     im.spl = slices_of(g, tuning_of(p).wg);
     im.rad = (int)std::floor(r + 0.5);
     im.prune = p->exact_pruning;
+    // Each XCD (own L2) takes a contiguous run of the cell order; strips of
+    // width about sqrt(nx ny / 8) make those runs near-square blocks of
+    // cells, so fewer table texels sit in cells that another XCD reads too.
+    im.strips = std::max(1, std::min({8, g->nx,
+        (int)std::lround(std::sqrt(8.0 * g->nx / std::max(1, g->ny)))}));
     return im;
 }
 

@@ -355,6 +355,19 @@ __device__ __forceinline__ int xcd_remap(int b, int G) {
     return x < rem ? x * (q + 1) + slot : rem * (q + 1) + (x - rem) * q + slot;
 }
 
+// Cell at position i of the cell order of the grid assignment: column
+// strips ceil(nx / strips) cells wide (the last one narrower), row-major
+// within a strip.  A bijection of [0, nx ny); strips = 1 is row-major order.
+__device__ __forceinline__ int cell_in_strips(int i, int nx, int ny, int strips) {
+    const int tw = (nx + strips - 1) / strips;
+    const int s = i / (tw * ny);
+    const int x0 = s * tw;
+    const int w = min(tw, nx - x0);
+    const int l = i - s * tw * ny;
+    const int r = l / w;
+    return r * nx + x0 + (l - r * w);
+}
+
 __device__ __forceinline__ int find_image(const int* start, int n, int v) {
     int lo = 0, hi = n - 1;
     while (lo < hi) {

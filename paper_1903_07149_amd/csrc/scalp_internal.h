@@ -43,6 +43,7 @@ struct Img {
     int spl;          // assignment work items per grid cell (at most WG pixels each)
     int rad;          // R = r rounded to whole pixels (the window form's half-width)
     int prune;        // 1: skip the walks that the exact lower bound of D rules out
+    int strips;       // column strips of the grid assignment's cell order (see cell_in_strips)
 };
 
 // An assignment work item has at most as many pixels as its workgroup has

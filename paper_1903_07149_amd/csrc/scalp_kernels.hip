@@ -365,9 +365,10 @@ __global__ __launch_bounds__(WG) void k_assign(Img im, const float4* __restrict_
     __shared__ CellShared sh;
     if (ACCUM && blockIdx.x == 0 && threadIdx.x == 0) ctrl[kCtrlProjCount] = 0;
     const int item = xcd_remap(blockIdx.x, gridDim.x);
-    const int cell = item / im.spl;
-    process_cell<WG, ACCUM, VOTED>(im, cell, item - cell * im.spl, packed, centres, endpoints, labels,
-                            acc, lambda, cap, tab_dyn, sh);
+    const int pos = item / im.spl;
+    process_cell<WG, ACCUM, VOTED>(im, cell_in_strips(pos, im.nx, im.ny, im.strips),
+                                   item - pos * im.spl, packed, centres, endpoints, labels, acc,
+                                   lambda, cap, tab_dyn, sh);
 }
 
 // At most 64 VGPRs (8 waves per SIMD): two 1024-thread workgroups per CU.
