@@ -510,7 +510,7 @@ bool batch_layout(const scalp_batch_desc_t* d, int n, BatchLayout* out) {
     out->imgs = out->base.total;
     out->starts = align_up(out->imgs + sizeof(Img) * (size_t)n);
     out->items = align_up(out->starts + sizeof(int) * (size_t)(n + 1));
-    out->total = align_up(out->items + sizeof(int) * (size_t)(n + 1));
+    out->total = align_up(out->items + sizeof(int) * 9 * (size_t)(n + 1));   // starts + 8 XCD runs
     out->N = N;
     out->K = K;
     return true;
@@ -525,7 +525,7 @@ int enq_batched(const scalp_batch_desc_t* d, int n, const scalp_params_t* p, con
     int* starts = reinterpret_cast<int*>(b + BL.starts);
     int* items = reinterpret_cast<int*>(b + BL.items);
     std::vector<Img> himg((size_t)n);
-    std::vector<int> hstart((size_t)n + 1), hitem((size_t)n + 1);
+    std::vector<int> hstart((size_t)n + 1), hitem(9 * ((size_t)n + 1));
     long long total_items = 0;
     for (int i = 0; i < n; ++i) {
         himg[(size_t)i] = img_of(&d[i].grid, p, d[i].pix_offset, d[i].sp_offset);
@@ -535,9 +535,18 @@ int enq_batched(const scalp_batch_desc_t* d, int n, const scalp_params_t* p, con
     }
     hstart[(size_t)n] = (int)BL.K;
     hitem[(size_t)n] = (int)total_items;
+    // the persistent assignment's run of XCD x: the x-th eighth of each image's items
+    for (int x = 0; x < 8; ++x) {
+        int* run = hitem.data() + ((size_t)n + 1) * (size_t)(1 + x);
+        run[0] = 0;
+        for (int i = 0; i < n; ++i) {
+            const long long ni = (long long)hitem[(size_t)i + 1] - hitem[(size_t)i];
+            run[i + 1] = run[i] + (int)((ni * (x + 1) >> 3) - (ni * x >> 3));
+        }
+    }
     int e = launch_write_bytes(imgs, himg.data(), sizeof(Img) * (size_t)n, s);
     if (e == hipSuccess) e = launch_write_bytes(starts, hstart.data(), sizeof(int) * (size_t)(n + 1), s);
-    if (e == hipSuccess) e = launch_write_bytes(items, hitem.data(), sizeof(int) * (size_t)(n + 1), s);
+    if (e == hipSuccess) e = launch_write_bytes(items, hitem.data(), sizeof(int) * hitem.size(), s);
     if (e == hipSuccess && !p->reuse_prepared) {
         if (p->contour_source == SCALP_CONTOUR_GRADIENT) {
             // the prior is normalised per image: one max + pack per image

@@ -20,10 +20,11 @@ constexpr int kAccStride = 8;
 // Control words in the workspace.
 enum Ctrl : int {
     kCtrlProjCount = 0,   // entries in the projection list
-    kCtrlQueue = 1,       // persistent work-queue head
     kCtrlGradMax = 64,    // words 64-1087: kGradSlots partial maxima of the squared
                           // gradient magnitude (FP64 bits), one per 128-byte line
-    kCtrlWords = 1088
+    kCtrlQueue = 1088,    // words 1088-1343: the persistent assignment's 8 queue heads
+                          // (one per XCD's run of items), one per 128-byte line
+    kCtrlWords = 1344
 };
 
 // The gradient maximum is kept in kGradSlots 64-bit slots kGradStride words

@@ -387,18 +387,32 @@ void k_assign_persistent(const Img* __restrict__ imgs,
     __shared__ CellShared sh;
     __shared__ int item;
     if (blockIdx.x == 0 && threadIdx.x == 0) ctrl[kCtrlProjCount] = 0;
-    for (;;) {
-        if (threadIdx.x == 0) item = atomicAdd(&ctrl[kCtrlQueue], 1);
+    // XCD x (workgroup b runs on XCD b mod 8) has its own run of items and
+    // queue head: the x-th eighth of every image's items, in the cell order
+    // of cell_in_strips, so its cells form a block and share its L2, and
+    // every XCD starts on every image (images of few, large cells walk long
+    // paths).  run x = item_start + (n_img + 1) (1 + x) holds where each
+    // image's share starts in the run.  A workgroup takes the items of its
+    // XCD's run, then those left in the other runs, in turn.
+    for (int q = 0; q < 8;) {
+        const int x = (int)((blockIdx.x + q) & 7u);
+        const int* __restrict__ run = item_start + (n_img + 1) * (1 + x);
+        if (threadIdx.x == 0) item = atomicAdd(&ctrl[kCtrlQueue + 32 * x], 1);
         __syncthreads();
-        const int it = __builtin_amdgcn_readfirstlane(item);   // uniform: keep the item in SGPRs
+        const int h = __builtin_amdgcn_readfirstlane(item);   // uniform: kept in SGPRs
         __syncthreads();
-        if (it >= total) break;
-        const int i = find_image(item_start, n_img, it);
+        if (h >= run[n_img]) {
+            ++q;
+            continue;
+        }
+        const int i = find_image(run, n_img, h);
         const Img im = imgs[i];
-        const int local = it - item_start[i];
-        const int cell = local / im.spl;
-        process_cell<WG, true, VOTED>(im, cell, local - cell * im.spl, packed, centres, endpoints, labels,
-                               acc, lambda, cap, tab_dyn, sh);
+        const int ni = item_start[i + 1] - item_start[i];
+        const int local = (int)((long long)ni * x >> 3) + (h - run[i]);
+        const int pos = local / im.spl;
+        process_cell<WG, true, VOTED>(im, cell_in_strips(pos, im.nx, im.ny, im.strips),
+                                      local - pos * im.spl, packed, centres, endpoints, labels,
+                                      acc, lambda, cap, tab_dyn, sh);
     }
 }
 
@@ -718,7 +732,7 @@ __global__ void k_finalize_batched(const Img* __restrict__ imgs, const int* __re
                                    int* counts, long long* acc, const int* labels, int* ctrl,
                                    int* plist, int project) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g == 0) ctrl[kCtrlQueue] = 0;   // the next persistent assignment starts at item 0
+    if (g < 8) ctrl[kCtrlQueue + 32 * g] = 0;   // the next persistent assignment starts afresh
     if (g >= total) return;
     const int i = find_image(sp_start, n_img, g);
     const Img im = imgs[i];
