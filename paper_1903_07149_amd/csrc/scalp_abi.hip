@@ -221,10 +221,9 @@ int enq_iterations(const Img& im, const scalp_params_t* p, const Views& v, float
                     : launch_assign(im, v.packed, centers, endpoints, labels, v.acc, v.ctrl,
                                     p->lambda, true, t, s);
         if (e == hipSuccess)
-            e = launch_finalize(im, centers, endpoints, counts, v.acc, labels, v.ctrl, v.plist,
-                                p->project != 0, s);
-        if (e == hipSuccess && p->project)
-            e = launch_project(im, centers, counts, labels, endpoints, v.ctrl, v.plist, s);
+            e = p->project ? launch_finalize_project(im, centers, endpoints, counts, v.acc, labels, s)
+                           : launch_finalize(im, centers, endpoints, counts, v.acc, labels, v.ctrl,
+                                             v.plist, false, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -568,11 +567,12 @@ int enq_batched(const scalp_batch_desc_t* d, int n, const scalp_params_t* p, con
         e = launch_assign_persistent(imgs, items, n, (int)total_items, v.packed, centers, endpoints,
                                      labels, v.acc, v.ctrl, p->lambda, t, grid, s);
         if (e == hipSuccess)
-            e = launch_finalize_batched(imgs, starts, n, (int)BL.K, centers, endpoints, counts,
-                                        v.acc, labels, v.ctrl, v.plist, p->project != 0, s);
-        if (e == hipSuccess && p->project)
-            e = launch_project_batched(imgs, starts, n, centers, counts, labels, endpoints, v.ctrl,
-                                       v.plist, s);
+            e = p->project ? launch_finalize_project_batched(imgs, starts, n, (int)BL.K, centers,
+                                                             endpoints, counts, v.acc, labels,
+                                                             v.ctrl, s)
+                           : launch_finalize_batched(imgs, starts, n, (int)BL.K, centers,
+                                                     endpoints, counts, v.acc, labels, v.ctrl,
+                                                     v.plist, false, s);
     }
     return e;
 }

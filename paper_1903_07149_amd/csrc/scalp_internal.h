@@ -96,6 +96,12 @@ int launch_accumulate_window(const Img& im, const float4* packed, int* labels,
 int launch_finalize(const Img& im, float* centres, int* endpoints, int* counts,
                     long long* acc, const int* labels, int* ctrl, int* plist, bool project,
                     hipStream_t s);
+// finalize + projection in one launch (one workgroup per superpixel)
+int launch_finalize_project_batched(const Img* imgs, const int* sp_start, int n_img,
+                                    int total_sp, float* centres, int* endpoints, int* counts,
+                                    long long* acc, const int* labels, int* ctrl, hipStream_t s);
+int launch_finalize_project(const Img& im, float* centres, int* endpoints, int* counts,
+                            long long* acc, const int* labels, hipStream_t s);
 int launch_project(const Img& im, const float* centres, const int* counts, const int* labels,
                    int* endpoints, const int* ctrl, const int* plist, hipStream_t s);
 
@@ -110,9 +116,6 @@ int launch_finalize_batched(const Img* imgs, const int* sp_start, int n_img, int
                             float* centres, int* endpoints, int* counts, long long* acc,
                             const int* labels, int* ctrl, int* plist, bool project,
                             hipStream_t s);
-int launch_project_batched(const Img* imgs, const int* sp_start, int n_img, const float* centres,
-                           const int* counts, const int* labels, int* endpoints,
-                           const int* ctrl, const int* plist, hipStream_t s);
 int persistent_grid(const Tuning& t);
 
 // ---- soft SCALP (scalp_soft.hip)

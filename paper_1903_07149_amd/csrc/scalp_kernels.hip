@@ -689,22 +689,27 @@ __global__ __launch_bounds__(WG) void k_accumulate(Img im, LabSource src,
 
 // ---------------------------------------------------------------- finalize
 
-__device__ __forceinline__ void finalize_one(const Img& im, int k, float* __restrict__ centres,
-                                             int* __restrict__ endpoints,
-                                             int* __restrict__ counts,
-                                             long long* __restrict__ acc,
-                                             const int* __restrict__ labels, int* ctrl,
-                                             int* plist, bool project) {
+// Superpixel k's centre, barycenter and count from its sums (which it
+// clears); the endpoint is the rounded barycenter when that pixel is one of
+// k's own or projection is off.  Returns true when the projection has to
+// move the endpoint instead (then xk, yk, cnt are what it needs).
+__device__ __forceinline__ bool finalize_core(const Img& im, int k, float* __restrict__ centres,
+                                              int* __restrict__ endpoints,
+                                              int* __restrict__ counts,
+                                              long long* __restrict__ acc,
+                                              const int* __restrict__ labels, bool project,
+                                              float& xk, float& yk, int& cnt_out) {
     long long* a = acc + kAccStride * (long long)(im.sp + k);
     const long long cnt = a[0];
+    bool move = false;
     if (cnt > 0) {
         const double n = (double)cnt;
         float* c = centres + 5LL * (im.sp + k);
         c[0] = (float)(((double)a[3] / n) * kFixInv);
         c[1] = (float)(((double)a[4] / n) * kFixInv);
         c[2] = (float)(((double)a[5] / n) * kFixInv);
-        const float xk = (float)((double)a[1] / n);
-        const float yk = (float)((double)a[2] / n);
+        xk = (float)((double)a[1] / n);
+        yk = (float)((double)a[2] / n);
         c[3] = xk;
         c[4] = yk;
         const int ex = round_coord(xk, im.W - 1), ey = round_coord(yk, im.H - 1);
@@ -712,12 +717,27 @@ __device__ __forceinline__ void finalize_one(const Img& im, int k, float* __rest
             endpoints[2LL * (im.sp + k)] = ex;
             endpoints[2LL * (im.sp + k) + 1] = ey;
         } else {
-            const int slot = atomicAdd(&ctrl[kCtrlProjCount], 1);
-            plist[slot] = im.sp + k;
+            move = true;
         }
     }
     counts[im.sp + k] = (int)cnt;
+    cnt_out = (int)cnt;
     for (int v = 0; v < 6; ++v) a[v] = 0;
+    return move;
+}
+
+__device__ __forceinline__ void finalize_one(const Img& im, int k, float* __restrict__ centres,
+                                             int* __restrict__ endpoints,
+                                             int* __restrict__ counts,
+                                             long long* __restrict__ acc,
+                                             const int* __restrict__ labels, int* ctrl,
+                                             int* plist, bool project) {
+    float xk, yk;
+    int cnt;
+    if (finalize_core(im, k, centres, endpoints, counts, acc, labels, project, xk, yk, cnt)) {
+        const int slot = atomicAdd(&ctrl[kCtrlProjCount], 1);
+        plist[slot] = im.sp + k;
+    }
 }
 
 __global__ void k_finalize(Img im, float* centres, int* endpoints, int* counts, long long* acc,
@@ -823,15 +843,11 @@ __device__ void scan_region(const int* __restrict__ lb, int W, int k, int X0, in
 // (the window form: members lie within R of the previous barycenter, which
 // lies within R of the new one), then the whole image (any labels).
 template <int WG>
-__device__ void project_one(const Img& im, int k, const float* __restrict__ centres,
-                            const int* __restrict__ counts, const int* __restrict__ labels,
-                            int* __restrict__ endpoints) {
+__device__ void project_at(const Img& im, int k, float xk, float yk, int count,
+                           const int* __restrict__ labels, int* __restrict__ endpoints) {
     const int W = im.W, H = im.H;
     const int* lb = labels + im.pix;
-    const float xk = centres[5LL * (im.sp + k) + 3];
-    const float yk = centres[5LL * (im.sp + k) + 4];
     const int ci = k / im.nx, cj = k - ci * im.nx;
-    const int count = counts[im.sp + k];
     unsigned long long best;
     int found;
     scan_region<WG>(lb, W, k, cell_lo(max(cj - 1, 0), W, im.nx), cell_lo(min(cj + 2, im.nx), W, im.nx),
@@ -852,28 +868,76 @@ __device__ void project_one(const Img& im, int k, const float* __restrict__ cent
 }
 
 template <int WG>
+__device__ void project_one(const Img& im, int k, const float* __restrict__ centres,
+                            const int* __restrict__ counts, const int* __restrict__ labels,
+                            int* __restrict__ endpoints) {
+    project_at<WG>(im, k, centres[5LL * (im.sp + k) + 3], centres[5LL * (im.sp + k) + 4],
+                   counts[im.sp + k], labels, endpoints);
+}
+
+// Finalize and projection in one pass, a workgroup per superpixel: thread 0
+// takes the superpixel's sums, and when its rounded barycenter is not one of
+// its pixels the workgroup moves the endpoint to the nearest member at once
+// (no queue, no second launch; projecting k reads only k's own centre and
+// count and the labels).
+template <int WG>
+__global__ __launch_bounds__(WG) void k_finalize_project(Img im, float* centres, int* endpoints,
+                                                         int* counts, long long* acc,
+                                                         const int* labels) {
+    __shared__ float sx, sy;
+    __shared__ int scnt, smove;
+    const int k = blockIdx.x;
+    if (threadIdx.x == 0) {
+        float xk = 0.0f, yk = 0.0f;
+        int cnt = 0;
+        smove = finalize_core(im, k, centres, endpoints, counts, acc, labels, true, xk, yk, cnt)
+                    ? 1 : 0;
+        sx = xk;
+        sy = yk;
+        scnt = cnt;
+    }
+    __syncthreads();
+    if (smove) project_at<WG>(im, k, sx, sy, scnt, labels, endpoints);   // uniform
+}
+
+// The same over a ragged batch, a workgroup per superpixel of the batch;
+// like k_finalize_batched it resets the persistent assignment's queue heads.
+template <int WG>
+__global__ __launch_bounds__(WG) void k_finalize_project_batched(const Img* __restrict__ imgs,
+                                                                 const int* __restrict__ sp_start,
+                                                                 int n_img, float* centres,
+                                                                 int* endpoints, int* counts,
+                                                                 long long* acc, const int* labels,
+                                                                 int* ctrl) {
+    __shared__ float sx, sy;
+    __shared__ int scnt, smove, simg;
+    const int g = blockIdx.x;
+    if (threadIdx.x == 0) {
+        if (g < 8) ctrl[kCtrlQueue + 32 * g] = 0;   // the next persistent assignment starts afresh
+        const int i = find_image(sp_start, n_img, g);
+        float xk = 0.0f, yk = 0.0f;
+        int cnt = 0;
+        smove = finalize_core(imgs[i], g - imgs[i].sp, centres, endpoints, counts, acc, labels,
+                              true, xk, yk, cnt) ? 1 : 0;
+        sx = xk;
+        sy = yk;
+        scnt = cnt;
+        simg = i;
+    }
+    __syncthreads();
+    if (smove) {                                   // uniform
+        const Img im = imgs[simg];
+        project_at<WG>(im, g - im.sp, sx, sy, scnt, labels, endpoints);
+    }
+}
+
+template <int WG>
 __global__ __launch_bounds__(WG) void k_project(Img im, const float* centres, const int* counts,
                                                 const int* labels, int* endpoints,
                                                 const int* ctrl, const int* plist) {
     const int n = ctrl[kCtrlProjCount];
     for (int i = blockIdx.x; i < n; i += gridDim.x)
         project_one<WG>(im, plist[i] - im.sp, centres, counts, labels, endpoints);
-}
-
-template <int WG>
-__global__ __launch_bounds__(WG) void k_project_batched(const Img* __restrict__ imgs,
-                                                        const int* __restrict__ sp_start,
-                                                        int n_img, const float* centres,
-                                                        const int* counts, const int* labels,
-                                                        int* endpoints, const int* ctrl,
-                                                        const int* plist) {
-    const int n = ctrl[kCtrlProjCount];
-    for (int i = blockIdx.x; i < n; i += gridDim.x) {
-        const int g = plist[i];
-        const int ii = find_image(sp_start, n_img, g);
-        const Img im = imgs[ii];
-        project_one<WG>(im, g - im.sp, centres, counts, labels, endpoints);
-    }
 }
 
 // Small host tables (image descriptors) reach the device as kernel
@@ -891,6 +955,7 @@ __global__ void k_write_bytes(unsigned char* __restrict__ dst, ByteChunk c) {
 constexpr int kSmallWG = 256;
 constexpr int kProjectWG = 1024;
 constexpr int kProjectBlocks = 256;
+constexpr int kFinProjectWG = 256;
 
 size_t dyn_lds(const Tuning& t) { return (size_t)t.lds_pixels * sizeof(float4); }
 
@@ -1157,18 +1222,26 @@ int launch_finalize_batched(const Img* imgs, const int* sp_start, int n_img, int
     return hipGetLastError();
 }
 
+int launch_finalize_project(const Img& im, float* centres, int* endpoints, int* counts,
+                            long long* acc, const int* labels, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize_project<kFinProjectWG>, dim3(im.nx * im.ny), dim3(kFinProjectWG),
+                       0, s, im, centres, endpoints, counts, acc, labels);
+    return hipGetLastError();
+}
+
+int launch_finalize_project_batched(const Img* imgs, const int* sp_start, int n_img,
+                                    int total_sp, float* centres, int* endpoints, int* counts,
+                                    long long* acc, const int* labels, int* ctrl, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize_project_batched<kFinProjectWG>, dim3(total_sp),
+                       dim3(kFinProjectWG), 0, s, imgs, sp_start, n_img, centres, endpoints, counts,
+                       acc, labels, ctrl);
+    return hipGetLastError();
+}
+
 int launch_project(const Img& im, const float* centres, const int* counts, const int* labels,
                    int* endpoints, const int* ctrl, const int* plist, hipStream_t s) {
     hipLaunchKernelGGL(k_project<kProjectWG>, dim3(kProjectBlocks), dim3(kProjectWG), 0, s, im,
                        centres, counts, labels, endpoints, ctrl, plist);
-    return hipGetLastError();
-}
-
-int launch_project_batched(const Img* imgs, const int* sp_start, int n_img, const float* centres,
-                           const int* counts, const int* labels, int* endpoints,
-                           const int* ctrl, const int* plist, hipStream_t s) {
-    hipLaunchKernelGGL(k_project_batched<kProjectWG>, dim3(kProjectBlocks), dim3(kProjectWG), 0, s,
-                       imgs, sp_start, n_img, centres, counts, labels, endpoints, ctrl, plist);
     return hipGetLastError();
 }
 
