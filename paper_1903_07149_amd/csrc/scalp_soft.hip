@@ -445,11 +445,16 @@ __global__ __launch_bounds__(256) void k_soft_bwd_update(SoftImg s, int first,
         float Q[9], G[9];
         float gfl = 0.0f, gfa = 0.0f, gfb = 0.0f, dot = 0.0f;
 #pragma unroll
+        for (int j = 0; j < 9; ++j) Q[j] = q[qb + (long long)j * s.N];
+        // a slot with Q_pj = 0 adds nothing to the softmax dot product, to
+        // dL/df or to dL/dD (Q_pj < 2^-24): its dL/dQ and candidate terms
+        // are not loaded
+#pragma unroll
         for (int j = 0; j < 9; ++j) {
             const int ii = ci + j / 3 - 1, jj = cj + j % 3 - 1;
-            Q[j] = q[qb + (long long)j * s.N];
-            G[j] = first ? gq_in[qb + (long long)j * s.N] : 0.0f;
-            if (ii < 0 || ii >= s.ny || jj < 0 || jj >= s.nx) continue;
+            G[j] = 0.0f;
+            if (ii < 0 || ii >= s.ny || jj < 0 || jj >= s.nx || Q[j] == 0.0f) continue;
+            if (first) G[j] = gq_in[qb + (long long)j * s.N];
             const int k = ii * s.nx + jj;
             const float4 u = cb[2 * k], u4v = cb[2 * k + 1];
             G[j] += (((u.x * f.x + u.y * f.y) + (u.z * f.z + u.w * fx)) + u4v.x * fy) - u4v.y;
