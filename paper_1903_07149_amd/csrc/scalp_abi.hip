@@ -563,13 +563,17 @@ int enq_batched(const scalp_batch_desc_t* d, int n, const scalp_params_t* p, con
         e = launch_finalize_batched(imgs, starts, n, (int)BL.K, centers, endpoints, counts, v.acc,
                                     labels, v.ctrl, v.plist, false, s);
     const Tuning t = tuning_of(p);
+    long long max_block = 0;
+    for (int i = 0; i < n; ++i)
+        max_block = std::max(max_block, block_pixels(d[i].grid.width, d[i].grid.height,
+                                                     d[i].grid.nx, d[i].grid.ny));
     for (int it = 0; e == hipSuccess && it < p->iterations; ++it) {
         e = launch_assign_persistent(imgs, items, n, (int)total_items, v.packed, centers, endpoints,
                                      labels, v.acc, v.ctrl, p->lambda, t, grid, s);
         if (e == hipSuccess)
-            e = p->project ? launch_finalize_project_batched(imgs, starts, n, (int)BL.K, centers,
-                                                             endpoints, counts, v.acc, labels,
-                                                             v.ctrl, s)
+            e = p->project ? launch_finalize_project_batched(imgs, starts, n, (int)BL.K, max_block,
+                                                             centers, endpoints, counts, v.acc,
+                                                             labels, v.ctrl, s)
                            : launch_finalize_batched(imgs, starts, n, (int)BL.K, centers,
                                                      endpoints, counts, v.acc, labels, v.ctrl,
                                                      v.plist, false, s);

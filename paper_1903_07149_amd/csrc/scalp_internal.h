@@ -97,9 +97,12 @@ int launch_finalize(const Img& im, float* centres, int* endpoints, int* counts,
                     long long* acc, const int* labels, int* ctrl, int* plist, bool project,
                     hipStream_t s);
 // finalize + projection in one launch (one workgroup per superpixel)
+// (max_block_px: the most pixels of any superpixel's 3x3 cell block in the batch)
 int launch_finalize_project_batched(const Img* imgs, const int* sp_start, int n_img,
-                                    int total_sp, float* centres, int* endpoints, int* counts,
-                                    long long* acc, const int* labels, int* ctrl, hipStream_t s);
+                                    int total_sp, long long max_block_px, float* centres,
+                                    int* endpoints, int* counts, long long* acc, const int* labels,
+                                    int* ctrl, hipStream_t s);
+long long block_pixels(int W, int H, int nx, int ny);
 int launch_finalize_project(const Img& im, float* centres, int* endpoints, int* counts,
                             long long* acc, const int* labels, hipStream_t s);
 int launch_project(const Img& im, const float* centres, const int* counts, const int* labels,

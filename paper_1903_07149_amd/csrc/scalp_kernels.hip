@@ -955,7 +955,13 @@ __global__ void k_write_bytes(unsigned char* __restrict__ dst, ByteChunk c) {
 constexpr int kSmallWG = 256;
 constexpr int kProjectWG = 1024;
 constexpr int kProjectBlocks = 256;
+// Workgroup of the finalize + projection pass: 256 lanes, or 1024 where a
+// superpixel's 3x3 cell block holds more than kWideProjectPixels pixels (the
+// coarse scales of the multi-scale batch: one projection then scans most of
+// the image, and its workgroup alone bounds the pass).
 constexpr int kFinProjectWG = 256;
+constexpr int kWideProjectWG = 1024;
+constexpr long long kWideProjectPixels = 32768;
 
 size_t dyn_lds(const Tuning& t) { return (size_t)t.lds_pixels * sizeof(float4); }
 
@@ -1222,19 +1228,33 @@ int launch_finalize_batched(const Img* imgs, const int* sp_start, int n_img, int
     return hipGetLastError();
 }
 
+long long block_pixels(int W, int H, int nx, int ny) {
+    return 9LL * ((W + nx - 1) / nx) * ((H + ny - 1) / ny);
+}
+
 int launch_finalize_project(const Img& im, float* centres, int* endpoints, int* counts,
                             long long* acc, const int* labels, hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize_project<kFinProjectWG>, dim3(im.nx * im.ny), dim3(kFinProjectWG),
-                       0, s, im, centres, endpoints, counts, acc, labels);
+    if (block_pixels(im.W, im.H, im.nx, im.ny) > kWideProjectPixels)
+        hipLaunchKernelGGL(k_finalize_project<kWideProjectWG>, dim3(im.nx * im.ny),
+                           dim3(kWideProjectWG), 0, s, im, centres, endpoints, counts, acc, labels);
+    else
+        hipLaunchKernelGGL(k_finalize_project<kFinProjectWG>, dim3(im.nx * im.ny),
+                           dim3(kFinProjectWG), 0, s, im, centres, endpoints, counts, acc, labels);
     return hipGetLastError();
 }
 
 int launch_finalize_project_batched(const Img* imgs, const int* sp_start, int n_img,
-                                    int total_sp, float* centres, int* endpoints, int* counts,
-                                    long long* acc, const int* labels, int* ctrl, hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize_project_batched<kFinProjectWG>, dim3(total_sp),
-                       dim3(kFinProjectWG), 0, s, imgs, sp_start, n_img, centres, endpoints, counts,
-                       acc, labels, ctrl);
+                                    int total_sp, long long max_block_px, float* centres,
+                                    int* endpoints, int* counts, long long* acc, const int* labels,
+                                    int* ctrl, hipStream_t s) {
+    if (max_block_px > kWideProjectPixels)
+        hipLaunchKernelGGL(k_finalize_project_batched<kWideProjectWG>, dim3(total_sp),
+                           dim3(kWideProjectWG), 0, s, imgs, sp_start, n_img, centres, endpoints,
+                           counts, acc, labels, ctrl);
+    else
+        hipLaunchKernelGGL(k_finalize_project_batched<kFinProjectWG>, dim3(total_sp),
+                           dim3(kFinProjectWG), 0, s, imgs, sp_start, n_img, centres, endpoints,
+                           counts, acc, labels, ctrl);
     return hipGetLastError();
 }
 
