@@ -912,8 +912,10 @@ __global__ __launch_bounds__(WG) void k_finalize_project_batched(const Img* __re
     __shared__ float sx, sy;
     __shared__ int scnt, smove, simg;
     const int g = blockIdx.x;
+    // the next persistent assignment starts afresh (block 0 clears all 8
+    // heads: a batch may have fewer than 8 superpixels)
+    if (g == 0 && threadIdx.x < 8) ctrl[kCtrlQueue + 32 * threadIdx.x] = 0;
     if (threadIdx.x == 0) {
-        if (g < 8) ctrl[kCtrlQueue + 32 * g] = 0;   // the next persistent assignment starts afresh
         const int i = find_image(sp_start, n_img, g);
         float xk = 0.0f, yk = 0.0f;
         int cnt = 0;

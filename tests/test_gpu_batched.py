@@ -105,3 +105,19 @@ def test_batched_full_size_workload(orc):
             ref = orc.run(img.lab, img.contour, w.k, iterations=10, mode=orc.MEAN_FIXED)
             assert (l[p0:p1].reshape(H, W) == ref.labels).all(), w.name
             assert (c[s0:s1] == ref.centres).all() and (e[s0:s1] == ref.endpoints).all()
+
+
+@pytest.mark.parametrize("W,H,k", [(481, 321, 250), (129, 77, 1), (1920, 1080, 2000)])
+def test_batched_single_image_equals_single_path(W, H, k):
+    """A batch of one image: every XCD's run of work items is a share of the
+    same image, and the results equal the single-image path's."""
+    from paper_1903_07149_amd.scalp import Scalp, ScalpBatch
+    wl = synth.Workload(f"one_{W}x{H}", W, H, 40, 10.0, 7, k, 5)
+    img = synth.workload_image(wl)
+    say("batch of one", W, H, k)
+    b = ScalpBatch([(W, H, k)], iterations=5)
+    c, e, l, n = (host(t) for t in b.run(dev(img.lab.reshape(-1, 3)), dev(img.contour.reshape(-1))))
+    r = Scalp(W, H, k, iterations=5).run(dev(img.lab), dev(img.contour))
+    assert (l.reshape(H, W) == host(r.labels)).all()
+    assert (c == host(r.centers)).all() and (e == host(r.endpoints)).all()
+    assert (n == host(r.counts)).all()
