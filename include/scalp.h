@@ -145,7 +145,8 @@ int scalp_make_grid(int32_t width, int32_t height, int32_t k, scalp_grid_t* out)
 /* Bytes of device workspace the single-image entry points need for grid g:
  * the packed (l, a, b, w) image (16 B per pixel), 8 B per pixel of window
  * minima, 68 B per superpixel (integer accumulators, projection queue) and
- * 256 B of control words.
+ * 5376 B of control words (projection queue length, partial maxima of the
+ * computed contour prior, the batched assignment's per-XCD queue heads).
  * 0 if g is invalid. */
 size_t scalp_workspace_bytes(const scalp_grid_t* g);
 
