@@ -564,16 +564,25 @@ __global__ __launch_bounds__(WG, 4) void k_soft_bwd_path(SoftImg s, const float4
     const int y0 = cell_lo(ci, H, s.ny), y1 = cell_lo(ci + 1, H, s.ny);
     const float4* __restrict__ img = packed + (long long)b * s.N;
     float4* __restrict__ gimg = gf + (long long)b * s.N;
-    load_candidates(s, ci, cj, theta_prev + 5LL * s.K * b, img, sh);
-    for (int t = tid; t < 9 * 7 * kBwdCopies; t += WG) (&bins[0][0][0])[t] = 0.0;
-    __syncthreads();
+    // the candidates' centres (this pass needs no endpoint texel) are loaded
+    // here and stored after the first pass, which does not use them; the
+    // slots' boxes start empty and take the endpoint in the layout step
+    float cl = 0.0f, ca = 0.0f, cb = 0.0f, cxf = 0.0f, cyf = 0.0f;
+    int ck = -1;
     if (tid < 9) {
-        bl.bx0[tid] = sh.cand[tid].cx;
-        bl.bx1[tid] = sh.cand[tid].cx + 1;
-        bl.by0[tid] = sh.cand[tid].cy;
-        bl.by1[tid] = sh.cand[tid].cy + 1;
+        const int ii = ci + tid / 3 - 1, jj = cj + tid % 3 - 1;
+        if (ii >= 0 && ii < s.ny && jj >= 0 && jj < s.nx) {
+            ck = ii * s.nx + jj;
+            const float* c5 = theta_prev + 5LL * s.K * b + 5LL * ck;
+            cl = c5[0]; ca = c5[1]; cb = c5[2]; cxf = c5[3]; cyf = c5[4];
+        }
+        bl.bx0[tid] = INT_MAX;
+        bl.bx1[tid] = INT_MIN;
+        bl.by0[tid] = INT_MAX;
+        bl.by1[tid] = INT_MIN;
         bl.has[tid] = 0;
     }
+    for (int t = tid; t < 9 * 7 * kBwdCopies; t += WG) (&bins[0][0][0])[t] = 0.0;
     __syncthreads();
     const int cw = x1 - x0, ch = y1 - y0, P = cw * ch;
     const int lane = tid & 63, wave = tid >> 6;
@@ -613,6 +622,15 @@ __global__ __launch_bounds__(WG, 4) void k_soft_bwd_path(SoftImg s, const float4
             }
         }
     }
+    if (tid < 9) {
+        SoftCand c;
+        c.k = ck;
+        c.l = cl; c.a = ca; c.b = cb; c.x = cxf; c.y = cyf;
+        c.cx = ck >= 0 ? round_coord(cxf, W - 1) : 0;
+        c.cy = ck >= 0 ? round_coord(cyf, H - 1) : 0;
+        c.dcc = c.wc = 0.0f;   // not used by this pass
+        sh.cand[tid] = c;
+    }
     __syncthreads();
     // tile layout: slots in the order own cell, edges, corners, while they fit
     if (tid == 0) {
@@ -623,6 +641,11 @@ __global__ __launch_bounds__(WG, 4) void k_soft_bwd_path(SoftImg s, const float4
             const int j = (int)((kOrder >> (4 * t)) & 15ULL);
             bl.soff[j] = -1;
             if (sh.cand[j].k < 0 || !bl.has[j]) continue;
+            // every path of the slot ends at its endpoint
+            bl.bx0[j] = min(bl.bx0[j], sh.cand[j].cx);
+            bl.bx1[j] = max(bl.bx1[j], sh.cand[j].cx + 1);
+            bl.by0[j] = min(bl.by0[j], sh.cand[j].cy);
+            bl.by1[j] = max(bl.by1[j], sh.cand[j].cy + 1);
             const int bw = bl.bx1[j] - bl.bx0[j], bh = bl.by1[j] - bl.by0[j];
             const long long sb = 8LL * bw * bh;
             const int nx0 = min(ux0, bl.bx0[j]), nx1 = max(ux1, bl.bx1[j]);
